@@ -1,0 +1,46 @@
+"""CPU oracle for exact decimal -> binary64/binary32 parsing.
+
+TEST INFRASTRUCTURE ONLY: importable from ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``; never from the product path.
+It shares no code with the HIP implementation.
+
+Parity status: every function here is pinned by ``tests/test_oracle_*.py``
+against the paper's worked examples, brute force over tiny formats, CPython's
+correctly rounded ``float()`` and glibc ``strtof``, and round-trip invariants.
+The status codes and NaN payload are the library contract (the paper leaves
+them open) and are pinned by golden files only.
+"""
+
+from .exact import (
+    BINARY32,
+    BINARY64,
+    FORMATS,
+    STATUS_INVALID,
+    STATUS_OK,
+    STATUS_OUT_OF_RANGE,
+    Format,
+    round_decimal,
+)
+from .grammar import (
+    FLAG_REJECT_PLUS,
+    decompose,
+    parse_buffer,
+    parse_token,
+    split_tokens,
+)
+
+__all__ = [
+    "BINARY32",
+    "BINARY64",
+    "FLAG_REJECT_PLUS",
+    "FORMATS",
+    "Format",
+    "STATUS_INVALID",
+    "STATUS_OK",
+    "STATUS_OUT_OF_RANGE",
+    "decompose",
+    "parse_buffer",
+    "parse_token",
+    "round_decimal",
+    "split_tokens",
+]

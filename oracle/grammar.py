@@ -1,0 +1,95 @@
+"""Token splitting and decimal grammar for the oracle.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/exact.py``).
+
+Section 4 of the paper lists the steps of reading a decimal string: the string
+is explicitly delimited and nothing outside it is read; an optional leading
+sign ('+' may be disallowed by some formats); a significand of digits with an
+optional '.', holding at least one digit; an optional 'e'/'E' exponent with its
+own sign, which must carry digits (the paper lets a parser either fail or
+truncate there; this library fails).  The exact value is then the integer of
+all significand digits times ten to the explicit exponent minus the number of
+fraction digits.
+
+Buffers hold many such strings separated by delimiter bytes: the tokens are
+the maximal non-empty runs of non-delimiter bytes, in buffer order.  That
+convention, the status codes and the NaN payload for rejected tokens are the
+library contract; the paper does not fix them.
+"""
+
+import re
+
+from .exact import BINARY32, BINARY64, FORMATS, STATUS_INVALID, round_decimal
+
+# [+-]? ( D+ ('.' D*)? | '.' D+ ) ( [eE] [+-]? D+ )?   -- whole token
+_TOKEN_RE = re.compile(
+    rb"([+-]?)(?:([0-9]+)(?:\.([0-9]*))?|\.([0-9]+))(?:[eE]([+-]?[0-9]+))?"
+)
+
+FLAG_REJECT_PLUS = 1
+
+
+def decompose(tok: bytes, flags: int = 0):
+    """Return (neg, D, E) with value (-1)^neg * D * 10^E, or None if invalid."""
+    m = _TOKEN_RE.fullmatch(tok)
+    if m is None:
+        return None
+    sign, int_digits, frac_digits, only_frac, exp = m.groups()
+    if sign == b"+" and (flags & FLAG_REJECT_PLUS):
+        return None
+    if only_frac is not None:
+        int_digits, frac_digits = b"", only_frac
+    if frac_digits is None:
+        frac_digits = b""
+    digits = int_digits + frac_digits
+    D = int(digits)
+    E = (int(exp) if exp is not None else 0) - len(frac_digits)
+    return sign == b"-", D, E
+
+
+def parse_token(tok: bytes, fmt=BINARY64, flags: int = 0):
+    """(bits, status) for one token."""
+    if isinstance(fmt, str):
+        fmt = FORMATS[fmt]
+    parts = decompose(tok, flags)
+    if parts is None:
+        return fmt.qnan_bits, STATUS_INVALID
+    neg, D, E = parts
+    return round_decimal(neg, D, E, fmt)
+
+
+def _delim_class(delims: bytes) -> bytes:
+    if len(delims) == 0:
+        raise ValueError("the delimiter set must not be empty")
+    body = b"".join(b"\\x%02x" % c for c in sorted(set(delims)))
+    return b"[^" + body + b"]+"
+
+
+def split_tokens(buf: bytes, delims: bytes = b"\n"):
+    """List of (start, end) byte ranges of the tokens of ``buf``."""
+    pat = re.compile(_delim_class(delims))
+    return [(mt.start(), mt.end()) for mt in pat.finditer(buf)]
+
+
+def parse_buffer(buf: bytes, fmt="f64", delims: bytes = b"\n", flags: int = 0):
+    """Parse every token of ``buf``.  Returns (bits list, status list)."""
+    if isinstance(fmt, str):
+        fmt = FORMATS[fmt]
+    pat = re.compile(_delim_class(delims))
+    bits, status = [], []
+    for mt in pat.finditer(buf):
+        b, s = parse_token(mt.group(0), fmt, flags)
+        bits.append(b)
+        status.append(s)
+    return bits, status
+
+
+__all__ = [
+    "BINARY32",
+    "BINARY64",
+    "FLAG_REJECT_PLUS",
+    "decompose",
+    "parse_buffer",
+    "parse_token",
+    "split_tokens",
+]

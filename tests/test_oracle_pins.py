@@ -1,0 +1,415 @@
+"""Pins for the CPU oracle: every check here compares the oracle with something
+other than itself -- values the paper prints, brute force over tiny formats,
+CPython's correctly rounded float(), glibc strtof, closed forms and
+invariants.  None of these tests touch the GPU path."""
+
+import bisect
+import ctypes
+import math
+import os
+import struct
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import (
+    BINARY32,
+    BINARY64,
+    FLAG_REJECT_PLUS,
+    Format,
+    STATUS_INVALID,
+    STATUS_OK,
+    STATUS_OUT_OF_RANGE,
+    decompose,
+    parse_buffer,
+    parse_token,
+    round_decimal,
+    split_tokens,
+)
+from gen import workloads as W
+
+
+# ---------------------------------------------------------------------------
+# independent helpers (decoding only; no rounding)
+# ---------------------------------------------------------------------------
+
+def decode_value(bits: int, fmt: Format):
+    """Exact value of an encoding as a Fraction, or +-inf as a float."""
+    sign = -1 if bits & fmt.sign_bit else 1
+    field = (bits >> (fmt.p - 1)) & ((1 << fmt.ebits) - 1)
+    frac = bits & ((1 << (fmt.p - 1)) - 1)
+    if field == (1 << fmt.ebits) - 1:
+        assert frac == 0
+        return sign * math.inf
+    if field == 0:
+        m, e = frac, fmt.emin - fmt.p + 1
+    else:
+        m, e = frac | (1 << (fmt.p - 1)), field - fmt.bias - fmt.p + 1
+    return sign * Fraction(m) * (Fraction(2) ** e)
+
+
+def f64_bits(x: float) -> int:
+    return struct.unpack("<Q", struct.pack("<d", x))[0]
+
+
+def f32_bits_from_strtof(s: bytes):
+    libc = ctypes.CDLL("libc.so.6")
+    libc.strtof.restype = ctypes.c_float
+    libc.strtof.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_char_p)]
+    end = ctypes.c_char_p()
+    v = libc.strtof(s, ctypes.byref(end))
+    return struct.unpack("<I", struct.pack("<f", v))[0]
+
+
+def load_tsv(path):
+    rows = []
+    with open(path, encoding="utf-8") as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            rows.append(line.rstrip("\n").split("\t"))
+    return rows
+
+
+# ---------------------------------------------------------------------------
+# values the paper prints
+# ---------------------------------------------------------------------------
+
+def test_paper_worked_examples(golden_dir):
+    rows = load_tsv(os.path.join(golden_dir, "paper_examples.tsv"))
+    assert len(rows) >= 20
+    for tok, fmtname, kind, expected, cite in rows:
+        fmt = BINARY64 if fmtname == "f64" else BINARY32
+        bits, st = parse_token(tok.encode(), fmt)
+        assert st == STATUS_OK, (tok, cite)
+        val = decode_value(bits, fmt)
+        neg, D, E = decompose(tok.encode())
+        exact = Fraction(D) * Fraction(10) ** E
+        if kind == "m_p":
+            m, p = map(int, expected.split())
+            assert val == Fraction(m) * Fraction(2) ** p, (tok, cite)
+        elif kind == "hex":
+            assert val == Fraction(float.fromhex(expected)), (tok, cite)
+        elif kind == "int":
+            assert val == int(expected), (tok, cite)
+        elif kind == "sig":
+            m = int(expected)
+            assert m.bit_length() == fmt.p
+            # the value must be m times a power of two
+            ratio = val / m
+            assert ratio.numerator == 1 or ratio.denominator == 1
+            r = ratio.numerator if ratio.denominator == 1 else ratio.denominator
+            assert r & (r - 1) == 0, (tok, cite)
+        elif kind == "exact":
+            assert val == exact, (tok, cite)
+        elif kind == "inexact":
+            assert val != exact, (tok, cite)
+        else:
+            raise AssertionError(kind)
+
+
+def _exact_decimal_string(num: int, e2: int) -> bytes:
+    """num * 2^e2 written exactly in decimal (e2 < 0): num*5^-e2 e e2."""
+    assert e2 < 0
+    return b"%de%d" % (num * 5 ** (-e2), e2)
+
+
+def test_paper_subnormal_examples():
+    # Section 9.3: (2^53-1) * 2^(-1022-54) becomes 2^51 * 2^(-1022-52)
+    tok = _exact_decimal_string(2 ** 53 - 1, -1022 - 54)
+    bits, st = parse_token(tok, BINARY64)
+    assert st == STATUS_OK
+    assert decode_value(bits, BINARY64) == Fraction(2) ** 51 * Fraction(2) ** (-1074)
+    assert bits == 2 ** 51
+    # Section 9.3: (2^53-1) * 2^(-1022-53) rounds up to the smallest normal
+    tok = _exact_decimal_string(2 ** 53 - 1, -1022 - 53)
+    bits, st = parse_token(tok, BINARY64)
+    assert st == STATUS_OK
+    assert decode_value(bits, BINARY64) == Fraction(2) ** (-1022)
+
+
+def test_paper_768_digit_midpoint():
+    # Section 11: the midpoint 2^-1022 + 2^-1074 + 2^-1075 needs 768
+    # significant digits and rounds to the even neighbour, the larger value.
+    num = 2 ** 53 + 2 + 1  # (2^-1022 + 2^-1074 + 2^-1075) * 2^1075
+    digits = str(num * 5 ** 1075).rstrip("0")
+    assert len(digits) == 768
+    tok = _exact_decimal_string(num, -1075)
+    bits, st = parse_token(tok, BINARY64)
+    assert st == STATUS_OK
+    assert decode_value(bits, BINARY64) == Fraction(2) ** -1022 + Fraction(2) ** -1073
+    assert float.fromhex("0x1.0000000000002p-1022") == struct.unpack(
+        "<d", struct.pack("<Q", bits))[0]
+    # every truncation of those digits is closer to the lower neighbour
+    for keep in (17, 19, 100, 400, 767):
+        t = (digits[:keep] + "e%d" % (len(str(num * 5 ** 1075)) - keep - 1075)).encode()
+        b2, _ = parse_token(t, BINARY64)
+        assert decode_value(b2, BINARY64) == Fraction(2) ** -1022 + Fraction(2) ** -1074
+
+
+def test_exact_numbers_section6():
+    # Section 6: w*10^q can be exact only for q in [-27, 22] (binary64).
+    for q in range(0, 23):
+        bits, _ = parse_token(b"1e%d" % q, BINARY64)
+        assert decode_value(bits, BINARY64) == 10 ** q
+    bits, _ = parse_token(b"1e23", BINARY64)
+    assert decode_value(bits, BINARY64) != 10 ** 23
+    for q in range(1, 28):
+        w = 5 ** q  # w * 10^-q = 2^-q exactly
+        bits, _ = parse_token(b"%de-%d" % (w, q), BINARY64)
+        assert decode_value(bits, BINARY64) == Fraction(1, 2 ** q)
+
+
+def test_exponent_of_ten_formula_section10():
+    # Section 10: the binary exponent of 10^q is q + floor(log2 5^q); the
+    # oracle's result for 10^q must have that leading exponent.
+    for q in range(-300, 300, 7):
+        bits, _ = parse_token(b"1e%d" % q, BINARY64)
+        field = (bits >> 52) & 0x7FF
+        if q >= 0:
+            expect = q + (5 ** q).bit_length() - 1
+        else:
+            p5 = 5 ** (-q)
+            expect = q - (p5.bit_length() - (1 if p5 & (p5 - 1) == 0 else 0))
+        assert field - 1023 == expect
+
+
+# ---------------------------------------------------------------------------
+# brute force over tiny formats
+# ---------------------------------------------------------------------------
+
+MINI_FORMATS = [
+    Format("mini3", 3, -2, 3, 3),
+    Format("mini4", 4, -6, 7, 4),
+    Format("mini5", 5, -14, 15, 5),
+]
+
+
+def _representables(fmt: Format):
+    """Sorted list of (value, significand) for every finite non-negative
+    number of the format, plus infinity as the even virtual value 2^(emax+1)."""
+    out = [(Fraction(0), 0)]
+    q0 = fmt.emin - fmt.p + 1
+    for m in range(1, 1 << (fmt.p - 1)):
+        out.append((Fraction(m) * Fraction(2) ** q0, m))
+    for e in range(fmt.emin, fmt.emax + 1):
+        for m in range(1 << (fmt.p - 1), 1 << fmt.p):
+            out.append((Fraction(m) * Fraction(2) ** (e - fmt.p + 1), m))
+    out.append((Fraction(2) ** (fmt.emax + 1), 0))  # infinity, even
+    out.sort()
+    return out
+
+
+def _brute_nearest(v: Fraction, table, keys):
+    i = bisect.bisect_left(keys, v)
+    if i < len(keys) and keys[i] == v:
+        return keys[i]
+    if i >= len(keys):
+        return keys[-1]
+    lo, hi = table[i - 1], table[i]
+    dl, dh = v - lo[0], hi[0] - v
+    if dl < dh:
+        return lo[0]
+    if dh < dl:
+        return hi[0]
+    return lo[0] if lo[1] % 2 == 0 else hi[0]
+
+
+@pytest.mark.parametrize("fmt", MINI_FORMATS, ids=lambda f: f.name)
+def test_bruteforce_mini_format(fmt):
+    table = _representables(fmt)
+    keys = [t[0] for t in table]
+    inf_value = keys[-1]
+    rng = np.random.default_rng(1234)
+    cases = [(D, E) for D in range(0, 1200) for E in range(-7, 3)]
+    cases += [(int(d), int(e)) for d, e in zip(rng.integers(0, 10 ** 7, 3000),
+                                               rng.integers(-14, 3, 3000))]
+    # exact midpoints of neighbouring representables, written in decimal
+    for (a, _), (b, _) in zip(table[:-1], table[1:]):
+        mid = (a + b) / 2
+        den = mid.denominator
+        k = den.bit_length() - 1  # den is a power of two
+        D = mid.numerator * 5 ** k
+        cases.append((D, -k))
+    for D, E in cases:
+        v = Fraction(D) * Fraction(10) ** E
+        want = _brute_nearest(v, table, keys)
+        for neg in (False, True):
+            bits, st = round_decimal(neg, D, E, fmt)
+            got = decode_value(bits, fmt)
+            if want == inf_value:
+                assert got == (-math.inf if neg else math.inf), (D, E)
+                assert st == STATUS_OUT_OF_RANGE
+            else:
+                assert got == (-want if neg else want), (D, E, fmt.name)
+                assert bool(bits & fmt.sign_bit) == neg
+                if want == 0 and D != 0:
+                    assert st == STATUS_OUT_OF_RANGE
+                else:
+                    assert st == STATUS_OK
+
+
+# ---------------------------------------------------------------------------
+# correctly rounded library parsers on the real formats
+# ---------------------------------------------------------------------------
+
+def _corpus(n_each=4000, seed=77):
+    rng = np.random.default_rng(seed)
+    toks = []
+    toks += W.uniform_shortest(rng, n_each)
+    toks += W.coordinates(rng, n_each)
+    toks += W.random_bits_e17(rng, n_each)
+    toks += W.hard_tokens(rng, n_each)
+    toks += [str(int(v)) for v in rng.integers(0, 2 ** 64, 500, dtype=np.uint64)]
+    toks += ["%.*e" % (int(k), float(x)) for k, x in
+             zip(rng.integers(0, 30, 2000), rng.standard_normal(2000) * 10.0 ** rng.integers(-300, 300, 2000))]
+    return [t.encode() for t in toks]
+
+
+def test_binary64_matches_cpython_float():
+    n = 0
+    for tok in _corpus():
+        bits, st = parse_token(tok, BINARY64)
+        assert st != STATUS_INVALID, tok
+        assert bits == f64_bits(float(tok)), tok
+        n += 1
+    assert n > 18000
+
+
+def test_binary32_matches_glibc_strtof():
+    n = 0
+    for tok in _corpus(n_each=2500, seed=78):
+        bits, st = parse_token(tok, BINARY32)
+        assert st != STATUS_INVALID, tok
+        assert bits == f32_bits_from_strtof(tok), tok
+        n += 1
+    assert n > 10000
+
+
+def test_binary32_double_rounding_traps():
+    # rounding through binary64 first would give a different answer
+    cases = {
+        b"1.0000000596046447753906250001": 0x3F800001,
+        b"3.4028235677973366e38": 0x7F7FFFFF,
+        b"1.4e-45": 0x00000001,
+        b"1.17549435e-38": 0x00800000,
+    }
+    for tok, want in cases.items():
+        bits, st = parse_token(tok, BINARY32)
+        assert bits == want, tok
+        assert bits == f32_bits_from_strtof(tok)
+
+
+# ---------------------------------------------------------------------------
+# invariants
+# ---------------------------------------------------------------------------
+
+def test_roundtrip_binary64():
+    # Section 1: 17 significant digits always parse back to the same double.
+    rng = np.random.default_rng(5)
+    u = rng.integers(0, 2 ** 64, 20000, dtype=np.uint64)
+    u = u[((u >> np.uint64(52)) & np.uint64(0x7FF)) != np.uint64(0x7FF)]
+    for x in u.view(np.float64).tolist():
+        for s in (repr(x), "%.17e" % x):
+            bits, st = parse_token(s.encode(), BINARY64)
+            assert bits == f64_bits(x), s
+
+
+def test_roundtrip_binary32():
+    # Section 2: 9 significant digits always parse back to the same float.
+    rng = np.random.default_rng(6)
+    u = rng.integers(0, 2 ** 32, 20000, dtype=np.uint64).astype(np.uint32)
+    u = u[((u >> np.uint32(23)) & np.uint32(0xFF)) != np.uint32(0xFF)]
+    for b, x in zip(u.tolist(), u.view(np.float32).tolist()):
+        s = "%.8e" % x  # 9 significant digits
+        bits, st = parse_token(s.encode(), BINARY32)
+        assert bits == b, s
+
+
+def test_sign_symmetry_and_monotonicity():
+    rng = np.random.default_rng(7)
+    toks = W.hard_tokens(rng, 3000) + W.uniform_shortest(rng, 1000)
+    vals = []
+    for t in toks:
+        t = t.lstrip("+-")
+        b, _ = parse_token(t.encode(), BINARY64)
+        bn, _ = parse_token(("-" + t).encode(), BINARY64)
+        assert bn == b | BINARY64.sign_bit
+        neg, D, E = decompose(t.encode())
+        vals.append((Fraction(D) * Fraction(10) ** E if abs(E) < 2000 else None, b))
+    vals = [v for v in vals if v[0] is not None]
+    vals.sort(key=lambda t: t[0])
+    prev = None
+    for _, b in vals:
+        x = decode_value(b, BINARY64)
+        if prev is not None:
+            assert x >= prev
+        prev = x
+
+
+def test_scale_invariance():
+    rng = np.random.default_rng(8)
+    for D, E in zip(rng.integers(1, 10 ** 18, 2000).tolist(), rng.integers(-340, 300, 2000).tolist()):
+        a = round_decimal(False, D, E, BINARY64)
+        b = round_decimal(False, D * 10, E - 1, BINARY64)
+        c = round_decimal(False, D * 1000, E - 3, BINARY64)
+        assert a == b == c
+
+
+# ---------------------------------------------------------------------------
+# grammar, status codes and tokenisation (library contract)
+# ---------------------------------------------------------------------------
+
+def test_grammar_golden(golden_dir):
+    rows = load_tsv(os.path.join(golden_dir, "grammar.tsv"))
+    for tok, flags, st, hexbits in rows:
+        bits, status = parse_token(tok.encode(), BINARY64, int(flags))
+        assert status == int(st), tok
+        assert bits == int(hexbits, 16), tok
+
+
+def test_grammar_agrees_with_cpython_on_acceptance():
+    # CPython float() also accepts '_', surrounding blanks and inf/nan; on
+    # tokens without those it must agree with the oracle on acceptance.
+    rng = np.random.default_rng(9)
+    alphabet = list("0123456789.eE+-") + ["x", "_", "1"]
+    for _ in range(20000):
+        n = int(rng.integers(1, 8))
+        tok = "".join(alphabet[int(i)] for i in rng.integers(0, len(alphabet), n))
+        if "_" in tok or "x" in tok:
+            continue
+        try:
+            float(tok)
+            ok_py = True
+        except ValueError:
+            ok_py = False
+        _, st = parse_token(tok.encode(), BINARY64)
+        assert (st != STATUS_INVALID) == ok_py, tok
+
+
+def test_invalid_examples_rejected():
+    for tok in W.INVALID_EXAMPLES:
+        bits, st = parse_token(tok.encode(), BINARY64)
+        assert st == STATUS_INVALID, tok
+        assert bits == 0x7FF8000000000000
+        bits, st = parse_token(tok.encode(), BINARY32)
+        assert bits == 0x7FC00000
+
+
+def test_reject_plus_flag():
+    assert parse_token(b"+1", BINARY64, FLAG_REJECT_PLUS)[1] == STATUS_INVALID
+    assert parse_token(b"1e+1", BINARY64, FLAG_REJECT_PLUS)[1] == STATUS_OK
+    assert parse_token(b"-1", BINARY64, FLAG_REJECT_PLUS)[1] == STATUS_OK
+
+
+def test_split_tokens():
+    assert split_tokens(b"") == []
+    assert split_tokens(b"\n\n\n") == []
+    assert split_tokens(b"1") == [(0, 1)]
+    assert split_tokens(b"1\n") == [(0, 1)]
+    assert split_tokens(b"\n12\n\n3") == [(1, 3), (5, 6)]
+    assert split_tokens(b"1,2 3\t4", b", \t") == [(0, 1), (2, 3), (4, 5), (6, 7)]
+    bits, st = parse_buffer(b"1\n\nx\n2.5", "f64")
+    assert st == [STATUS_OK, STATUS_INVALID, STATUS_OK]
+    assert bits[2] == f64_bits(2.5)
