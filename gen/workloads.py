@@ -83,7 +83,7 @@ def join_tokens(tokens, delim: str = "\n", trailing: bool = True) -> bytes:
     body = delim.join(tokens)
     if trailing and tokens:
         body += delim
-    return body.encode("ascii")
+    return body.encode("utf-8")
 
 
 def config1(seed: int = 1, n: int = 100_000) -> bytes:

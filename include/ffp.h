@@ -1,0 +1,181 @@
+/*
+ * ffp.h -- exact decimal -> IEEE-754 binary64 / binary32 parsing on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library turns a buffer of delimiter-separated ASCII decimal numbers into
+ * the nearest binary64 or binary32 values, ties rounded to even, following
+ * Lemire, "Number Parsing at a Gigabyte per Second" (Software: Practice and
+ * Experience, 2021):
+ *   - strings are explicitly delimited and nothing outside [text, text+nbytes)
+ *     is ever read (Section 4);
+ *   - up to 19 significant digits go into a 64-bit significand w with a
+ *     decimal exponent q (Sections 4 and 11);
+ *   - w * 10^q is converted with one or two 64x64->128-bit products against a
+ *     128-bit power-of-five table (Algorithm 1, Sections 5 to 10);
+ *   - longer numbers try the truncated w and w+1 (Section 11), and whatever
+ *     those cannot decide goes to an exact big-integer fallback on the GPU;
+ *   - the result is the correctly rounded value in every case.
+ *
+ * All entry points use plain C types.  Device pointers come from hipMalloc
+ * (for instance torch tensors on a ROCm device); `stream` is a hipStream_t
+ * (NULL = the default stream).  No entry point throws; every one returns an
+ * ffp_error code.  Calls that take a stream are asynchronous and
+ * stream-ordered unless their name ends in _sync.
+ */
+#ifndef FFP_H
+#define FFP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------------------
+ * Per-token status, one byte per token in the caller's status array.
+ * ------------------------------------------------------------------------- */
+enum ffp_token_status {
+    /* The correctly rounded value.  A zero significand gives a signed zero,
+     * "-0" gives -0.0, subnormal results are FFP_OK. */
+    FFP_OK = 0,
+    /* The token does not match the grammar below.  The value is the canonical
+     * quiet NaN: 0x7FF8000000000000 (binary64) or 0x7FC00000 (binary32). */
+    FFP_INVALID = 1,
+    /* A nonzero decimal whose rounded value is +-infinity (overflow) or +-0
+     * (total underflow).  The value is that infinity or zero. */
+    FFP_OUT_OF_RANGE = 2
+};
+
+/* ---------------------------------------------------------------------------
+ * Error codes returned by the entry points.
+ * ------------------------------------------------------------------------- */
+enum ffp_error {
+    FFP_SUCCESS = 0,
+    FFP_E_ARG = -1,       /* invalid argument (null pointer, bad option, ...) */
+    FFP_E_CAPACITY = -2,  /* more tokens than the caller's capacity (_sync) */
+    FFP_E_HIP = -3,       /* a HIP runtime call failed */
+    FFP_E_NOMEM = -4,     /* device scratch could not be allocated */
+    FFP_E_BUDGET = -5,    /* request does not fit the server's HBM budget */
+    FFP_E_BUSY = -6,      /* server has no free slot (non-blocking submit) */
+    FFP_E_QUEUE = -7,     /* fallback queue overflowed; result incomplete */
+    FFP_E_INTERNAL = -8   /* internal consistency check failed */
+};
+
+/* Reject a leading '+' sign, as JSON does (Section 4). */
+#define FFP_REJECT_PLUS 1u
+
+/* ---------------------------------------------------------------------------
+ * Options.  delim_set is a 256-bit set of delimiter bytes: byte c is a
+ * delimiter when bit (c & 63) of delim_set[c >> 6] is set.  It must be
+ * non-empty and must not contain any byte of the grammar
+ * (0-9 . e E + -).  Passing NULL for the options selects {'\n'} and flags 0.
+ * ------------------------------------------------------------------------- */
+typedef struct ffp_options {
+    uint64_t delim_set[4];
+    uint32_t flags;
+    uint32_t reserved;
+} ffp_options;
+
+typedef struct ffp_ctx ffp_ctx;
+
+/* ---------------------------------------------------------------------------
+ * Tokens and grammar.
+ *
+ * Tokens are the maximal non-empty runs of non-delimiter bytes, in buffer
+ * order; empty runs between delimiters are skipped.  Token i gets values[i]
+ * and status[i].  A token is accepted when the whole run matches
+ *
+ *     [+-]? ( D+ ('.' D*)? | '.' D+ ) ( [eE] [+-]? D+ )?       D = [0-9]
+ *
+ * over ASCII (Section 4 leaves the grammar to the application; this is the
+ * strict from_chars-like choice: no blanks, no inf/nan, no hexadecimal, an
+ * exponent marker must be followed by digits).
+ * ------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `hip_device`.  The context owns the
+ * power-of-five table (10,416 bytes, Appendix B), the tile-scan state, the
+ * fallback queue and timing events.  Returns FFP_E_ARG for a bad option set,
+ * FFP_E_HIP / FFP_E_NOMEM on runtime failures.  *out is NULL on failure. */
+int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out);
+
+/* Destroy a context; waits for its outstanding work.  NULL is a no-op. */
+void ffp_destroy(ffp_ctx* ctx);
+
+/* Human-readable text for an ffp_error code (static storage). */
+const char* ffp_strerror(int err);
+
+/* Grow the context's device scratch so that later calls on buffers of up to
+ * max_nbytes bytes allocate nothing.  Calls on larger buffers grow the scratch
+ * themselves (a hipMalloc outside any kernel).  Returns FFP_E_NOMEM on
+ * failure. */
+int ffp_reserve(ffp_ctx* ctx, uint64_t max_nbytes);
+
+/* ---------------------------------------------------------------------------
+ * Plain parse: one buffer, one stream-ordered launch sequence.
+ *
+ *   d_text    device pointer to nbytes bytes of text (read only; bytes
+ *             outside [d_text, d_text+nbytes) are never read).  nbytes may
+ *             be 0.  nbytes must be below 2^47.
+ *   d_values  device array of `capacity` doubles (or floats) -- written for
+ *             tokens 0 .. min(count, capacity)-1 only.
+ *   d_status  device array of `capacity` bytes (ffp_token_status).
+ *   d_count   device pointer to one uint64_t: receives the true number of
+ *             tokens, which may exceed capacity.
+ *   stream    hipStream_t; the work is queued and the call returns.
+ *
+ * Returns FFP_SUCCESS when the work was queued, FFP_E_ARG for bad arguments
+ * (null pointers with nonzero sizes, nbytes too large), FFP_E_NOMEM if the
+ * scratch could not grow, FFP_E_HIP if a launch failed.  A context serves one
+ * stream at a time: calls on one context must be ordered on one stream (or
+ * synchronised by the caller); the context is not thread-safe.
+ * ------------------------------------------------------------------------- */
+int ffp_parse_f64(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                  double* d_values, uint8_t* d_status, uint64_t capacity,
+                  uint64_t* d_count, void* stream);
+int ffp_parse_f32(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                  float* d_values, uint8_t* d_status, uint64_t capacity,
+                  uint64_t* d_count, void* stream);
+
+/* As above, then waits for the stream.  Returns the token count (>= 0), or a
+ * negative ffp_error: FFP_E_CAPACITY when count > capacity (the first
+ * `capacity` tokens are still written), FFP_E_QUEUE when the fallback queue
+ * overflowed (impossible unless more than 65536 tokens hit the rare
+ * inconclusive-product case of Algorithm 1), FFP_E_INTERNAL on a failed
+ * device-side consistency check. */
+int64_t ffp_parse_f64_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                           double* d_values, uint8_t* d_status, uint64_t capacity,
+                           uint64_t* d_count, void* stream);
+int64_t ffp_parse_f32_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                           float* d_values, uint8_t* d_status, uint64_t capacity,
+                           uint64_t* d_count, void* stream);
+
+/* Device-side error word of the last call on this context, read after the
+ * caller has synchronised its stream: FFP_SUCCESS, FFP_E_QUEUE or
+ * FFP_E_INTERNAL.  Blocks on the context's own copy stream. */
+int ffp_last_device_error(ffp_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Timing of the dominant kernel.  When enabled, each parse call records HIP
+ * events on its stream around the parse kernel (K-parse) only; the totals
+ * accumulate until read.  ffp_timing_read synchronises on the last event and
+ * returns the summed milliseconds and the number of timed launches.
+ * ------------------------------------------------------------------------- */
+int ffp_timing_enable(ffp_ctx* ctx, int enable);
+int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches);
+
+/* ---------------------------------------------------------------------------
+ * Device path counters (Table 5 of the paper reports the same categories on
+ * CPUs).  When enabled, the parse kernels count tokens per path; reading
+ * synchronises.  counters[0..5]: tokens, invalid, early-exit (zero / out of
+ * range before any product), one significand evaluated (up to 19 digits,
+ * decided), w and w+1 evaluated (more than 19 digits, decided), sent to the
+ * exact fallback.
+ * ------------------------------------------------------------------------- */
+int ffp_counters_enable(ffp_ctx* ctx, int enable);
+int ffp_counters_read(ffp_ctx* ctx, uint64_t counters[6]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFP_H */

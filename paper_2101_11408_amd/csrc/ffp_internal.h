@@ -1,0 +1,112 @@
+// Shared host/device definitions of the parsing library (not part of the
+// public C-ABI; see include/ffp.h for that).
+#pragma once
+
+#include <stdint.h>
+
+namespace ffp {
+
+// Parse kernel geometry: 256 threads per workgroup (4 wave64s), each thread
+// loads 16-byte chunks; a tile is kThreads * 16 * K bytes.
+constexpr int kThreads = 256;
+constexpr int kChunk = 16;
+constexpr int kWave = 64;
+
+// Internal per-token status for tokens whose exact value is still being
+// decided by the fallback kernel; never visible after a completed call.
+constexpr uint8_t kPending = 3;
+
+// Decoupled look-back tile state: 2 flag bits + 62-bit token count.
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+
+// Significant decimal digits kept by the exact fallback.  Any midpoint
+// between neighbouring binary64 values needs at most 768 significant digits
+// (Section 11), so 769 digits plus a sticky digit decide every comparison.
+constexpr int kFallbackDigits = 769;
+
+// Limbs (32-bit) of the fallback's big integers: the largest operand is
+// (2m+1) * 5^1093 < 2^2594.
+constexpr int kBigLimbs = 84;
+
+// Maximum buffer size accepted (keeps saturated exponents exact, see the
+// lexer).
+constexpr uint64_t kMaxBytes = 1ull << 47;
+
+// Queue entries reserved for the rare inconclusive-product case of
+// Algorithm 1 on top of the provable bound for long tokens.
+constexpr uint64_t kAbortReserve = 65536;
+
+enum DType : uint32_t { kF64 = 0, kF32 = 1 };
+
+enum DevError : uint32_t { kDevOk = 0, kDevQueue = 1, kDevInternal = 2 };
+
+// Path counters (same categories as the code-path table of the paper's
+// experiments).
+enum Counter : int {
+  kCntTokens = 0,
+  kCntInvalid = 1,
+  kCntEarly = 2,
+  kCntOne = 3,
+  kCntTwo = 4,
+  kCntFallback = 5,
+  kNumCounters = 6
+};
+
+struct JobDesc {
+  const uint8_t* text;
+  uint64_t nbytes;
+  void* values;
+  uint8_t* status;
+  uint64_t capacity;
+  uint64_t* count_out;
+  uint64_t tile_begin;  // index of this job's first tile in the tile space
+  uint32_t dtype;
+  uint32_t job_id;
+};
+
+struct QueueEntry {
+  uint64_t offset;     // byte offset of the token's first byte in its job
+  uint64_t index_job;  // token index | (job id << 48)
+};
+
+struct DeviceState {
+  unsigned int tile_counter;
+  unsigned int error;
+  unsigned long long queue_tail;
+  unsigned long long counters[8];
+};
+
+struct DelimSet {
+  uint64_t bits[4];
+  uint32_t single;     // 1 if the set holds exactly one byte
+  uint32_t byte;       // that byte (or any member, used as padding)
+};
+
+struct ParseParams {
+  JobDesc single;           // plain calls: the one job
+  const JobDesc* jobs;      // batched calls: device job table (else null)
+  uint32_t njobs;
+  uint32_t flags;           // FFP_REJECT_PLUS ...
+  uint64_t total_tiles;     // plain calls
+  const uint64_t* total_tiles_dev;  // batched calls
+  uint64_t* tile_state;
+  DeviceState* st;
+  QueueEntry* queue;
+  uint64_t queue_cap;
+  DelimSet delim;
+  uint32_t count_paths;
+  uint32_t pad;
+};
+
+struct FallbackParams {
+  JobDesc single;
+  const JobDesc* jobs;
+  const QueueEntry* queue;
+  uint64_t queue_cap;
+  DeviceState* st;
+  DelimSet delim;
+};
+
+}  // namespace ffp

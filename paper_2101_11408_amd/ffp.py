@@ -1,0 +1,234 @@
+"""ctypes binding of libffp.so (include/ffp.h).
+
+Argument marshalling only: every step of parsing runs in the HIP kernels of
+the library.  PyTorch provides device memory and streams.  If the library has
+not been built, importing the binding raises -- there is no CPU fallback.
+"""
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libffp.so")
+
+# ffp_token_status
+FFP_OK = 0
+FFP_INVALID = 1
+FFP_OUT_OF_RANGE = 2
+
+# ffp_error
+FFP_SUCCESS = 0
+FFP_E_ARG = -1
+FFP_E_CAPACITY = -2
+FFP_E_HIP = -3
+FFP_E_NOMEM = -4
+FFP_E_BUDGET = -5
+FFP_E_BUSY = -6
+FFP_E_QUEUE = -7
+FFP_E_INTERNAL = -8
+
+FFP_REJECT_PLUS = 1
+
+DTYPE_F64 = 0
+DTYPE_F32 = 1
+
+
+class ffp_options(ctypes.Structure):
+    _fields_ = [("delim_set", ctypes.c_uint64 * 4), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+_c = ctypes
+_P = _c.c_void_p
+_U64 = _c.c_uint64
+_I64 = _c.c_int64
+_INT = _c.c_int
+
+# name -> (restype, argtypes)
+_SIGNATURES = {
+    "ffp_create": (_INT, [_INT, _c.POINTER(ffp_options), _c.POINTER(_P)]),
+    "ffp_destroy": (None, [_P]),
+    "ffp_strerror": (_c.c_char_p, [_INT]),
+    "ffp_reserve": (_INT, [_P, _U64]),
+    "ffp_parse_f64": (_INT, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_parse_f32": (_INT, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_parse_f64_sync": (_I64, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_parse_f32_sync": (_I64, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_last_device_error": (_INT, [_P]),
+    "ffp_timing_enable": (_INT, [_P, _INT]),
+    "ffp_timing_read": (_INT, [_P, _c.POINTER(_c.c_double), _c.POINTER(_U64)]),
+    "ffp_counters_enable": (_INT, [_P, _INT]),
+    "ffp_counters_read": (_INT, [_P, _U64 * 6]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libffp.so (once) and declare the C-ABI prototypes."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            "libffp.so is not built (%s); run `python -m paper_2101_11408_amd.build` "
+            "or __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+class FFPError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        lib = load()
+        msg = lib.ffp_strerror(code).decode()
+        super().__init__("%s%s (%d)" % (what + ": " if what else "", msg, code))
+        self.code = code
+
+
+def check(code: int, what: str = "") -> int:
+    if code < 0:
+        raise FFPError(code, what)
+    return code
+
+
+def make_options(delims: bytes = b"\n", flags: int = 0) -> ffp_options:
+    o = ffp_options()
+    for c in set(delims):
+        o.delim_set[c >> 6] |= 1 << (c & 63)
+    o.flags = flags
+    return o
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def ffp_create(device: int = 0, delims: bytes = b"\n", flags: int = 0):
+    lib = load()
+    out = _P()
+    opts = make_options(delims, flags)
+    check(lib.ffp_create(device, ctypes.byref(opts), ctypes.byref(out)), "ffp_create")
+    return out
+
+
+def ffp_destroy(ctx):
+    load().ffp_destroy(ctx)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def ffp_parse_f64(ctx, text, nbytes, values, status, capacity, count, stream=None):
+    return load().ffp_parse_f64(ctx, text, nbytes, values, status, capacity, count,
+                                _stream_handle(stream))
+
+
+def ffp_parse_f32(ctx, text, nbytes, values, status, capacity, count, stream=None):
+    return load().ffp_parse_f32(ctx, text, nbytes, values, status, capacity, count,
+                                _stream_handle(stream))
+
+
+def ffp_parse_f64_sync(ctx, text, nbytes, values, status, capacity, count, stream=None):
+    return load().ffp_parse_f64_sync(ctx, text, nbytes, values, status, capacity, count,
+                                     _stream_handle(stream))
+
+
+def ffp_parse_f32_sync(ctx, text, nbytes, values, status, capacity, count, stream=None):
+    return load().ffp_parse_f32_sync(ctx, text, nbytes, values, status, capacity, count,
+                                     _stream_handle(stream))
+
+
+# ---------------------------------------------------------------------------
+# torch convenience layer (memory management only)
+# ---------------------------------------------------------------------------
+
+class Context:
+    """Owns an ffp_ctx on one device."""
+
+    def __init__(self, device: int = 0, delims: bytes = b"\n", flags: int = 0):
+        self.device = device
+        self.handle = ffp_create(device, delims, flags)
+
+    def close(self):
+        if self.handle:
+            ffp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, nbytes: int):
+        check(load().ffp_reserve(self.handle, nbytes), "ffp_reserve")
+
+    def timing(self, enable: bool = True):
+        check(load().ffp_timing_enable(self.handle, 1 if enable else 0))
+
+    def timing_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_uint64()
+        check(load().ffp_timing_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def counters(self, enable: bool = True):
+        check(load().ffp_counters_enable(self.handle, 1 if enable else 0))
+
+    def counters_read(self):
+        arr = (ctypes.c_uint64 * 6)()
+        check(load().ffp_counters_read(self.handle, arr))
+        keys = ["tokens", "invalid", "early", "one", "two", "fallback"]
+        return dict(zip(keys, list(arr)))
+
+    def last_device_error(self) -> int:
+        return load().ffp_last_device_error(self.handle)
+
+    def parse_into(self, text, values, status, count, nbytes=None, stream=None,
+                   sync=False):
+        """Parse device uint8 tensor `text` into preallocated device tensors."""
+        import torch
+        assert text.is_cuda and text.dtype == torch.uint8 and text.is_contiguous()
+        f32 = values.dtype == torch.float32
+        if not f32:
+            assert values.dtype == torch.float64
+        nb = text.numel() if nbytes is None else nbytes
+        cap = min(values.numel(), status.numel())
+        args = (self.handle, text.data_ptr(), nb, values.data_ptr(), status.data_ptr(), cap,
+                count.data_ptr(), stream)
+        if sync:
+            fn = ffp_parse_f32_sync if f32 else ffp_parse_f64_sync
+            return fn(*args)
+        fn = ffp_parse_f32 if f32 else ffp_parse_f64
+        return check(fn(*args), "parse")
+
+    def parse(self, text, dtype=None, capacity=None, stream=None):
+        """Parse a device uint8 tensor; returns (values, status) of the exact
+        token count (a second pass with a larger capacity if needed)."""
+        import torch
+        dtype = dtype or torch.float64
+        if capacity is None:
+            capacity = max(1, text.numel() // 2 + 1)
+        dev = text.device
+        values = torch.empty(capacity, dtype=dtype, device=dev)
+        status = torch.empty(capacity, dtype=torch.uint8, device=dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        n = self.parse_into(text, values, status, count, stream=stream, sync=True)
+        if n == FFP_E_CAPACITY:
+            total = int(count.item())
+            return self.parse(text, dtype, capacity=total, stream=stream)
+        check(n, "parse")
+        return values[:n], status[:n]

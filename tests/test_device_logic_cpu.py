@@ -1,0 +1,125 @@
+"""The library's per-token logic (ffp_device.h: lexer, Algorithm 1, the
+w / w+1 test and the exact big-integer fallback), compiled for the host and
+compared bit for bit with the oracle.  No GPU involved; the tile scan and
+the kernels themselves are covered by the GPU tests."""
+
+import os
+import subprocess
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+from gen import workloads as W
+from oracle import parse_buffer
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2101_11408_amd")
+
+
+@pytest.fixture(scope="module")
+def host_check(tmp_path_factory):
+    d = tmp_path_factory.mktemp("host_check")
+    sys.path.insert(0, os.path.join(PKG, "csrc"))
+    try:
+        import gen_table
+    finally:
+        sys.path.pop(0)
+    inc = d / "ffp_table.inc"
+    inc.write_text(gen_table.render())
+    exe = d / "host_check"
+    cmd = ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O2", "-std=c++17",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"), "-I", str(d),
+           os.path.join(ROOT, "tests", "host_logic", "host_check.cpp"), "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return str(exe)
+
+
+def run_host(exe, buf: bytes, fmt: str, flags=0, delims=b"\n"):
+    with tempfile.TemporaryDirectory() as td:
+        src = os.path.join(td, "in.txt")
+        out = os.path.join(td, "out.bin")
+        with open(src, "wb") as f:
+            f.write(buf)
+        res = subprocess.run([exe, src, fmt, str(flags), out, delims.decode()],
+                             check=True, capture_output=True, text=True)
+        ntok, nfb = map(int, res.stdout.split())
+        raw = np.fromfile(out, dtype=np.dtype([("bits", "<u8"), ("st", "u1")]))
+    assert len(raw) == ntok
+    return raw["bits"], raw["st"], nfb
+
+
+def check(exe, buf, fmt, label, **kw):
+    bits, st, nfb = run_host(exe, buf, fmt, **kw)
+    wb, ws = parse_buffer(buf, fmt, **kw)
+    assert len(bits) == len(wb), label
+    wb = np.array(wb, dtype=np.uint64)
+    ws = np.array(ws, dtype=np.uint8)
+    bad = np.flatnonzero((bits != wb) | (st != ws))
+    if bad.size:
+        toks = [t for t in buf.split(b"\n") if t] if kw.get("delims", b"\n") == b"\n" else None
+        i = int(bad[0])
+        tok = toks[i][:100] if toks else "?"
+        raise AssertionError("%s %s: %d mismatches, first #%d %r host=%x/%d oracle=%x/%d" % (
+            label, fmt, bad.size, i, tok, int(bits[i]), int(st[i]), int(wb[i]), int(ws[i])))
+    return nfb
+
+
+def test_uniform_and_mixed(host_check):
+    buf = W.config2(seed=44, n=60_000)
+    for fmt in ("f64", "f32"):
+        check(host_check, buf, fmt, "mixed")
+
+
+def test_hard_cases_exercise_fallback(host_check):
+    buf = W.config3(seed=45, n=20_000)
+    nfb64 = check(host_check, buf, "f64", "hard")
+    nfb32 = check(host_check, buf, "f32", "hard")
+    assert nfb64 > 1000 and nfb32 > 1000
+
+
+def test_grammar_and_specials(host_check):
+    toks = [t for t in W.INVALID_EXAMPLES if t and "\n" not in t and " " not in t]
+    toks += ["1", "-1", "+1", "-0", ".5", "5.", "1e309", "1e-400", "4.9e-324",
+             "2.4703282292062327e-324", "2.4703282292062328e-324", "9007199254740993",
+             "9000000000000000.5", "9000000000000001.5", "1e+100000000000000000000",
+             "0e99999999999", "1" * 40 + "e-40", "0." + "0" * 400 + "1"]
+    buf = W.join_tokens(toks)
+    for fmt in ("f64", "f32"):
+        check(host_check, buf, fmt, "grammar")
+    check(host_check, b"+1\n1\n-1\n", "f64", "reject-plus", flags=1)
+
+
+def test_random_bit_patterns_e17_and_integers(host_check):
+    rng = np.random.default_rng(46)
+    toks = W.random_bits_e17(rng, 30_000)
+    toks += [str(int(v)) for v in rng.integers(0, 2 ** 64, 5000, dtype=np.uint64)]
+    toks += ["%.*e" % (int(k), float(x)) for k, x in
+             zip(rng.integers(0, 25, 5000), rng.standard_normal(5000) * 10.0 ** rng.integers(-320, 300, 5000))]
+    buf = W.join_tokens(toks)
+    for fmt in ("f64", "f32"):
+        check(host_check, buf, fmt, "bits")
+
+
+def test_exact_ties_near_one(host_check):
+    """Exact midpoints written with few digits: the tie windows of Section 6
+    (q in [-4, 23] for binary64, [-17, 10] for binary32)."""
+    rng = np.random.default_rng(47)
+    toks = []
+    for _ in range(20_000):
+        m = int(rng.integers(2 ** 52, 2 ** 53))
+        e = int(rng.integers(-20, 40))
+        num = 2 * m + 1  # midpoint (2m+1) * 2^(e-1)
+        if e - 1 >= 0:
+            toks.append(str(num << (e - 1)))
+        else:
+            toks.append("%de%d" % (num * 5 ** (1 - e), e - 1))
+    for _ in range(10_000):
+        m = int(rng.integers(2 ** 23, 2 ** 24))
+        e = int(rng.integers(-30, 40))
+        num = 2 * m + 1
+        toks.append(str(num << (e - 1)) if e >= 1 else "%de%d" % (num * 5 ** (1 - e), e - 1))
+    buf = W.join_tokens(toks)
+    for fmt in ("f64", "f32"):
+        check(host_check, buf, fmt, "ties")

@@ -1,0 +1,250 @@
+"""Parity of the HIP path with the CPU oracle, bit for bit, on values, status
+codes and the token count.  Every call goes through the C-ABI (libffp.so)."""
+
+import os
+
+import numpy as np
+import pytest
+
+from gen import workloads as W
+from oracle import parse_buffer, parse_token, split_tokens
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ffpmod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_11408_amd import ffp
+    ffp.load()
+    return ffp
+
+
+@pytest.fixture(scope="module")
+def ctx(ffpmod):
+    c = ffpmod.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, buf: bytes, fmt: str, capacity=None):
+    dev = torch.device("cuda", 0)
+    text = torch.frombuffer(bytearray(buf), dtype=torch.uint8).to(dev) if buf else \
+        torch.empty(0, dtype=torch.uint8, device=dev)
+    dt = torch.float64 if fmt == "f64" else torch.float32
+    if capacity is None:
+        capacity = len(buf) // 2 + 1
+    values = torch.empty(max(capacity, 1), dtype=dt, device=dev)
+    status = torch.full((max(capacity, 1),), 255, dtype=torch.uint8, device=dev)
+    count = torch.full((1,), -1, dtype=torch.int64, device=dev)
+    rc = ctx.parse_into(text, values, status, count, sync=True) if len(buf) else \
+        ctx.parse_into(text, values, status, count, nbytes=0, sync=True)
+    n = int(count.item())
+    ib = torch.int64 if fmt == "f64" else torch.int32
+    bits = values.view(ib).cpu().numpy()
+    if fmt == "f64":
+        bits = bits.view(np.uint64)
+    else:
+        bits = bits.view(np.uint32)
+    return rc, n, bits, status.cpu().numpy()
+
+
+def compare_full(ctx, buf: bytes, fmt: str, label: str):
+    _log("case", label, fmt, len(buf), "bytes")
+    rc, n, bits, status = run_gpu(ctx, buf, fmt)
+    want_bits, want_st = parse_buffer(buf, fmt)
+    assert rc == len(want_bits), (label, rc)
+    assert n == len(want_bits)
+    dt = np.uint64 if fmt == "f64" else np.uint32
+    wb = np.array(want_bits, dtype=dt)
+    ws = np.array(want_st, dtype=np.uint8)
+    bad = np.flatnonzero((bits[:n] != wb) | (status[:n] != ws))
+    if bad.size:
+        toks = split_tokens(buf)
+        msgs = []
+        for i in bad[:10].tolist():
+            s, e = toks[i]
+            msgs.append("%d %r gpu=%x/%d oracle=%x/%d" % (i, buf[s:e][:80], int(bits[i]),
+                                                           int(status[i]), int(wb[i]), int(ws[i])))
+        raise AssertionError("%s %s: %d mismatches\n%s" % (label, fmt, bad.size, "\n".join(msgs)))
+    return n
+
+
+def compare_sampled(ctx, buf: bytes, fmt: str, label: str, nsample: int, seed: int):
+    _log("case", label, fmt, len(buf), "bytes (sampled)")
+    rc, n, bits, status = run_gpu(ctx, buf, fmt)
+    toks = split_tokens(buf)
+    assert rc == len(toks) and n == len(toks), (rc, n, len(toks))
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([rng.integers(0, n, nsample), [0, n - 1]]))
+    for i in idx.tolist():
+        s, e = toks[i]
+        b, st = parse_token(buf[s:e], fmt)
+        assert int(bits[i]) == b and int(status[i]) == st, (label, i, buf[s:e][:80])
+    # every status is a public code: nothing left pending
+    assert status[:n].max() <= 2
+    return n
+
+
+# ---------------------------------------------------------------------------
+# configs at sizes the oracle finishes in seconds
+# ---------------------------------------------------------------------------
+
+def test_config1_full(ctx):
+    buf = W.config1()
+    assert compare_full(ctx, buf, "f64", "config1") == 100_000
+    assert compare_full(ctx, buf, "f32", "config1") == 100_000
+
+
+def test_config2_mix_300k(ctx):
+    buf = W.config2(seed=22, n=300_000)
+    assert compare_full(ctx, buf, "f64", "config2-300k") == 300_000
+    compare_full(ctx, buf, "f32", "config2-300k")
+
+
+def test_config3_hard_40k(ctx):
+    buf = W.config3(seed=33, n=40_000)
+    compare_full(ctx, buf, "f64", "config3-40k")
+    compare_full(ctx, buf, "f32", "config3-40k")
+
+
+def test_ragged_random_layout(ctx):
+    """Tokens of random lengths separated by runs of 1-3 delimiters, so that
+    tokens start, end and straddle at every offset of the tiles."""
+    rng = np.random.default_rng(11)
+    toks = W.mixed_tokens(rng, 60_000) + W.hard_tokens(rng, 3000)
+    rng.shuffle(toks)
+    seps = rng.integers(1, 4, size=len(toks))
+    buf = b"".join(t.encode() + b"\n" * int(k) for t, k in zip(toks, seps))
+    for cut in (0, 1, 7):  # also without trailing delimiters
+        b = buf[: len(buf) - cut] if cut else buf
+        compare_full(ctx, b.rstrip(b"\n") if cut == 7 else b, "f64", "ragged-%d" % cut)
+
+
+@pytest.mark.parametrize("tile_k", [1, 2, 4])
+def test_tile_sizes(ffpmod, tile_k):
+    os.environ["FFP_TILE_K"] = str(tile_k)
+    try:
+        c = ffpmod.Context(0)
+    finally:
+        del os.environ["FFP_TILE_K"]
+    try:
+        rng = np.random.default_rng(100 + tile_k)
+        toks = W.mixed_tokens(rng, 20_000) + W.hard_tokens(rng, 500)
+        rng.shuffle(toks)
+        buf = W.join_tokens(toks)
+        compare_full(c, buf, "f64", "tile-k%d" % tile_k)
+        compare_full(c, buf, "f32", "tile-k%d" % tile_k)
+    finally:
+        c.close()
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_empty_and_tiny_buffers(ctx):
+    for buf in [b"", b"\n", b"\n\n\n", b"1", b"7\n", b"\n5", b"-", b".", b"0"]:
+        for fmt in ("f64", "f32"):
+            rc, n, bits, status = run_gpu(ctx, buf, fmt, capacity=4)
+            want_bits, want_st = parse_buffer(buf, fmt)
+            assert n == len(want_bits) and rc == n, buf
+            assert list(map(int, bits[:n])) == want_bits, buf
+            assert list(map(int, status[:n])) == want_st, buf
+
+
+def test_grammar_edge_tokens(ctx):
+    toks = W.INVALID_EXAMPLES[1:] + [
+        "1", "-1", "+1", "-0", "0", ".5", "5.", "1.e1", "1e+1", "1E-1", "1e0001",
+        "0e999999999999", "-0.0e-999", "1e309", "1e-400", "4.9e-324",
+        "2.4703282292062327e-324", "2.4703282292062328e-324", "18446744073709551615",
+        "18446744073709551616", "9007199254740993", "9000000000000000.5",
+        "1e+100000000000000000000", "1e-100000000000000000000",
+        "00000000000000000000000000000000000000001", "0." + "0" * 500 + "1e500",
+        "1" * 40 + "e-40", "9" * 19, "9" * 20, "1" + "0" * 19, "1" + "0" * 30 + "1",
+    ]
+    toks = [t.replace(" ", "").replace("\n", "") or "x" for t in toks if "\n" not in t]
+    buf = W.join_tokens(toks)
+    compare_full(ctx, buf, "f64", "grammar")
+    compare_full(ctx, buf, "f32", "grammar")
+
+
+def test_capacity_smaller_than_count(ctx, ffpmod):
+    buf = W.config1(seed=5, n=5000)
+    rc, n, bits, status = run_gpu(ctx, buf, "f64", capacity=1234)
+    assert rc == ffpmod.FFP_E_CAPACITY
+    assert n == 5000
+    wb, ws = parse_buffer(buf, "f64")
+    assert list(map(int, bits[:1234])) == wb[:1234]
+    assert list(map(int, status[:1234])) == ws[:1234]
+
+
+def test_many_tiny_tokens(ctx):
+    # the densest layout: one digit per token, half the bytes are delimiters
+    buf = b"7\n" * 300_000 + b"8"
+    compare_full(ctx, buf, "f64", "dense")
+
+
+def test_long_tokens(ctx):
+    rng = np.random.default_rng(12)
+    long_digits = "".join(map(str, rng.integers(0, 10, 100_000).tolist()))
+    toks = ["1" + long_digits, "0." + long_digits, long_digits[:5000] + "e-5200",
+            "0" * 70_000 + "3.25", "1" + "0" * 50_000 + "e-50000"]
+    buf = W.join_tokens(toks)
+    compare_full(ctx, buf, "f64", "long")
+    compare_full(ctx, buf, "f32", "long")
+
+
+def test_delimiter_set_and_flags(ffpmod):
+    c = ffpmod.Context(0, delims=b",; \t\r\n", flags=ffpmod.FFP_REJECT_PLUS)
+    try:
+        rng = np.random.default_rng(13)
+        toks = W.mixed_tokens(rng, 20_000)
+        seps = [b",", b";", b" ", b"\t", b"\r\n", b", "]
+        parts = []
+        for i, t in enumerate(toks):
+            parts.append(("+" + t if i % 97 == 0 else t).encode())
+            parts.append(seps[int(rng.integers(0, len(seps)))])
+        buf = b"".join(parts)
+        rc, n, bits, status = run_gpu(c, buf, "f64")
+        wb, ws = parse_buffer(buf, "f64", delims=b",; \t\r\n", flags=1)
+        assert rc == n == len(wb)
+        assert np.array_equal(bits[:n], np.array(wb, dtype=np.uint64))
+        assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8))
+        assert (status[:n] == 1).sum() >= 20000 // 97
+    finally:
+        c.close()
+
+
+def test_path_counters(ctx, ffpmod):
+    buf = W.config3(seed=34, n=5000)
+    ctx.counters(True)
+    ctx.counters_read()
+    run_gpu(ctx, buf, "f64")
+    cnt = ctx.counters_read()
+    ctx.counters(False)
+    assert cnt["tokens"] == 5000
+    assert cnt["invalid"] + cnt["early"] + cnt["one"] + cnt["two"] + cnt["fallback"] == 5000
+    assert cnt["fallback"] > 0
+
+
+# ---------------------------------------------------------------------------
+# full sizes, sampled against the oracle
+# ---------------------------------------------------------------------------
+
+def test_config2_full_size_sampled(ctx):
+    buf = W.config2()
+    assert compare_sampled(ctx, buf, "f64", "config2-full", 100_000, 21) == 10_000_000
+
+
+def test_config3_full_size_sampled(ctx):
+    buf = W.config3()
+    compare_sampled(ctx, buf, "f64", "config3-full", 20_000, 31)
+    compare_sampled(ctx, buf, "f32", "config3-full", 20_000, 32)
