@@ -29,7 +29,13 @@ library contract (the paper leaves them open); they are pinned by golden
 files, not by the paper.
 """
 
+import sys
 from dataclasses import dataclass
+
+# Tokens may carry tens of thousands of digits; CPython limits int <-> str
+# conversions to 4300 digits by default.
+if hasattr(sys, "set_int_max_str_digits"):
+    sys.set_int_max_str_digits(0)
 
 STATUS_OK = 0
 STATUS_INVALID = 1
