@@ -23,12 +23,12 @@ struct ffp_ctx {
   DelimSet delim{};
   uint32_t flags = 0;
   int num_cus = 0;
-  int tile_k = 4;
+  int tile_k = 2;
   int blocks_per_cu = 1;
   int fb_grid = 0;
 
-  uint64_t* d_tile_state = nullptr;
-  uint64_t tile_state_cap = 0;
+  uint64_t* d_block_sum = nullptr;  // per-block counts, then their prefix
+  uint64_t block_cap = 0;
   QueueEntry* d_queue = nullptr;
   uint64_t queue_cap = 0;
   DeviceState* d_state = nullptr;
@@ -63,22 +63,21 @@ bool is_grammar_byte(int c) {
 // Grow the scratch for buffers of up to nbytes.  Old buffers may still be in
 // use by queued work, so the device is drained before anything is freed.
 int grow(ffp_ctx* ctx, uint64_t nbytes) {
-  const uint64_t tb = (uint64_t)ffp::parse_tile_bytes(ctx->tile_k);
-  const uint64_t tiles = (nbytes + 15 + tb - 1) / tb + 1;
-  const uint64_t q = (nbytes + 1) / 21 + ffp::kAbortReserve;
-  if ((tiles > ctx->tile_state_cap || q > ctx->queue_cap) && hipDeviceSynchronize() != hipSuccess)
-    return FFP_E_HIP;
-  if (tiles > ctx->tile_state_cap) {
-    if (ctx->d_tile_state) (void)hipFree(ctx->d_tile_state);
-    ctx->d_tile_state = nullptr;
-    ctx->tile_state_cap = 0;
-    if (hipMalloc(&ctx->d_tile_state, tiles * sizeof(uint64_t)) != hipSuccess) return FFP_E_NOMEM;
-    ctx->tile_state_cap = tiles;
-  }
+  const uint64_t blocks = (nbytes + 15 + ffp::kBlockBytes - 1) / ffp::kBlockBytes + 1;
   // A token that reaches the fallback through the w / w+1 test has more than
   // 19 significant digits, hence at least 20 bytes plus a delimiter (except
   // the last token): (nbytes + 1) / 21 bounds their number.  The reserve
   // covers the inconclusive-product case of Algorithm 1.
+  const uint64_t q = (nbytes + 1) / 21 + ffp::kAbortReserve;
+  if ((blocks > ctx->block_cap || q > ctx->queue_cap) && hipDeviceSynchronize() != hipSuccess)
+    return FFP_E_HIP;
+  if (blocks > ctx->block_cap) {
+    if (ctx->d_block_sum) (void)hipFree(ctx->d_block_sum);
+    ctx->d_block_sum = nullptr;
+    ctx->block_cap = 0;
+    if (hipMalloc(&ctx->d_block_sum, blocks * sizeof(uint64_t)) != hipSuccess) return FFP_E_NOMEM;
+    ctx->block_cap = blocks;
+  }
   if (q > ctx->queue_cap) {
     if (ctx->d_queue) (void)hipFree(ctx->d_queue);
     ctx->d_queue = nullptr;
@@ -86,6 +85,63 @@ int grow(ffp_ctx* ctx, uint64_t nbytes) {
     if (hipMalloc(&ctx->d_queue, q * sizeof(QueueEntry)) != hipSuccess) return FFP_E_NOMEM;
     ctx->queue_cap = q;
   }
+  return FFP_SUCCESS;
+}
+
+int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, uint64_t nblocks, hipStream_t s) {
+  ffp::ScanParams sp{};
+  sp.js = js;
+  sp.block_sum = ctx->d_block_sum;
+  sp.st = ctx->d_state;
+  if (nblocks > 0) {
+    ffp::CountParams cp{};
+    cp.js = js;
+    cp.block_sum = ctx->d_block_sum;
+    cp.delim = ctx->delim;
+    uint64_t grid = (uint64_t)ctx->num_cus * 8;
+    if (grid > nblocks) grid = nblocks;
+    if (ffp::launch_count(ctx->delim.single != 0, cp, (int)grid, s) != hipSuccess) return FFP_E_HIP;
+  }
+  if (ffp::launch_scan(sp, s) != hipSuccess) return FFP_E_HIP;
+  if (nblocks == 0) return FFP_SUCCESS;
+
+  ffp::ParseParams P{};
+  P.js = js;
+  P.block_prefix = ctx->d_block_sum;
+  P.st = ctx->d_state;
+  P.queue = ctx->d_queue;
+  P.queue_cap = ctx->queue_cap;
+  P.delim = ctx->delim;
+  P.flags = ctx->flags;
+  P.count_paths = ctx->counters ? 1u : 0u;
+  uint64_t grid = (uint64_t)ctx->num_cus * (uint64_t)ctx->blocks_per_cu;
+  if (grid > nblocks) grid = nblocks;
+
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (ctx->timing) {
+    if (!ctx->ev_free.empty()) {
+      ev = ctx->ev_free.back();
+      ctx->ev_free.pop_back();
+    } else {
+      if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess)
+        return FFP_E_HIP;
+    }
+    if (hipEventRecord(ev.first, s) != hipSuccess) return FFP_E_HIP;
+  }
+  if (ffp::launch_parse(ctx->tile_k, ctx->delim.single != 0, P, (int)grid, s) != hipSuccess)
+    return FFP_E_HIP;
+  if (ctx->timing) {
+    if (hipEventRecord(ev.second, s) != hipSuccess) return FFP_E_HIP;
+    ctx->ev_used.push_back(ev);
+  }
+
+  ffp::FallbackParams F{};
+  F.js = js;
+  F.queue = ctx->d_queue;
+  F.queue_cap = ctx->queue_cap;
+  F.st = ctx->d_state;
+  F.delim = ctx->delim;
+  if (ffp::launch_fallback(F, ctx->fb_grid, s) != hipSuccess) return FFP_E_HIP;
   return FFP_SUCCESS;
 }
 
@@ -99,15 +155,6 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   DeviceGuard g(ctx->device);
   int rc = grow(ctx, nbytes);
   if (rc != FFP_SUCCESS) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  const uint64_t tb = (uint64_t)ffp::parse_tile_bytes(ctx->tile_k);
-  // tiles start at the 16-byte boundary at or below d_text
-  const uint64_t vbytes = nbytes ? nbytes + ((uintptr_t)d_text & 15u) : 0;
-  const uint64_t ntiles = (vbytes + tb - 1) / tb;
-
-  if (ffp::launch_init(ctx->d_tile_state, ntiles, ctx->d_state, d_count, s) != hipSuccess)
-    return FFP_E_HIP;
-  if (ntiles == 0) return FFP_SUCCESS;
 
   JobDesc job{};
   job.text = d_text;
@@ -116,54 +163,20 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   job.status = d_status;
   job.capacity = capacity;
   job.count_out = d_count;
-  job.tile_begin = 0;
+  job.block_begin = 0;
   job.dtype = dtype;
   job.job_id = 0;
+  // blocks start at the 16-byte boundary at or below d_text
+  const uint64_t vbytes = nbytes ? nbytes + ((uintptr_t)d_text & 15u) : 0;
+  const uint64_t nblocks = (vbytes + ffp::kBlockBytes - 1) / ffp::kBlockBytes;
 
-  ffp::ParseParams P{};
-  P.single = job;
-  P.jobs = nullptr;
-  P.njobs = 1;
-  P.flags = ctx->flags;
-  P.total_tiles = ntiles;
-  P.total_tiles_dev = nullptr;
-  P.tile_state = ctx->d_tile_state;
-  P.st = ctx->d_state;
-  P.queue = ctx->d_queue;
-  P.queue_cap = ctx->queue_cap;
-  P.delim = ctx->delim;
-  P.count_paths = ctx->counters ? 1u : 0u;
-
-  uint64_t grid = (uint64_t)ctx->num_cus * (uint64_t)ctx->blocks_per_cu;
-  if (grid > ntiles) grid = ntiles;
-  if (grid < 1) grid = 1;
-
-  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-  if (ctx->timing) {
-    if (!ctx->ev_free.empty()) {
-      ev = ctx->ev_free.back();
-      ctx->ev_free.pop_back();
-    } else {
-      if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess)
-        return FFP_E_HIP;
-    }
-    if (hipEventRecord(ev.first, s) != hipSuccess) return FFP_E_HIP;
-  }
-  if (ffp::launch_parse(ctx->tile_k, P, (int)grid, s) != hipSuccess) return FFP_E_HIP;
-  if (ctx->timing) {
-    if (hipEventRecord(ev.second, s) != hipSuccess) return FFP_E_HIP;
-    ctx->ev_used.push_back(ev);
-  }
-
-  ffp::FallbackParams F{};
-  F.single = job;
-  F.jobs = nullptr;
-  F.queue = ctx->d_queue;
-  F.queue_cap = ctx->queue_cap;
-  F.st = ctx->d_state;
-  F.delim = ctx->delim;
-  if (ffp::launch_fallback(F, ctx->fb_grid, s) != hipSuccess) return FFP_E_HIP;
-  return FFP_SUCCESS;
+  ffp::JobSet js{};
+  js.single = job;
+  js.jobs = nullptr;
+  js.njobs = 1;
+  js.total_blocks = nblocks;
+  js.total_blocks_dev = nullptr;
+  return launch_jobs(ctx, js, nblocks, (hipStream_t)stream);
 }
 
 int64_t finish_sync(ffp_ctx* ctx, int rc, uint64_t capacity, uint64_t* d_count, void* stream) {
@@ -242,10 +255,10 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
     return FFP_E_HIP;
   }
   ctx->num_cus = prop.multiProcessorCount;
-  if (ffp::parse_occupancy(ctx->tile_k, &ctx->blocks_per_cu) != hipSuccess ||
+  if (ffp::parse_occupancy(ctx->tile_k, ctx->delim.single != 0, &ctx->blocks_per_cu) != hipSuccess ||
       ctx->blocks_per_cu < 1)
     ctx->blocks_per_cu = 1;
-  ctx->fb_grid = ctx->num_cus * 4;
+  ctx->fb_grid = ctx->num_cus * 2;
   if (hipMalloc(&ctx->d_state, sizeof(DeviceState)) != hipSuccess) {
     delete ctx;
     return FFP_E_NOMEM;
@@ -272,7 +285,7 @@ void ffp_destroy(ffp_ctx* ctx) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
     }
-    if (ctx->d_tile_state) (void)hipFree(ctx->d_tile_state);
+    if (ctx->d_block_sum) (void)hipFree(ctx->d_block_sum);
     if (ctx->d_queue) (void)hipFree(ctx->d_queue);
     if (ctx->d_state) (void)hipFree(ctx->d_state);
   }

@@ -28,6 +28,7 @@ struct F64 {
   static constexpr int kTieLo = -4;        // ties only for q in [-4, 23]
   static constexpr int kTieHi = 23;
   static constexpr int kSubExp = -1074;    // exponent of the subnormal quantum
+  static constexpr uint64_t kSecondMask = 0x1FFull;  // 64 - 55 low bits
   static constexpr uint64_t kInf = 0x7FF0000000000000ull;
   static constexpr uint64_t kQNaN = 0x7FF8000000000000ull;
   static constexpr uint64_t kSign = 1ull << 63;
@@ -43,6 +44,7 @@ struct F32 {
   static constexpr int kTieLo = -17;       // ties only for q in [-17, 10]
   static constexpr int kTieHi = 10;
   static constexpr int kSubExp = -149;
+  static constexpr uint64_t kSecondMask = (1ull << 38) - 1;  // 64 - 26 low bits
   static constexpr uint32_t kInf = 0x7F800000u;
   static constexpr uint32_t kQNaN = 0x7FC00000u;
   static constexpr uint32_t kSign = 1u << 31;
@@ -79,10 +81,11 @@ constexpr uint32_t kStRange = 2;
 // `st` to kStRange for results that overflowed to infinity or underflowed to
 // zero.  The sign is applied by the caller.
 //
-// Both 64-bit products are always computed: the paper stops after the first
-// when its low 9 (binary64) or 38 (binary32) bits are not all ones; doing the
-// second unconditionally keeps every lane of a wavefront on one path and
-// only makes the product closer to exact.
+// The second 64-bit product is computed only when the low 9 (binary64) or
+// 38 (binary32) bits of the first product's high word are all ones, the
+// paper's stopping rule (Sections 7 to 9); otherwise the bits that decide
+// the result are already exact.  On the GPU a wavefront executes the second
+// product only when one of its lanes needs it.
 //
 // Subnormal branch: p is the exponent of the leading bit of the 54/25-bit m,
 // so the result is subnormal when p < -1022 (-126) and m must lose
@@ -108,11 +111,14 @@ FFP_HD typename F::bits_t alg1(uint64_t w, int q, uint64_t thi,
   }
   const int l = __builtin_clzll(w);
   w <<= l;
-  uint64_t zh, zl, ph, pl;
+  uint64_t zh, zl;
   mul_64x64(w, thi, zh, zl);
-  mul_64x64(w, tlo, ph, pl);
-  zl += ph;
-  zh += (zl < ph);
+  if ((zh & F::kSecondMask) == F::kSecondMask) {
+    uint64_t ph, pl;
+    mul_64x64(w, tlo, ph, pl);
+    zl += ph;
+    zh += (zl < ph);
+  }
   abort = (zl == ~0ull) && (q < -27 || q > 55);
   const int u = (int)(zh >> 63);
   uint64_t m = zh >> (u + F::kShift);

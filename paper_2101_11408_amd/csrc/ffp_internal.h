@@ -16,10 +16,12 @@ constexpr int kWave = 64;
 // decided by the fallback kernel; never visible after a completed call.
 constexpr uint8_t kPending = 3;
 
-// Decoupled look-back tile state: 2 flag bits + 62-bit token count.
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagInc = 2ull << 62;
-constexpr uint64_t kValueMask = (1ull << 62) - 1;
+// The text of a job is cut into blocks of kBlockBytes (counted from the
+// 16-byte boundary at or below its first byte).  The count kernel gives the
+// number of tokens starting in each block, a scan turns those into the index
+// of each block's first token, and the parse kernel walks a block in tiles of
+// kThreads * kChunk * K bytes.
+constexpr uint64_t kBlockBytes = 64 * 1024;
 
 // Significant decimal digits kept by the exact fallback.  Any midpoint
 // between neighbouring binary64 values needs at most 768 significant digits
@@ -61,7 +63,7 @@ struct JobDesc {
   uint8_t* status;
   uint64_t capacity;
   uint64_t* count_out;
-  uint64_t tile_begin;  // index of this job's first tile in the tile space
+  uint64_t block_begin;  // index of this job's first block in the block space
   uint32_t dtype;
   uint32_t job_id;
 };
@@ -72,7 +74,6 @@ struct QueueEntry {
 };
 
 struct DeviceState {
-  unsigned int tile_counter;
   unsigned int error;
   unsigned long long queue_tail;
   unsigned long long counters[8];
@@ -84,25 +85,42 @@ struct DelimSet {
   uint32_t byte;       // that byte (or any member, used as padding)
 };
 
-struct ParseParams {
-  JobDesc single;           // plain calls: the one job
-  const JobDesc* jobs;      // batched calls: device job table (else null)
+// Jobs: either one job passed by value (plain calls) or a device table
+// sorted by block_begin (batched calls).
+struct JobSet {
+  JobDesc single;
+  const JobDesc* jobs;      // null for plain calls
   uint32_t njobs;
-  uint32_t flags;           // FFP_REJECT_PLUS ...
-  uint64_t total_tiles;     // plain calls
-  const uint64_t* total_tiles_dev;  // batched calls
-  uint64_t* tile_state;
+  uint32_t pad;
+  uint64_t total_blocks;             // plain calls
+  const uint64_t* total_blocks_dev;  // batched calls
+};
+
+struct CountParams {
+  JobSet js;
+  uint64_t* block_sum;  // per block: tokens starting in it
+  DelimSet delim;
+};
+
+struct ScanParams {
+  JobSet js;
+  uint64_t* block_sum;  // in: counts; out: exclusive prefix over all blocks
+  DeviceState* st;
+};
+
+struct ParseParams {
+  JobSet js;
+  const uint64_t* block_prefix;
   DeviceState* st;
   QueueEntry* queue;
   uint64_t queue_cap;
   DelimSet delim;
+  uint32_t flags;           // FFP_REJECT_PLUS ...
   uint32_t count_paths;
-  uint32_t pad;
 };
 
 struct FallbackParams {
-  JobDesc single;
-  const JobDesc* jobs;
+  JobSet js;
   const QueueEntry* queue;
   uint64_t queue_cap;
   DeviceState* st;

@@ -9,11 +9,12 @@ namespace ffp {
 
 // Bytes per parse tile for tile multiplier k (1, 2 or 4).
 int parse_tile_bytes(int k);
-hipError_t parse_occupancy(int k, int* blocks_per_cu);
+// Resident workgroups per CU of the parse kernel.
+hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu);
 
-hipError_t launch_init(uint64_t* tile_state, uint64_t ntiles, DeviceState* st,
-                       uint64_t* count_out, hipStream_t s);
-hipError_t launch_parse(int k, const ParseParams& P, int grid, hipStream_t s);
+hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipStream_t s);
+hipError_t launch_scan(const ScanParams& P, hipStream_t s);
+hipError_t launch_parse(int k, bool single_delim, const ParseParams& P, int grid, hipStream_t s);
 hipError_t launch_fallback(const FallbackParams& P, int grid, hipStream_t s);
 
 }  // namespace ffp

@@ -1,16 +1,20 @@
 // HIP kernels of the parser (gfx950, wave64).
 //
-//   k_init      clears the per-call scan state and the token count.
-//   k_parse     single pass over the text: 16-byte coalesced loads into an
-//               LDS tile, delimiter classification, a block scan of token
-//               starts, a decoupled look-back across tiles for the global
-//               token index, then one lane per token: lexing (Section 4),
-//               Algorithm 1 (Sections 5-10), the w / w+1 test for long
-//               significands (Section 11) and the stores.  Tokens that stay
-//               undecided are appended to a compact queue.
+// One parse call runs four kernels on the caller's stream:
+//   k_count     streams the text once and counts the tokens starting in each
+//               64 KiB block (a token starts at a non-delimiter byte that
+//               follows a delimiter or the start of the text);
+//   k_scan      one workgroup turns the block counts into the index of each
+//               block's first token and writes every job's token count;
+//   k_parse     each workgroup walks whole blocks in LDS tiles: 16-byte
+//               coalesced loads, digit and delimiter bitmaps, a block scan of
+//               token starts, then one lane per token: lexing (Section 4),
+//               Algorithm 1 (Sections 5-10) and the w / w+1 test for long
+//               significands (Section 11).  Undecided tokens go to a queue;
 //   k_fallback  exact decision for the queued tokens by big-integer
-//               comparison against the halfway point between two
-//               neighbouring binary values.
+//               comparison with the halfway points between neighbouring
+//               binary values.
+// No workgroup ever waits for another one.
 #include <hip/hip_runtime.h>
 
 #include "ffp_device.h"
@@ -23,31 +27,45 @@ namespace ffp {
 __device__ const unsigned long long g_table[FFP_TABLE_SIZE * 2] = {FFP_TABLE_ENTRIES};
 
 // ---------------------------------------------------------------------------
-// small wave / block helpers
+// helpers
 // ---------------------------------------------------------------------------
+#define FFP_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const FFP_GLOBAL T*)p;  // address-space cast: a global load
+}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(FFP_GLOBAL T*)p = v;  // address-space cast: a global store
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
   return v;
 }
 
-// Exclusive scan over the 256 threads of a block; `total` receives the sum.
-// s_tmp holds 4 words and must not be reused before the next barrier.
-__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t& total,
-                                                    uint64_t* s_tmp) {
+// Exclusive scan over the threads of a block of `nthreads` threads; `total`
+// receives the sum.  s_tmp holds nthreads / 64 words and must not be reused
+// before the next barrier.
+template <int nthreads, class T>
+__device__ __forceinline__ T block_excl_scan(T v, T& total, T* s_tmp) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  uint64_t x = v;
+  T x = v;
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
-    const uint64_t y = __shfl_up(x, d, kWave);
+    const T y = __shfl_up(x, d, kWave);
     if (lane >= d) x += y;
   }
   if (lane == kWave - 1) s_tmp[wid] = x;
   __syncthreads();
-  uint64_t before = 0, sum = 0;
+  T before = 0, sum = 0;
 #pragma unroll
-  for (int i = 0; i < kThreads / kWave; ++i) {
-    const uint64_t t = s_tmp[i];
+  for (int i = 0; i < nthreads / kWave; ++i) {
+    const T t = s_tmp[i];
     before += (i < wid) ? t : 0;
     sum += t;
   }
@@ -55,31 +73,199 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t& total,
   return before + x - v;
 }
 
-__device__ __forceinline__ uint64_t atomic_load_agent(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void atomic_store_agent(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Job that owns global block b.
+__device__ __forceinline__ JobDesc job_of_block(const JobSet& js, uint64_t b) {
+  if (!js.jobs) return js.single;
+  uint32_t lo = 0, hi = js.njobs;  // last job with block_begin <= b
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (js.jobs[mid].block_begin <= b) lo = mid; else hi = mid;
+  }
+  return js.jobs[lo];
 }
 
-// Look-back spin budget: a predecessor publishes its aggregate right after
-// counting its own tile, so this is never reached unless the scan state is
-// corrupt; the kernel then records an internal error and still exits.
-constexpr uint32_t kSpinLimit = 1u << 22;
+__device__ __forceinline__ uint64_t total_blocks_of(const JobSet& js) {
+  return js.jobs ? *js.total_blocks_dev : js.total_blocks;
+}
+
+// Blocks of a job: its text starts `align` bytes into the first block.
+__device__ __forceinline__ uint64_t job_blocks(const JobDesc& job) {
+  if (job.nbytes == 0) return 0;
+  const uint64_t vend = job.nbytes + ((uint64_t)(uintptr_t)job.text & 15u);
+  return (vend + kBlockBytes - 1) / kBlockBytes;
+}
+
+// High bit of each byte of x set for non-delimiter bytes (single delimiter
+// byte replicated in drep) / for ASCII digits; exact per byte (no carry or
+// borrow crosses a byte).
+__device__ __forceinline__ uint32_t nondelim_word(uint32_t x, uint32_t drep) {
+  const uint32_t y = x ^ drep;
+  return (((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y) & 0x80808080u;
+}
+
+__device__ __forceinline__ uint32_t digit_word(uint32_t x) {
+  const uint32_t xh = x | 0x80808080u;
+  return (xh - 0x30303030u) & ~(xh - 0x3A3A3A3Au) & ~x & 0x80808080u;
+}
+
+__device__ __forceinline__ uint32_t nondelim_word_lut(uint32_t x, const uint8_t* lut) {
+  uint32_t h = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) h |= (lut[(x >> (8 * b)) & 0xFF] ? 0u : 0x80u) << (8 * b);
+  return h;
+}
+
+// Gather the high bits of the bytes of four words into a 16-bit mask.
+__device__ __forceinline__ uint32_t pack_high_bits(uint32_t h0, uint32_t h1, uint32_t h2,
+                                                   uint32_t h3) {
+  const uint32_t lo = __builtin_amdgcn_udot4(
+      h1, 0x80402010u, __builtin_amdgcn_udot4(h0, 0x08040201u, 0u, false), false);
+  const uint32_t hi = __builtin_amdgcn_udot4(
+      h3, 0x80402010u, __builtin_amdgcn_udot4(h2, 0x08040201u, 0u, false), false);
+  return (lo >> 7) | ((hi >> 7) << 8);
+}
+
+// 16 bytes of virtual text [off, off+16) of a job: one aligned load inside the
+// text; byte by byte at its two ends, where bytes outside the text read as a
+// delimiter and no memory outside it is touched.
+__device__ __forceinline__ uint4 load_chunk(const uint8_t* vbase, uint64_t off, uint64_t align,
+                                            uint64_t vend, uint32_t pad) {
+  if (off >= align && off + kChunk <= vend) {
+    const u32x4 v = gload(reinterpret_cast<const u32x4*>(vbase + off));
+    return make_uint4(v.x, v.y, v.z, v.w);
+  }
+  uint32_t wds[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint64_t o = off + k * 4 + b;
+      const uint32_t byte = (o >= align && o < vend) ? (uint32_t)gload(vbase + o) : pad;
+      word |= byte << (8 * b);
+    }
+    wds[k] = word;
+  }
+  return make_uint4(wds[0], wds[1], wds[2], wds[3]);
+}
+
+template <bool kSingle>
+__device__ __forceinline__ uint32_t nondelim_mask16(uint4 v, uint32_t drep, const uint8_t* lut) {
+  if (kSingle)
+    return pack_high_bits(nondelim_word(v.x, drep), nondelim_word(v.y, drep),
+                          nondelim_word(v.z, drep), nondelim_word(v.w, drep));
+  return pack_high_bits(nondelim_word_lut(v.x, lut), nondelim_word_lut(v.y, lut),
+                        nondelim_word_lut(v.z, lut), nondelim_word_lut(v.w, lut));
+}
+
+// Is the byte just before virtual offset off a non-delimiter?
+__device__ __forceinline__ uint32_t prev_nondelim(const uint8_t* vbase, uint64_t off,
+                                                  uint64_t align, const DelimSet& d) {
+  if (off <= align) return 0;  // start of the text
+  return is_delim(d, gload(vbase + off - 1)) ? 0u : 1u;
+}
 
 // ---------------------------------------------------------------------------
-// k_init
+// k_count: tokens starting in each block.  Each thread classifies 16 chunks
+// of 16 bytes; the start mask of a chunk needs the last bit of the chunk
+// before it, exchanged through LDS.
 // ---------------------------------------------------------------------------
-__global__ void k_init(uint64_t* tile_state, uint64_t ntiles, DeviceState* st,
-                       uint64_t* count_out) {
-  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = tid; i < ntiles; i += stride) tile_state[i] = 0;
+constexpr int kCountRows = (int)(kBlockBytes / (kThreads * kChunk));  // 16
+
+template <bool kSingle>
+__global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
+  __shared__ uint16_t s_nd[kCountRows * kThreads];
+  __shared__ uint8_t s_lut[256];
+  __shared__ uint32_t s_scan[kThreads / kWave];
+  __shared__ uint32_t s_prev;
+  const int tid = threadIdx.x;
+  if (!kSingle)
+    for (int i = tid; i < 256; i += kThreads) s_lut[i] = is_delim(P.delim, (uint32_t)i);
+  const uint32_t drep = P.delim.byte * 0x01010101u;
+  const uint64_t nblk = total_blocks_of(P.js);
+  for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const JobDesc job = job_of_block(P.js, b);
+    const uint64_t align = (uint64_t)(uintptr_t)job.text & 15u;
+    const uint8_t* vbase = job.text - align;
+    const uint64_t vend = job.nbytes + align;
+    const uint64_t bstart = (b - job.block_begin) * kBlockBytes;
+    __syncthreads();  // s_nd / s_prev of the previous block are consumed
+    uint32_t m[kCountRows];
+#pragma unroll
+    for (int r = 0; r < kCountRows; ++r) {
+      const uint64_t off = bstart + (uint64_t)(r * kThreads + tid) * kChunk;
+      m[r] = off < vend ? nondelim_mask16<kSingle>(
+                              load_chunk(vbase, off, align, vend, P.delim.byte), drep, s_lut)
+                        : 0u;
+      s_nd[r * kThreads + tid] = (uint16_t)m[r];
+    }
+    if (tid == 0) s_prev = prev_nondelim(vbase, bstart, align, P.delim);
+    __syncthreads();
+    uint32_t n = 0;
+#pragma unroll
+    for (int r = 0; r < kCountRows; ++r) {
+      const int chunk = r * kThreads + tid;
+      const uint32_t pb = chunk == 0 ? s_prev : ((uint32_t)s_nd[chunk - 1] >> 15);
+      n += __popc(m[r] & ~((m[r] << 1) | pb) & 0xFFFFu);
+    }
+    uint32_t total;
+    (void)block_excl_scan<kThreads>(n, total, s_scan);
+    if (tid == 0) P.block_sum[b] = total;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_scan: exclusive prefix of the block counts (in place, one extra entry for
+// the grand total), each job's token count, and the per-call reset of the
+// fallback queue and the device error word.
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
+  __shared__ uint32_t s_scan[kScanThreads / kWave];
+  __shared__ uint64_t s_carry;
+  const int tid = threadIdx.x;
+  const uint64_t n = total_blocks_of(P.js);
+  if (tid == 0) s_carry = 0;
+  for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * kScanPer) {
+    uint64_t v[kScanPer];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      const uint64_t k = base + (uint64_t)tid * kScanPer + i;
+      v[i] = k < n ? P.block_sum[k] : 0;
+      sum += v[i];
+    }
+    __syncthreads();  // s_carry of the previous round is final
+    const uint64_t carry = s_carry;
+    // a round covers 8192 blocks of 64 KiB with at most 32768 token starts
+    // each: its sums fit in 32 bits
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<kScanThreads>((uint32_t)sum, total, s_scan);
+    uint64_t run = carry + ex;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+      const uint64_t k = base + (uint64_t)tid * kScanPer + i;
+      if (k < n) P.block_sum[k] = run;
+      run += v[i];
+    }
+    __syncthreads();
+    if (tid == 0) s_carry = carry + total;
+  }
+  __syncthreads();
   if (tid == 0) {
-    st->tile_counter = 0;
-    st->error = 0;
-    st->queue_tail = 0;
-    if (count_out) *count_out = 0;
+    P.block_sum[n] = s_carry;
+    P.st->queue_tail = 0;
+    P.st->error = 0;
+  }
+  __syncthreads();
+  // token count of every job: prefix at its end minus prefix at its start
+  const uint32_t nj = P.js.jobs ? P.js.njobs : 1;
+  for (uint32_t j = tid; j < nj; j += kScanThreads) {
+    const JobDesc job = P.js.jobs ? P.js.jobs[j] : P.js.single;
+    const uint64_t b0 = job.block_begin, b1 = b0 + job_blocks(job);
+    *job.count_out = P.block_sum[b1] - P.block_sum[b0];
   }
 }
 
@@ -90,19 +276,30 @@ template <int K>
 struct TileSmem {
   static constexpr int kBytes = kThreads * kChunk * K;
   static constexpr int kChunks = kThreads * K;
+  static constexpr int kTiles = (int)(kBlockBytes / kBytes);
+  // The fast lexer reads up to 24 bytes before and 68 bytes after a token
+  // start; the pads keep those reads inside the array (their contents are
+  // masked off).
+  static constexpr int kPadFront = 32;
+  static constexpr int kPadBack = 96;
+  // block scan of the per-thread start counts: one 16-bit field per row of
+  // 256 chunks (a row holds at most 2048 starts)
+  using Packed = typename std::conditional<(K <= 2), uint32_t, uint64_t>::type;
   unsigned long long table[FFP_TABLE_SIZE * 2];
-  alignas(16) uint8_t text[kBytes];
+  unsigned long long pow10[20];
+  alignas(16) uint8_t text[kPadFront + kBytes + kPadBack];
   uint16_t starts[kBytes / 2];
-  uint16_t nd[kChunks];
+  // bit i of these bitmaps describes byte i of the tile (16 bits per chunk),
+  // followed by 128 zero bits so that 64-bit windows stay in range
+  alignas(8) uint16_t nd[kChunks + 8];  // not a delimiter
+  alignas(8) uint16_t dg[kChunks + 8];  // ASCII digit
   uint8_t delim_lut[256];
-  uint64_t scan[kThreads / kWave];
-  uint64_t tile;
-  uint64_t excl;
+  Packed scan[kThreads / kWave];
   uint32_t prev_nd;
 };
 
 struct LdsSrc {
-  const uint8_t* text;  // LDS tile
+  const uint8_t* text;  // LDS tile (first byte of the tile)
   uint64_t tile_start;
   const uint8_t* lut;   // LDS delimiter table
   __device__ __forceinline__ uint32_t operator()(uint64_t i) const {
@@ -111,21 +308,134 @@ struct LdsSrc {
   __device__ __forceinline__ bool is_end(uint32_t c) const { return lut[c] != 0; }
 };
 
-template <class F>
-__device__ __forceinline__ void store_result(const JobDesc& job, uint64_t idx,
-                                             typename F::bits_t bits, uint8_t st) {
-  reinterpret_cast<typename F::bits_t*>(job.values)[idx] = bits;
-  job.status[idx] = st;
+// 64 bits of a tile bitmap starting at bit s.
+__device__ __forceinline__ uint64_t bit_window(const uint16_t* bm, uint32_t s) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(bm);
+  const uint32_t i = s >> 5, sh = s & 31;
+  const uint64_t lo = (uint64_t)w[i] | ((uint64_t)w[i + 1] << 32);
+  const uint64_t hi = w[i + 2];
+  return sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
 }
 
-// Decide one token; src_pos is its first byte in the source's coordinates,
-// text_pos its offset in the job's text.  Returns the path counter index.
-template <class F, class Src>
-__device__ __forceinline__ int decide_token(const Src& src, uint64_t src_pos, uint64_t text_pos,
-                                            const JobDesc& job, uint64_t idx,
-                                            const unsigned long long* table,
+// Value of 4 ASCII digits, the first (most significant) in the low byte:
+// (d0*10 + d1) * 100 + (d2*10 + d3) from two byte dot products.
+__device__ __forceinline__ uint32_t value4(uint32_t x) {
+  return __builtin_amdgcn_udot4(x, 0x0000010Au, 0u, false) * 100u +
+         __builtin_amdgcn_udot4(x, 0x010A0000u, 0u, false);
+}
+
+// Value of the n (0..8) ASCII digits that end just before tile offset `end`
+// (SWAR on two 32-bit words; Appendix D of the paper does the same on one
+// 64-bit word).  Reads bytes [end-8, end).
+template <int K>
+__device__ __forceinline__ uint32_t digits8_before(const TileSmem<K>& sm, int end, int n) {
+  const int A = end - 8 + TileSmem<K>::kPadFront;
+  const uint32_t* W = reinterpret_cast<const uint32_t*>(sm.text);
+  const uint32_t w0 = W[A >> 2], w1 = W[(A >> 2) + 1], w2 = W[(A >> 2) + 2];
+  uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)A & 3u);
+  uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, (uint32_t)A & 3u);
+  const int drop = 8 - n;  // leading bytes that are not part of the run
+  const uint64_t keep = drop >= 8 ? 0ull : (~0ull << (8 * drop));
+  lo &= (uint32_t)keep & 0x0F0F0F0Fu;
+  hi &= (uint32_t)(keep >> 32) & 0x0F0F0F0Fu;
+  return value4(lo) * 10000u + value4(hi);
+}
+
+// Same for n (0..4) digits.  Reads bytes [end-4, end).
+template <int K>
+__device__ __forceinline__ uint32_t digits4_before(const TileSmem<K>& sm, int end, int n) {
+  const int A = end - 4 + TileSmem<K>::kPadFront;
+  const uint32_t* W = reinterpret_cast<const uint32_t*>(sm.text);
+  const uint32_t w0 = W[A >> 2], w1 = W[(A >> 2) + 1];
+  const uint32_t x = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)A & 3u);
+  const uint32_t keep = n <= 0 ? 0u : (~0u << (8 * (4 - n)));
+  return value4(x & keep & 0x0F0F0F0Fu);
+}
+
+// Value of the n (0..19) digits ending before `end`; the wave skips groups
+// that no lane needs.
+template <int K>
+__device__ __forceinline__ uint64_t digits_before(const TileSmem<K>& sm, int end, int n) {
+  if (__all(n <= 4)) return digits4_before<K>(sm, end, n);
+  uint64_t v = digits8_before<K>(sm, end, n < 8 ? n : 8);
+  if (__any(n > 8)) {
+    const int n1 = n > 16 ? 8 : (n > 8 ? n - 8 : 0);
+    v += (uint64_t)digits8_before<K>(sm, end - 8, n1) * 100000000ull;
+    if (__any(n > 16)) {
+      const int n2 = n > 16 ? n - 16 : 0;
+      v += (uint64_t)digits8_before<K>(sm, end - 16, n2) * 10000000000000000ull;
+    }
+  }
+  return v;
+}
+
+constexpr uint32_t kFastOk = 0, kFastInvalid = 1, kFastSlow = 2;
+
+struct FastLex {
+  uint64_t w;
+  int32_t q;
+  uint32_t neg;
+  uint32_t code;
+};
+
+// Lexer for a token lying wholly inside the tile, from the digit and
+// delimiter bitmaps: the runs of the grammar are found with count-trailing-
+// zeros instead of a loop over bytes, and the digits are converted up to
+// eight at a time.  Tokens of 64 bytes or more, with more than 19 mantissa
+// digits or more than 8 exponent digits are left to the byte-by-byte lexer
+// (kFastSlow); for all others the result equals lex_token's.
+template <int K>
+__device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, uint32_t flags) {
+  FastLex r;
+  r.w = 0;
+  r.q = 0;
+  r.neg = 0;
+  r.code = kFastSlow;
+  const uint8_t* tb = sm.text + TileSmem<K>::kPadFront;
+  const uint64_t nd = bit_window(sm.nd, s);
+  if (~nd == 0) return r;
+  const uint64_t dg = bit_window(sm.dg, s);
+  const int L = __builtin_ctzll(~nd);  // token length
+  const uint32_t c0 = tb[s];
+  const int a = (c0 == '-' || c0 == '+') ? 1 : 0;
+  const int b = a + __builtin_ctzll(~(dg >> a));                 // end of integer digits
+  const int f1d = b + 1 + __builtin_ctzll(~((dg >> b) >> 1));    // end of fraction if '.' at b
+  const uint32_t cb = tb[s + b], cb1 = tb[s + b + 1];
+  const uint32_t cf = tb[s + f1d], cf1 = tb[s + f1d + 1];
+  const bool dot = cb == '.';
+  const int f0 = dot ? b + 1 : b;
+  const int f1 = dot ? f1d : b;
+  const uint32_t cx = dot ? cf : cb, cx1 = dot ? cf1 : cb1;
+  const bool has_e = f1 < L && (cx | 0x20u) == 'e';
+  const bool es = has_e && (cx1 == '-' || cx1 == '+');
+  const int e0 = f1 + 1 + (es ? 1 : 0);
+  const int e1 = has_e ? e0 + __builtin_ctzll(~(dg >> (e0 & 63))) : e0;
+  const int end = has_e ? e1 : f1;
+  const int nint = b - a, nfrac = f1 - f0, nexp = e1 - e0;
+  r.neg = c0 == '-';
+  const bool valid = end == L && nint + nfrac > 0 && (!has_e || nexp > 0) &&
+                     !(c0 == '+' && (flags & 1u));
+  if (!valid) {
+    r.code = kFastInvalid;
+    return r;
+  }
+  if (nint + nfrac > 19 || nexp > 8) return r;
+  const uint64_t iv = digits_before<K>(sm, (int)s + b, nint);
+  const uint64_t fv = digits_before<K>(sm, (int)s + f1, nfrac);
+  r.w = iv * sm.pow10[nfrac] + fv;
+  int ev = 0;
+  if (__any(has_e)) ev = (int)digits8_before<K>(sm, (int)s + e1, has_e ? nexp : 0);
+  r.q = (es && cx1 == '-' ? -ev : ev) - nfrac;
+  r.code = kFastOk;
+  return r;
+}
+
+// Algorithm 1 (and w+1 for long significands) on a lexed token, the queue
+// append for undecided tokens, and the stores.  Returns the path counter.
+template <class F>
+__device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, const JobDesc& job,
+                                            uint64_t idx, const unsigned long long* table,
                                             const ParseParams& P) {
-  const Lexed L = lex_token(src, src_pos, P.flags);
   Decision<F> d = decide_lexed<F>(L, table);
   uint8_t st = (uint8_t)d.status;
   if (d.fallback) {
@@ -140,204 +450,144 @@ __device__ __forceinline__ int decide_token(const Src& src, uint64_t src_pos, ui
     }
     st = kPending;
   }
-  store_result<F>(job, idx, d.bits, st);
+  gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, d.bits);
+  gstore(job.status + idx, st);
   return (int)d.path;
 }
 
-template <int K>
+template <int K, bool kSingle>
 __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
   using S = TileSmem<K>;
+  using Packed = typename S::Packed;
   __shared__ S sm;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wid = tid / kWave;
 
   for (int i = tid; i < FFP_TABLE_SIZE * 2; i += kThreads) sm.table[i] = g_table[i];
   for (int i = tid; i < 256; i += kThreads) sm.delim_lut[i] = is_delim(P.delim, (uint32_t)i);
-
-  const uint64_t total_tiles = P.jobs ? *P.total_tiles_dev : P.total_tiles;
+  if (tid < 20) {
+    unsigned long long p = 1;
+    for (int i = 0; i < tid; ++i) p *= 10;
+    sm.pow10[tid] = p;
+  }
+  if (tid < 8) {
+    sm.nd[S::kChunks + tid] = 0;
+    sm.dg[S::kChunks + tid] = 0;
+  }
+  const uint32_t drep = P.delim.byte * 0x01010101u;
+  const uint64_t nblk = total_blocks_of(P.js);
   // path counters, kept in scalars (a runtime-indexed array would live in
   // scratch memory)
   uint32_t c_tok = 0, c_inv = 0, c_early = 0, c_one = 0, c_two = 0, c_fb = 0;
 
-  for (;;) {
-    if (tid == 0) sm.tile = atomicAdd(&P.st->tile_counter, 1u);
-    __syncthreads();
-    const uint64_t tile = sm.tile;
-    if (tile >= total_tiles) break;
-
-    // -- which job owns this tile --------------------------------------
-    JobDesc job;
-    if (P.jobs) {
-      uint32_t lo = 0, hi = P.njobs;  // last job with tile_begin <= tile
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (P.jobs[mid].tile_begin <= tile) lo = mid; else hi = mid;
-      }
-      job = P.jobs[lo];
-    } else {
-      job = P.single;
-    }
+  for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const JobDesc job = job_of_block(P.js, blk);
     // Tiles cover the job's text as if it started at the 16-byte boundary
-    // below `text`: virtual byte v is text[v - align].  Chunks wholly inside
-    // the text use one aligned 16-byte load; the (at most two) edge chunks
-    // of a job load byte by byte and never touch memory outside the text.
+    // below `text`: virtual byte v is text[v - align].
     const uint64_t align = (uint64_t)(uintptr_t)job.text & 15u;
     const uint8_t* vbase = job.text - align;
-    const uint64_t tile_in_job = tile - job.tile_begin;
-    const uint64_t tile_start = tile_in_job * S::kBytes;  // virtual
     const uint64_t nbytes = job.nbytes;
     const uint64_t vend = nbytes + align;
+    const uint64_t bstart = (blk - job.block_begin) * kBlockBytes;
+    uint64_t next_idx = P.block_prefix[blk] - P.block_prefix[job.block_begin];
+    const GlobalSrc gsrc{job.text, nbytes, P.delim};
 
-    // -- load the tile and classify bytes ------------------------------
-    uint32_t ndm[K];
+    for (int t = 0; t < S::kTiles; ++t) {
+      const uint64_t tile_start = bstart + (uint64_t)t * S::kBytes;  // virtual
+      if (tile_start >= vend) break;
+      __syncthreads();  // LDS of the previous tile is consumed
+      // -- load the tile and classify bytes ----------------------------
+      uint32_t ndm[K];
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
-      const int chunk = c * kThreads + tid;
-      const uint64_t off = tile_start + (uint64_t)chunk * kChunk;
-      uint4 v;
-      if (off >= align && off + kChunk <= vend) {
-        v = *reinterpret_cast<const uint4*>(vbase + off);
-      } else {
-        uint32_t wds[4];
+      for (int c = 0; c < K; ++c) {
+        const int chunk = c * kThreads + tid;
+        const uint4 v = load_chunk(vbase, tile_start + (uint64_t)chunk * kChunk, align, vend,
+                                   P.delim.byte);
+        *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + chunk * kChunk]) = v;
+        ndm[c] = nondelim_mask16<kSingle>(v, drep, sm.delim_lut);
+        sm.nd[chunk] = (uint16_t)ndm[c];
+        sm.dg[chunk] = (uint16_t)pack_high_bits(digit_word(v.x), digit_word(v.y),
+                                                digit_word(v.z), digit_word(v.w));
+      }
+      if (tid == 0 && t == 0) sm.prev_nd = prev_nondelim(vbase, tile_start, align, P.delim);
+      __syncthreads();
+
+      // -- token starts: non-delimiter byte after a delimiter -----------
+      uint32_t startm[K];
+      Packed packed = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uint32_t word = 0;
+      for (int c = 0; c < K; ++c) {
+        const int chunk = c * kThreads + tid;
+        const uint32_t prevbit =
+            chunk == 0 ? sm.prev_nd : ((uint32_t)sm.nd[chunk - 1] >> 15) & 1u;
+        const uint32_t m = ndm[c];
+        startm[c] = m & ~((m << 1) | prevbit) & 0xFFFFu;
+        packed |= (Packed)__popc(startm[c]) << (16 * c);
+      }
+      Packed total_packed;
+      const Packed excl_packed = block_excl_scan<kThreads>(packed, total_packed, sm.scan);
+      uint32_t row_off[K];
+      uint32_t ntok = 0;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const uint64_t o = off + k * 4 + b;
-            const uint32_t byte = (o >= align && o < vend) ? vbase[o] : P.delim.byte;
-            word |= byte << (8 * b);
-          }
-          wds[k] = word;
+      for (int c = 0; c < K; ++c) {
+        row_off[c] = ntok;
+        ntok += (uint32_t)(total_packed >> (16 * c)) & 0xFFFFu;
+      }
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        uint32_t p = row_off[c] + ((uint32_t)(excl_packed >> (16 * c)) & 0xFFFFu);
+        uint32_t m = startm[c];
+        const uint32_t base = (uint32_t)((c * kThreads + tid) * kChunk);
+        while (m) {
+          const uint32_t k = __ffs(m) - 1;
+          sm.starts[p++] = (uint16_t)(base + k);
+          m &= m - 1;
         }
-        v = make_uint4(wds[0], wds[1], wds[2], wds[3]);
       }
-      *reinterpret_cast<uint4*>(&sm.text[chunk * kChunk]) = v;
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-      uint32_t m = 0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const uint32_t byte = (w4[k >> 2] >> (8 * (k & 3))) & 0xFF;
-        const bool nd = P.delim.single ? (byte != P.delim.byte) : !sm.delim_lut[byte];
-        m |= (uint32_t)nd << k;
-      }
-      ndm[c] = m;
-      sm.nd[chunk] = (uint16_t)m;
-    }
-    if (tid == 0) {
-      uint32_t prev = 0;
-      if (tile_start > align) {
-        const uint32_t byte = vbase[tile_start - 1];
-        prev = P.delim.single ? (byte != P.delim.byte) : !is_delim(P.delim, byte);
-      }
-      sm.prev_nd = prev;
-    }
-    __syncthreads();
+      __syncthreads();
 
-    // -- token starts: non-delimiter byte after a delimiter -------------
-    uint32_t startm[K];
-    uint64_t packed = 0;
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-      const int chunk = c * kThreads + tid;
-      const uint32_t prevbit = chunk == 0 ? sm.prev_nd : ((uint32_t)sm.nd[chunk - 1] >> 15) & 1u;
-      const uint32_t m = ndm[c];
-      startm[c] = m & ~((m << 1) | prevbit) & 0xFFFFu;
-      packed |= (uint64_t)__popc(startm[c]) << (16 * c);
-    }
-    uint64_t total_packed;
-    const uint64_t excl_packed = block_excl_scan(packed, total_packed, sm.scan);
-    uint32_t row_off[K];
-    uint32_t ntok = 0;
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-      row_off[c] = ntok;
-      ntok += (uint32_t)((total_packed >> (16 * c)) & 0xFFFF);
-    }
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-      uint32_t p = row_off[c] + (uint32_t)((excl_packed >> (16 * c)) & 0xFFFF);
-      uint32_t m = startm[c];
-      const uint32_t base = (uint32_t)((c * kThreads + tid) * kChunk);
-      while (m) {
-        const uint32_t k = __ffs(m) - 1;
-        sm.starts[p++] = (uint16_t)(base + k);
-        m &= m - 1;
-      }
-    }
-
-    // -- decoupled look-back for the global index of the first token ----
-    if (wid == 0) {
-      const uint64_t agg = ntok;
-      uint64_t excl = 0;
-      uint64_t* state = P.tile_state;
-      if (tile_in_job == 0) {
-        if (lane == 0) atomic_store_agent(&state[tile], kFlagInc | agg);
-      } else {
-        if (lane == 0) atomic_store_agent(&state[tile], kFlagAgg | agg);
-        int64_t look = (int64_t)tile - 1 - lane;
-        const int64_t first = (int64_t)job.tile_begin;
-        uint32_t spins = 0;
-        for (;;) {
-          const uint64_t s = look >= first ? atomic_load_agent(&state[look]) : kFlagInc;
-          const uint32_t flag = (uint32_t)(s >> 62);
-          const uint64_t incm = __ballot(flag == 2);
-          const uint64_t window = incm ? (((incm & (~incm + 1)) << 1) - 1) : ~0ull;
-          const uint64_t invm = __ballot(flag == 0) & window;
-          if (invm) {
-            if (++spins > kSpinLimit) {
-              if (lane == 0) atomicOr(&P.st->error, (unsigned)kDevInternal);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          const uint64_t mine = ((window >> lane) & 1ull) ? (s & kValueMask) : 0;
-          excl += wave_sum_u64(mine);
-          if (incm) break;
-          look -= kWave;
+      // -- one lane per token -------------------------------------------
+      // When the tile's last byte belongs to a token, that token (the last
+      // one starting here) may continue past the tile: it is read from
+      // global memory, which returns a delimiter past the end of the text.
+      const bool straddle = (sm.nd[S::kChunks - 1] >> 15) & 1u;
+      const LdsSrc lsrc{sm.text + S::kPadFront, tile_start, sm.delim_lut};
+      for (uint32_t j = tid; j < ntok; j += kThreads) {
+        const uint64_t idx = next_idx + j;
+        if (idx >= job.capacity) break;
+        const uint32_t s = sm.starts[j];
+        const uint64_t vpos = tile_start + s;  // virtual
+        const uint64_t pos = vpos - align;     // offset in the text
+        const bool global = straddle && j == ntok - 1;
+        FastLex fl;
+        if (!global) {
+          fl = fast_lex<K>(sm, s, P.flags);
+        } else {
+          fl.code = kFastSlow;
         }
-        if (lane == 0) atomic_store_agent(&state[tile], kFlagInc | (excl + agg));
+        Lexed L;
+        if (fl.code == kFastSlow) {
+          L = global ? lex_token(gsrc, pos, P.flags) : lex_token(lsrc, vpos, P.flags);
+        } else {
+          L.w = fl.w;
+          L.q = fl.q;
+          L.neg = fl.neg;
+          L.kind = fl.code == kFastInvalid ? kLexInvalid : kLexExact;
+        }
+        const int path = job.dtype == kF64 ? finish_token<F64>(L, pos, job, idx, sm.table, P)
+                                           : finish_token<F32>(L, pos, job, idx, sm.table, P);
+        if (P.count_paths) {
+          c_tok += 1;
+          c_inv += path == kCntInvalid;
+          c_early += path == kCntEarly;
+          c_one += path == kCntOne;
+          c_two += path == kCntTwo;
+          c_fb += path == kCntFallback;
+        }
       }
-      if (lane == 0) {
-        sm.excl = excl;
-        const uint64_t ntiles_job = (vend + S::kBytes - 1) / S::kBytes;
-        if (tile_in_job + 1 == ntiles_job) *job.count_out = excl + agg;
-      }
+      next_idx += ntok;
+      if (tid == 0) sm.prev_nd = (sm.nd[S::kChunks - 1] >> 15) & 1u;
     }
-    __syncthreads();
-    const uint64_t excl = sm.excl;
-
-    // -- one lane per token ---------------------------------------------
-    // When the tile's last byte belongs to a token, that token (the last
-    // one starting here) may continue past the tile: it is read from global
-    // memory, which returns a delimiter past the end of the buffer.
-    const bool straddle = (sm.nd[S::kChunks - 1] >> 15) & 1u;
-    LdsSrc lsrc{sm.text, tile_start, sm.delim_lut};
-    GlobalSrc gsrc{job.text, nbytes, P.delim};
-    for (uint32_t j = tid; j < ntok; j += kThreads) {
-      const uint64_t idx = excl + j;
-      if (idx >= job.capacity) break;
-      const uint64_t vpos = tile_start + sm.starts[j];  // virtual
-      const uint64_t pos = vpos - align;                 // offset in the text
-      int path;
-      const bool global = straddle && j == ntok - 1;
-      if (job.dtype == kF64) {
-        path = global ? decide_token<F64>(gsrc, pos, pos, job, idx, sm.table, P)
-                      : decide_token<F64>(lsrc, vpos, pos, job, idx, sm.table, P);
-      } else {
-        path = global ? decide_token<F32>(gsrc, pos, pos, job, idx, sm.table, P)
-                      : decide_token<F32>(lsrc, vpos, pos, job, idx, sm.table, P);
-      }
-      c_tok += 1;
-      c_inv += path == kCntInvalid;
-      c_early += path == kCntEarly;
-      c_one += path == kCntOne;
-      c_two += path == kCntTwo;
-      c_fb += path == kCntFallback;
-    }
-    __syncthreads();
   }
 
   if (P.count_paths) {
@@ -364,8 +614,8 @@ __device__ void fallback_token(const JobDesc& job, uint64_t pos, uint64_t idx,
   const GlobalSrc src{job.text, job.nbytes, delim};
   if (!fallback_decide<F>(src, pos, g_table, lds, kWave, bits, status))
     atomicOr(&st->error, (unsigned)kDevInternal);
-  reinterpret_cast<typename F::bits_t*>(job.values)[idx] = bits;
-  job.status[idx] = (uint8_t)status;
+  gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, bits);
+  gstore(job.status + idx, (uint8_t)status);
 }
 
 __global__ __launch_bounds__(kFbThreads) void k_fallback(FallbackParams P) {
@@ -378,7 +628,7 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(FallbackParams P) {
     const QueueEntry e = P.queue[i];
     const uint32_t job_id = (uint32_t)(e.index_job >> 48);
     const uint64_t idx = e.index_job & ((1ull << 48) - 1);
-    const JobDesc job = P.jobs ? P.jobs[job_id] : P.single;
+    const JobDesc job = P.js.jobs ? P.js.jobs[job_id] : P.js.single;
     if (job.dtype == kF64) {
       fallback_token<F64>(job, e.offset, idx, P.delim, P.st, mine);
     } else {
@@ -390,38 +640,47 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(FallbackParams P) {
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-template <int K>
-static hipError_t launch_parse_k(const ParseParams& P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_parse<K>, dim3(grid), dim3(kThreads), 0, s, P);
-  return hipGetLastError();
-}
-
 int parse_tile_bytes(int k) { return kThreads * kChunk * k; }
 
-hipError_t parse_occupancy(int k, int* blocks_per_cu) {
+template <int K>
+static hipError_t occ_k(bool single, int* blocks) {
+  return single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_parse<K, true>, kThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_parse<K, false>, kThreads, 0);
+}
+
+hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu) {
   switch (k) {
-    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_parse<1>, kThreads, 0);
-    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_parse<2>, kThreads, 0);
-    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_parse<4>, kThreads, 0);
+    case 1: return occ_k<1>(single_delim, blocks_per_cu);
+    case 2: return occ_k<2>(single_delim, blocks_per_cu);
+    case 4: return occ_k<4>(single_delim, blocks_per_cu);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_init(uint64_t* tile_state, uint64_t ntiles, DeviceState* st,
-                       uint64_t* count_out, hipStream_t s) {
-  uint64_t blocks = (ntiles + 255) / 256;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(256), 0, s, tile_state, ntiles, st,
-                     count_out);
+hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipStream_t s) {
+  if (single_delim)
+    hipLaunchKernelGGL((k_count<true>), dim3(grid), dim3(kThreads), 0, s, P);
+  else
+    hipLaunchKernelGGL((k_count<false>), dim3(grid), dim3(kThreads), 0, s, P);
   return hipGetLastError();
 }
 
-hipError_t launch_parse(int k, const ParseParams& P, int grid, hipStream_t s) {
+hipError_t launch_scan(const ScanParams& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, P);
+  return hipGetLastError();
+}
+
+template <int K, bool kSingle>
+static hipError_t launch_parse_k(const ParseParams& P, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_parse<K, kSingle>), dim3(grid), dim3(kThreads), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_parse(int k, bool single_delim, const ParseParams& P, int grid, hipStream_t s) {
   switch (k) {
-    case 1: return launch_parse_k<1>(P, grid, s);
-    case 2: return launch_parse_k<2>(P, grid, s);
-    case 4: return launch_parse_k<4>(P, grid, s);
+    case 1: return single_delim ? launch_parse_k<1, true>(P, grid, s) : launch_parse_k<1, false>(P, grid, s);
+    case 2: return single_delim ? launch_parse_k<2, true>(P, grid, s) : launch_parse_k<2, false>(P, grid, s);
+    case 4: return single_delim ? launch_parse_k<4, true>(P, grid, s) : launch_parse_k<4, false>(P, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
