@@ -23,7 +23,7 @@ struct ffp_ctx {
   DelimSet delim{};
   uint32_t flags = 0;
   int num_cus = 0;
-  int tile_k = 2;
+  int tile_k = 4;
   int blocks_per_cu = 1;
   int fb_grid = 0;
 

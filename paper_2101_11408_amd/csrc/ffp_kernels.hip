@@ -277,7 +277,7 @@ struct TileSmem {
   static constexpr int kBytes = kThreads * kChunk * K;
   static constexpr int kChunks = kThreads * K;
   static constexpr int kTiles = (int)(kBlockBytes / kBytes);
-  // The fast lexer reads up to 24 bytes before and 68 bytes after a token
+  // The fast lexer reads up to 24 bytes before and 36 bytes after a token
   // start; the pads keep those reads inside the array (their contents are
   // masked off).
   static constexpr int kPadFront = 32;
@@ -290,7 +290,7 @@ struct TileSmem {
   alignas(16) uint8_t text[kPadFront + kBytes + kPadBack];
   uint16_t starts[kBytes / 2];
   // bit i of these bitmaps describes byte i of the tile (16 bits per chunk),
-  // followed by 128 zero bits so that 64-bit windows stay in range
+  // followed by 128 zero bits so that 32-bit windows stay in range
   alignas(8) uint16_t nd[kChunks + 8];  // not a delimiter
   alignas(8) uint16_t dg[kChunks + 8];  // ASCII digit
   uint8_t delim_lut[256];
@@ -308,19 +308,17 @@ struct LdsSrc {
   __device__ __forceinline__ bool is_end(uint32_t c) const { return lut[c] != 0; }
 };
 
-// 64 bits of a tile bitmap starting at bit s.
-__device__ __forceinline__ uint64_t bit_window(const uint16_t* bm, uint32_t s) {
+// 32 bits of a tile bitmap starting at bit s (one funnel shift).
+__device__ __forceinline__ uint32_t bit_window(const uint16_t* bm, uint32_t s) {
   const uint32_t* w = reinterpret_cast<const uint32_t*>(bm);
-  const uint32_t i = s >> 5, sh = s & 31;
-  const uint64_t lo = (uint64_t)w[i] | ((uint64_t)w[i + 1] << 32);
-  const uint64_t hi = w[i + 2];
-  return sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+  const uint32_t i = s >> 5;
+  return __builtin_amdgcn_alignbit(w[i + 1], w[i], s & 31);
 }
 
 // Value of 4 ASCII digits, the first (most significant) in the low byte:
 // (d0*10 + d1) * 100 + (d2*10 + d3) from two byte dot products.
 __device__ __forceinline__ uint32_t value4(uint32_t x) {
-  return __builtin_amdgcn_udot4(x, 0x0000010Au, 0u, false) * 100u +
+  return __umul24(__builtin_amdgcn_udot4(x, 0x0000010Au, 0u, false), 100u) +
          __builtin_amdgcn_udot4(x, 0x010A0000u, 0u, false);
 }
 
@@ -338,7 +336,7 @@ __device__ __forceinline__ uint32_t digits8_before(const TileSmem<K>& sm, int en
   const uint64_t keep = drop >= 8 ? 0ull : (~0ull << (8 * drop));
   lo &= (uint32_t)keep & 0x0F0F0F0Fu;
   hi &= (uint32_t)(keep >> 32) & 0x0F0F0F0Fu;
-  return value4(lo) * 10000u + value4(hi);
+  return __umul24(value4(lo), 10000u) + value4(hi);
 }
 
 // Same for n (0..4) digits.  Reads bytes [end-4, end).
@@ -380,10 +378,11 @@ struct FastLex {
 
 // Lexer for a token lying wholly inside the tile, from the digit and
 // delimiter bitmaps: the runs of the grammar are found with count-trailing-
-// zeros instead of a loop over bytes, and the digits are converted up to
-// eight at a time.  Tokens of 64 bytes or more, with more than 19 mantissa
-// digits or more than 8 exponent digits are left to the byte-by-byte lexer
-// (kFastSlow); for all others the result equals lex_token's.
+// zeros on 32-bit windows instead of a loop over bytes, and the digits are
+// converted up to eight at a time.  Tokens of 32 bytes or more, with more than
+// 19 mantissa digits or more than 8 exponent digits are left to the
+// byte-by-byte lexer (kFastSlow); for all others the result equals
+// lex_token's.
 template <int K>
 __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, uint32_t flags) {
   FastLex r;
@@ -392,14 +391,16 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
   r.neg = 0;
   r.code = kFastSlow;
   const uint8_t* tb = sm.text + TileSmem<K>::kPadFront;
-  const uint64_t nd = bit_window(sm.nd, s);
-  if (~nd == 0) return r;
-  const uint64_t dg = bit_window(sm.dg, s);
-  const int L = __builtin_ctzll(~nd);  // token length
+  const uint32_t nd = bit_window(sm.nd, s);
+  if (nd == ~0u) return r;
+  const uint32_t dg = bit_window(sm.dg, s);
+  const int L = __builtin_ctz(~nd);  // token length, < 32
   const uint32_t c0 = tb[s];
   const int a = (c0 == '-' || c0 == '+') ? 1 : 0;
-  const int b = a + __builtin_ctzll(~(dg >> a));                 // end of integer digits
-  const int f1d = b + 1 + __builtin_ctzll(~((dg >> b) >> 1));    // end of fraction if '.' at b
+  // bit L of dg is clear (a delimiter is not a digit), so every count below
+  // stops at or before L
+  const int b = a + __builtin_ctz(~(dg >> a));                // end of integer digits
+  const int f1d = b + 1 + __builtin_ctz(~((dg >> b) >> 1));   // end of fraction if '.' at b
   const uint32_t cb = tb[s + b], cb1 = tb[s + b + 1];
   const uint32_t cf = tb[s + f1d], cf1 = tb[s + f1d + 1];
   const bool dot = cb == '.';
@@ -409,7 +410,7 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
   const bool has_e = f1 < L && (cx | 0x20u) == 'e';
   const bool es = has_e && (cx1 == '-' || cx1 == '+');
   const int e0 = f1 + 1 + (es ? 1 : 0);
-  const int e1 = has_e ? e0 + __builtin_ctzll(~(dg >> (e0 & 63))) : e0;
+  const int e1 = has_e ? e0 + __builtin_ctz(~(dg >> (e0 & 31))) : e0;
   const int end = has_e ? e1 : f1;
   const int nint = b - a, nfrac = f1 - f0, nexp = e1 - e0;
   r.neg = c0 == '-';
@@ -492,22 +493,35 @@ __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
     uint64_t next_idx = P.block_prefix[blk] - P.block_prefix[job.block_begin];
     const GlobalSrc gsrc{job.text, nbytes, P.delim};
 
+    // The chunks of the next tile of the block are loaded into registers
+    // while the current tile's tokens are decided (software pipelining).
+    uint4 pre[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+      pre[c] = load_chunk(vbase, bstart + (uint64_t)(c * kThreads + tid) * kChunk, align, vend,
+                          P.delim.byte);
     for (int t = 0; t < S::kTiles; ++t) {
       const uint64_t tile_start = bstart + (uint64_t)t * S::kBytes;  // virtual
       if (tile_start >= vend) break;
       __syncthreads();  // LDS of the previous tile is consumed
-      // -- load the tile and classify bytes ----------------------------
+      // -- store the tile to LDS and classify bytes ---------------------
       uint32_t ndm[K];
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         const int chunk = c * kThreads + tid;
-        const uint4 v = load_chunk(vbase, tile_start + (uint64_t)chunk * kChunk, align, vend,
-                                   P.delim.byte);
+        const uint4 v = pre[c];
         *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + chunk * kChunk]) = v;
         ndm[c] = nondelim_mask16<kSingle>(v, drep, sm.delim_lut);
         sm.nd[chunk] = (uint16_t)ndm[c];
         sm.dg[chunk] = (uint16_t)pack_high_bits(digit_word(v.x), digit_word(v.y),
                                                 digit_word(v.z), digit_word(v.w));
+      }
+      const uint64_t next_start = tile_start + S::kBytes;
+      if (t + 1 < S::kTiles && next_start < vend) {
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+          pre[c] = load_chunk(vbase, next_start + (uint64_t)(c * kThreads + tid) * kChunk, align,
+                              vend, P.delim.byte);
       }
       if (tid == 0 && t == 0) sm.prev_nd = prev_nondelim(vbase, tile_start, align, P.delim);
       __syncthreads();
@@ -552,9 +566,12 @@ __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
       // global memory, which returns a delimiter past the end of the text.
       const bool straddle = (sm.nd[S::kChunks - 1] >> 15) & 1u;
       const LdsSrc lsrc{sm.text + S::kPadFront, tile_start, sm.delim_lut};
-      for (uint32_t j = tid; j < ntok; j += kThreads) {
+      // tokens of this tile that fit the caller's capacity
+      const uint32_t nfit = next_idx >= job.capacity ? 0u
+                            : (job.capacity - next_idx < ntok ? (uint32_t)(job.capacity - next_idx)
+                                                              : ntok);
+      for (uint32_t j = tid; j < nfit; j += kThreads) {
         const uint64_t idx = next_idx + j;
-        if (idx >= job.capacity) break;
         const uint32_t s = sm.starts[j];
         const uint64_t vpos = tile_start + s;  // virtual
         const uint64_t pos = vpos - align;     // offset in the text
