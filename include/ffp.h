@@ -92,9 +92,10 @@ typedef struct ffp_ctx ffp_ctx;
  * exponent marker must be followed by digits).
  * ------------------------------------------------------------------------- */
 
-/* Create a context on HIP device `hip_device`.  The context owns the
- * power-of-five table (10,416 bytes, Appendix B), the tile-scan state, the
- * fallback queue and timing events.  Returns FFP_E_ARG for a bad option set,
+/* Create a context on HIP device `hip_device`.  The context owns the device
+ * scratch (per-block token counts, the fallback queue, the job table of
+ * batched calls), its launch schedule and timing events; the 10,416-byte
+ * power-of-five table (Appendix B) lives in the library's device image.  Returns FFP_E_ARG for a bad option set,
  * FFP_E_HIP / FFP_E_NOMEM on runtime failures.  *out is NULL on failure. */
 int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out);
 
@@ -153,6 +154,70 @@ int64_t ffp_parse_f32_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
  * caller has synchronised its stream: FFP_SUCCESS, FFP_E_QUEUE or
  * FFP_E_INTERNAL.  Blocks on the context's own copy stream. */
 int ffp_last_device_error(ffp_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Batched parse: many independent buffers in one launch sequence.
+ *
+ * d_jobs is a device array of njobs (1 <= njobs <= 65535) ffp_job records.
+ * The kernels read text, nbytes, values, status, capacity and dtype from it
+ * and write count and err back into it; the caller may rewrite the records
+ * on the device between calls (this is what a captured graph replays).
+ * Every job is parsed exactly as ffp_parse_f64 / ffp_parse_f32 would parse
+ * it alone; all blocks of all jobs share one persistent launch of each
+ * kernel.  max_total_bytes bounds the sum of nbytes over the jobs (it sizes
+ * the scratch); if the jobs exceed it, every job gets err = FFP_E_CAPACITY
+ * and count = 0.  Returns FFP_E_ARG for bad arguments, FFP_E_NOMEM, FFP_E_HIP.
+ * ------------------------------------------------------------------------- */
+#define FFP_DTYPE_F64 0
+#define FFP_DTYPE_F32 1
+
+typedef struct ffp_job {
+    const uint8_t* text;  /* device text of this job (any alignment) */
+    uint64_t nbytes;
+    void* values;         /* device: capacity doubles or floats (dtype) */
+    uint8_t* status;      /* device: capacity bytes */
+    uint64_t capacity;
+    uint64_t count;       /* out: true number of tokens */
+    int32_t dtype;        /* FFP_DTYPE_F64 or FFP_DTYPE_F32 */
+    int32_t err;          /* out: FFP_SUCCESS, FFP_E_CAPACITY (count >
+                             capacity, or max_total_bytes exceeded) or
+                             FFP_E_ARG (unknown dtype) */
+} ffp_job;
+
+int ffp_parse_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
+                    void* stream);
+
+/* A batched parse captured once into a HIP graph and replayed: the graph
+ * holds the fixed d_jobs pointer, njobs and the scratch sized for
+ * max_total_bytes; the records behind d_jobs may change between launches.
+ * The context must outlive the graph and must not run other calls
+ * concurrently with a launch. */
+typedef struct ffp_graph ffp_graph;
+int ffp_batch_graph_create(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs,
+                           uint64_t max_total_bytes, ffp_graph** out);
+int ffp_batch_graph_launch(ffp_graph* g, void* stream);
+void ffp_batch_graph_destroy(ffp_graph* g);
+
+/* Launch schedule of the parse kernel: tile bytes per workgroup step
+ * (4096 * tile_k, tile_k in {1, 2, 4}) and resident workgroups per CU
+ * (1 .. the occupancy limit; 0 = the limit). */
+typedef struct ffp_tuning {
+    int32_t tile_k;
+    int32_t blocks_per_cu;
+    int32_t reserved[2];
+} ffp_tuning;
+
+int ffp_get_tuning(ffp_ctx* ctx, ffp_tuning* out);
+int ffp_set_tuning(ffp_ctx* ctx, const ffp_tuning* t);
+
+/* Autotuner: runs the given batch (it must be valid input; its outputs are
+ * overwritten) under every candidate schedule, times the parse kernel with
+ * HIP events, keeps the fastest in the context and returns it.  With the
+ * environment variable FFP_TUNE_CACHE naming a file, results are cached
+ * there as JSON keyed by GPU architecture, job count and byte-size bucket,
+ * and a cached entry is used without measuring.  Synchronises the stream. */
+int ffp_autotune_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
+                       void* stream, ffp_tuning* out);
 
 /* ---------------------------------------------------------------------------
  * Timing of the dominant kernel.  When enabled, each parse call records HIP

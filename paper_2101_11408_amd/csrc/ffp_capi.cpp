@@ -1,11 +1,15 @@
-// C-ABI of the parsing library: context, scratch, argument checks and the
-// launch sequence init -> parse -> fallback on the caller's stream.
+// C-ABI of the parsing library: contexts, scratch, argument checks, the
+// stream-ordered launch sequences (plain and batched), captured graphs and
+// the autotuner.
 #include <hip/hip_runtime.h>
 
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <new>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -23,14 +27,18 @@ struct ffp_ctx {
   DelimSet delim{};
   uint32_t flags = 0;
   int num_cus = 0;
+  std::string arch;
   int tile_k = 4;
-  int blocks_per_cu = 1;
+  int blocks_per_cu = 1;        // chosen schedule
+  int max_bpc[5] = {0, 0, 0, 0, 0};  // occupancy limit per tile_k
   int fb_grid = 0;
 
   uint64_t* d_block_sum = nullptr;  // per-block counts, then their prefix
   uint64_t block_cap = 0;
   QueueEntry* d_queue = nullptr;
   uint64_t queue_cap = 0;
+  JobDesc* d_jobs = nullptr;  // internal job table of batched calls
+  uint64_t jobs_cap = 0;
   DeviceState* d_state = nullptr;
 
   bool timing = false;
@@ -41,7 +49,16 @@ struct ffp_ctx {
   bool counters = false;
 };
 
+struct ffp_graph {
+  ffp_ctx* own = nullptr;  // private context: the graph holds its scratch
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 namespace {
+
+constexpr uint32_t kMaxJobs = 65535;  // job ids travel in 16 bits
+constexpr uint64_t kMaxBatchBytes = 1ull << 52;
 
 // Keeps the caller's current device across a call.
 struct DeviceGuard {
@@ -60,34 +77,48 @@ bool is_grammar_byte(int c) {
   return (c >= '0' && c <= '9') || c == '.' || c == 'e' || c == 'E' || c == '+' || c == '-';
 }
 
-// Grow the scratch for buffers of up to nbytes.  Old buffers may still be in
-// use by queued work, so the device is drained before anything is freed.
-int grow(ffp_ctx* ctx, uint64_t nbytes) {
-  const uint64_t blocks = (nbytes + 15 + ffp::kBlockBytes - 1) / ffp::kBlockBytes + 1;
-  // A token that reaches the fallback through the w / w+1 test has more than
-  // 19 significant digits, hence at least 20 bytes plus a delimiter (except
-  // the last token): (nbytes + 1) / 21 bounds their number.  The reserve
-  // covers the inconclusive-product case of Algorithm 1.
-  const uint64_t q = (nbytes + 1) / 21 + ffp::kAbortReserve;
-  if ((blocks > ctx->block_cap || q > ctx->queue_cap) && hipDeviceSynchronize() != hipSuccess)
-    return FFP_E_HIP;
-  if (blocks > ctx->block_cap) {
-    if (ctx->d_block_sum) (void)hipFree(ctx->d_block_sum);
-    ctx->d_block_sum = nullptr;
-    ctx->block_cap = 0;
-    if (hipMalloc(&ctx->d_block_sum, blocks * sizeof(uint64_t)) != hipSuccess) return FFP_E_NOMEM;
-    ctx->block_cap = blocks;
-  }
-  if (q > ctx->queue_cap) {
-    if (ctx->d_queue) (void)hipFree(ctx->d_queue);
-    ctx->d_queue = nullptr;
-    ctx->queue_cap = 0;
-    if (hipMalloc(&ctx->d_queue, q * sizeof(QueueEntry)) != hipSuccess) return FFP_E_NOMEM;
-    ctx->queue_cap = q;
-  }
+template <class T>
+int grow_array(T** p, uint64_t* cap, uint64_t need) {
+  if (need <= *cap) return FFP_SUCCESS;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  if (hipMalloc(p, need * sizeof(T)) != hipSuccess) return FFP_E_NOMEM;
+  *cap = need;
   return FFP_SUCCESS;
 }
 
+// Grow the scratch for up to `bytes` of text spread over `njobs` jobs.  Old
+// buffers may still be in use by queued work, so the device is drained before
+// anything is freed.
+int grow(ffp_ctx* ctx, uint64_t bytes, uint64_t njobs) {
+  // every job may start 15 bytes into its first block and end in a partial
+  // block; one more entry holds the grand total
+  const uint64_t blocks = (bytes + 15 * njobs) / ffp::kBlockBytes + 2 * njobs + 1;
+  // A token that reaches the fallback through the w / w+1 test has more than
+  // 19 significant digits, hence at least 20 bytes plus a delimiter (except
+  // the last token of a job): (bytes + njobs) / 21 bounds their number.  The
+  // reserve covers the inconclusive-product case of Algorithm 1.
+  const uint64_t q = (bytes + njobs) / 21 + ffp::kAbortReserve;
+  const bool batch = njobs > 1;
+  if (blocks > ctx->block_cap || q > ctx->queue_cap || (batch && njobs > ctx->jobs_cap)) {
+    if (hipDeviceSynchronize() != hipSuccess) return FFP_E_HIP;
+  }
+  int rc = grow_array(&ctx->d_block_sum, &ctx->block_cap, blocks);
+  if (rc == FFP_SUCCESS) rc = grow_array(&ctx->d_queue, &ctx->queue_cap, q);
+  if (rc == FFP_SUCCESS && batch) rc = grow_array(&ctx->d_jobs, &ctx->jobs_cap, njobs);
+  return rc;
+}
+
+int parse_grid(const ffp_ctx* ctx) {
+  int bpc = ctx->blocks_per_cu;
+  const int lim = ctx->max_bpc[ctx->tile_k];
+  if (bpc < 1 || bpc > lim) bpc = lim;
+  return ctx->num_cus * (bpc < 1 ? 1 : bpc);
+}
+
+// count -> scan -> parse -> fallback for a job set whose block count is
+// `nblocks` (plain calls) or on the device (batched calls, nblocks = ~0).
 int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, uint64_t nblocks, hipStream_t s) {
   ffp::ScanParams sp{};
   sp.js = js;
@@ -114,7 +145,7 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, uint64_t nblocks, hipStream
   P.delim = ctx->delim;
   P.flags = ctx->flags;
   P.count_paths = ctx->counters ? 1u : 0u;
-  uint64_t grid = (uint64_t)ctx->num_cus * (uint64_t)ctx->blocks_per_cu;
+  uint64_t grid = (uint64_t)parse_grid(ctx);
   if (grid > nblocks) grid = nblocks;
 
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
@@ -153,7 +184,7 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   if (nbytes > 0 && !d_text) return FFP_E_ARG;
   if (capacity > 0 && (!d_values || !d_status)) return FFP_E_ARG;
   DeviceGuard g(ctx->device);
-  int rc = grow(ctx, nbytes);
+  int rc = grow(ctx, nbytes, 1);
   if (rc != FFP_SUCCESS) return rc;
 
   JobDesc job{};
@@ -163,6 +194,7 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   job.status = d_status;
   job.capacity = capacity;
   job.count_out = d_count;
+  job.err_out = nullptr;
   job.block_begin = 0;
   job.dtype = dtype;
   job.job_id = 0;
@@ -179,6 +211,32 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   return launch_jobs(ctx, js, nblocks, (hipStream_t)stream);
 }
 
+int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
+                 hipStream_t s) {
+  if (!ctx || !d_jobs || njobs == 0 || njobs > kMaxJobs) return FFP_E_ARG;
+  if (max_total_bytes >= kMaxBatchBytes) return FFP_E_ARG;
+  DeviceGuard g(ctx->device);
+  // at least two jobs' worth of job table, so that grow() sizes it
+  int rc = grow(ctx, max_total_bytes, njobs < 2 ? 2 : njobs);
+  if (rc != FFP_SUCCESS) return rc;
+  ffp::PrepParams pp{};
+  pp.user = reinterpret_cast<ffp::UserJob*>(d_jobs);
+  pp.njobs = njobs;
+  pp.jobs = ctx->d_jobs;
+  pp.st = ctx->d_state;
+  pp.block_cap = ctx->block_cap - 1;
+  pp.max_bytes = max_total_bytes;
+  if (ffp::launch_prep(pp, s) != hipSuccess) return FFP_E_HIP;
+  ffp::JobSet js{};
+  js.jobs = ctx->d_jobs;
+  js.njobs = njobs;
+  js.total_blocks = 0;
+  js.total_blocks_dev = reinterpret_cast<const uint64_t*>(&ctx->d_state->total_blocks);
+  // grids are sized for the largest batch the scratch allows; kernels read
+  // the true block count on the device
+  return launch_jobs(ctx, js, ctx->block_cap - 1, s);
+}
+
 int64_t finish_sync(ffp_ctx* ctx, int rc, uint64_t capacity, uint64_t* d_count, void* stream) {
   if (rc != FFP_SUCCESS) return rc;
   DeviceGuard g(ctx->device);
@@ -192,6 +250,56 @@ int64_t finish_sync(ffp_ctx* ctx, int rc, uint64_t capacity, uint64_t* d_count, 
   if (err & ffp::kDevQueue) return FFP_E_QUEUE;
   if (count > capacity) return FFP_E_CAPACITY;
   return (int64_t)count;
+}
+
+// --- autotuner cache: a flat JSON object {"key": [tile_k, blocks_per_cu]} --
+std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
+  std::map<std::string, std::pair<int, int>> out;
+  FILE* f = fopen(path, "r");
+  if (!f) return out;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+  fclose(f);
+  size_t i = 0;
+  while ((i = text.find('"', i)) != std::string::npos) {
+    const size_t j = text.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = text.substr(i + 1, j - i - 1);
+    int a = 0, b = 0;
+    const size_t lb = text.find('[', j);
+    if (lb == std::string::npos || sscanf(text.c_str() + lb, "[%d,%d]", &a, &b) != 2) break;
+    out[key] = {a, b};
+    i = text.find(']', lb);
+    if (i == std::string::npos) break;
+  }
+  return out;
+}
+
+void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t k = 0;
+  for (const auto& e : m)
+    fprintf(f, "  \"%s\": [%d, %d]%s\n", e.first.c_str(), e.second.first, e.second.second,
+            ++k < m.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  rename(tmp.c_str(), path);
+}
+
+std::string tune_key(const ffp_ctx* ctx, uint32_t njobs, uint64_t bytes) {
+  int lg = 0;
+  while ((1ull << (lg + 1)) <= bytes) ++lg;
+  int lj = 0;
+  while ((1u << (lj + 1)) <= njobs) ++lj;
+  char key[160];
+  snprintf(key, sizeof key, "%s|cus=%d|jobs=2^%d|bytes=2^%d|single=%u", ctx->arch.c_str(),
+           ctx->num_cus, lj, lg, ctx->delim.single);
+  return key;
 }
 
 }  // namespace
@@ -243,10 +351,6 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   ctx->delim.single = members == 1 ? 1u : 0u;
   ctx->delim.byte = (uint32_t)first;
   ctx->flags = o.flags;
-  if (const char* k = getenv("FFP_TILE_K")) {
-    const int v = atoi(k);
-    if (v == 1 || v == 2 || v == 4) ctx->tile_k = v;
-  }
 
   DeviceGuard g(hip_device);
   hipDeviceProp_t prop;
@@ -255,16 +359,24 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
     return FFP_E_HIP;
   }
   ctx->num_cus = prop.multiProcessorCount;
-  if (ffp::parse_occupancy(ctx->tile_k, ctx->delim.single != 0, &ctx->blocks_per_cu) != hipSuccess ||
-      ctx->blocks_per_cu < 1)
-    ctx->blocks_per_cu = 1;
+  ctx->arch = prop.gcnArchName;
+  for (int k : {1, 2, 4}) {
+    int b = 0;
+    if (ffp::parse_occupancy(k, ctx->delim.single != 0, &b) != hipSuccess || b < 1) b = 1;
+    ctx->max_bpc[k] = b;
+  }
+  if (const char* k = getenv("FFP_TILE_K")) {
+    const int v = atoi(k);
+    if (v == 1 || v == 2 || v == 4) ctx->tile_k = v;
+  }
+  ctx->blocks_per_cu = ctx->max_bpc[ctx->tile_k];
   ctx->fb_grid = ctx->num_cus * 2;
   if (hipMalloc(&ctx->d_state, sizeof(DeviceState)) != hipSuccess) {
     delete ctx;
     return FFP_E_NOMEM;
   }
   if (hipMemset(ctx->d_state, 0, sizeof(DeviceState)) != hipSuccess ||
-      grow(ctx, 1 << 20) != FFP_SUCCESS) {
+      grow(ctx, 1 << 20, 1) != FFP_SUCCESS) {
     ffp_destroy(ctx);
     return FFP_E_NOMEM;
   }
@@ -287,6 +399,7 @@ void ffp_destroy(ffp_ctx* ctx) {
     }
     if (ctx->d_block_sum) (void)hipFree(ctx->d_block_sum);
     if (ctx->d_queue) (void)hipFree(ctx->d_queue);
+    if (ctx->d_jobs) (void)hipFree(ctx->d_jobs);
     if (ctx->d_state) (void)hipFree(ctx->d_state);
   }
   delete ctx;
@@ -295,7 +408,7 @@ void ffp_destroy(ffp_ctx* ctx) {
 int ffp_reserve(ffp_ctx* ctx, uint64_t max_nbytes) {
   if (!ctx || max_nbytes >= ffp::kMaxBytes) return FFP_E_ARG;
   DeviceGuard g(ctx->device);
-  return grow(ctx, max_nbytes);
+  return grow(ctx, max_nbytes, 1);
 }
 
 int ffp_parse_f64(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes, double* d_values,
@@ -324,6 +437,153 @@ int64_t ffp_parse_f32_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
   const int rc = parse_common(ctx, ffp::kF32, d_text, nbytes, d_values, d_status, capacity,
                               d_count, stream);
   return finish_sync(ctx, rc, capacity, d_count, stream);
+}
+
+int ffp_parse_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
+                    void* stream) {
+  return batch_common(ctx, d_jobs, njobs, max_total_bytes, (hipStream_t)stream);
+}
+
+int ffp_batch_graph_create(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs,
+                           uint64_t max_total_bytes, ffp_graph** out) {
+  if (!ctx || !out) return FFP_E_ARG;
+  *out = nullptr;
+  if (!d_jobs || njobs == 0 || njobs > kMaxJobs || max_total_bytes >= kMaxBatchBytes)
+    return FFP_E_ARG;
+  ffp_graph* gr = new (std::nothrow) ffp_graph();
+  if (!gr) return FFP_E_NOMEM;
+  // a private context with the same options and schedule
+  ffp_options o{};
+  for (int i = 0; i < 4; ++i) o.delim_set[i] = ctx->delim.bits[i];
+  o.flags = ctx->flags;
+  int rc = ffp_create(ctx->device, &o, &gr->own);
+  if (rc != FFP_SUCCESS) {
+    delete gr;
+    return rc;
+  }
+  gr->own->tile_k = ctx->tile_k;
+  gr->own->blocks_per_cu = ctx->blocks_per_cu;
+  DeviceGuard g(ctx->device);
+  rc = grow(gr->own, max_total_bytes, njobs < 2 ? 2 : njobs);
+  hipStream_t cs = nullptr;
+  if (rc == FFP_SUCCESS && hipStreamCreate(&cs) != hipSuccess) rc = FFP_E_HIP;
+  if (rc == FFP_SUCCESS) {
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = FFP_E_HIP;
+    } else {
+      const int lrc = batch_common(gr->own, d_jobs, njobs, max_total_bytes, cs);
+      const hipError_t ec = hipStreamEndCapture(cs, &gr->graph);
+      if (lrc != FFP_SUCCESS) rc = lrc;
+      else if (ec != hipSuccess) rc = FFP_E_HIP;
+      else if (hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = FFP_E_HIP;
+    }
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  if (rc != FFP_SUCCESS) {
+    ffp_batch_graph_destroy(gr);
+    return rc;
+  }
+  *out = gr;
+  return FFP_SUCCESS;
+}
+
+int ffp_batch_graph_launch(ffp_graph* gr, void* stream) {
+  if (!gr || !gr->exec) return FFP_E_ARG;
+  DeviceGuard g(gr->own->device);
+  return hipGraphLaunch(gr->exec, (hipStream_t)stream) == hipSuccess ? FFP_SUCCESS : FFP_E_HIP;
+}
+
+void ffp_batch_graph_destroy(ffp_graph* gr) {
+  if (!gr) return;
+  if (gr->own) {
+    DeviceGuard g(gr->own->device);
+    (void)hipDeviceSynchronize();
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    ffp_destroy(gr->own);
+  }
+  delete gr;
+}
+
+int ffp_get_tuning(ffp_ctx* ctx, ffp_tuning* out) {
+  if (!ctx || !out) return FFP_E_ARG;
+  memset(out, 0, sizeof *out);
+  out->tile_k = ctx->tile_k;
+  out->blocks_per_cu = ctx->blocks_per_cu;
+  return FFP_SUCCESS;
+}
+
+int ffp_set_tuning(ffp_ctx* ctx, const ffp_tuning* t) {
+  if (!ctx || !t) return FFP_E_ARG;
+  if (t->tile_k != 1 && t->tile_k != 2 && t->tile_k != 4) return FFP_E_ARG;
+  if (t->blocks_per_cu < 0 || t->blocks_per_cu > ctx->max_bpc[t->tile_k]) return FFP_E_ARG;
+  ctx->tile_k = t->tile_k;
+  ctx->blocks_per_cu = t->blocks_per_cu == 0 ? ctx->max_bpc[t->tile_k] : t->blocks_per_cu;
+  return FFP_SUCCESS;
+}
+
+int ffp_autotune_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
+                       void* stream, ffp_tuning* out) {
+  if (!ctx || !d_jobs || !out) return FFP_E_ARG;
+  DeviceGuard g(ctx->device);
+  const char* cache_path = getenv("FFP_TUNE_CACHE");
+  const std::string key = tune_key(ctx, njobs, max_total_bytes);
+  std::map<std::string, std::pair<int, int>> cache;
+  if (cache_path) {
+    cache = read_cache(cache_path);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      ffp_tuning t{};
+      t.tile_k = it->second.first;
+      t.blocks_per_cu = it->second.second;
+      if (ffp_set_tuning(ctx, &t) == FFP_SUCCESS) return ffp_get_tuning(ctx, out);
+    }
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  const bool was_timing = ctx->timing;
+  // drop pending measurements of the caller
+  double ms0 = 0;
+  uint64_t n0 = 0;
+  if (was_timing && ffp_timing_read(ctx, &ms0, &n0) != FFP_SUCCESS) return FFP_E_HIP;
+  ctx->timing = true;
+  double best = 1e30;
+  int best_k = ctx->tile_k, best_b = ctx->blocks_per_cu;
+  for (int k : {1, 2, 4}) {
+    std::vector<int> cands;
+    for (int b = ctx->max_bpc[k]; b >= 1; b = (b > 2 ? b - 1 : b - 1)) cands.push_back(b);
+    for (int b : cands) {
+      ctx->tile_k = k;
+      ctx->blocks_per_cu = b;
+      int rc = batch_common(ctx, d_jobs, njobs, max_total_bytes, s);  // warm-up
+      double ms = 0;
+      uint64_t n = 0;
+      if (rc == FFP_SUCCESS) rc = ffp_timing_read(ctx, &ms, &n);
+      double t_best = 1e30;
+      for (int rep = 0; rep < 3 && rc == FFP_SUCCESS; ++rep) {
+        rc = batch_common(ctx, d_jobs, njobs, max_total_bytes, s);
+        if (rc == FFP_SUCCESS) rc = ffp_timing_read(ctx, &ms, &n);
+        if (rc == FFP_SUCCESS && n > 0 && ms < t_best) t_best = ms;
+      }
+      if (rc != FFP_SUCCESS) {
+        ctx->timing = was_timing;
+        return rc;
+      }
+      if (t_best < best) {
+        best = t_best;
+        best_k = k;
+        best_b = b;
+      }
+    }
+  }
+  ctx->timing = was_timing;
+  ctx->tile_k = best_k;
+  ctx->blocks_per_cu = best_b;
+  if (cache_path) {
+    cache[key] = {best_k, best_b};
+    write_cache(cache_path, cache);
+  }
+  return ffp_get_tuning(ctx, out);
 }
 
 int ffp_last_device_error(ffp_ctx* ctx) {

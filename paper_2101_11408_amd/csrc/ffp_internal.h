@@ -63,6 +63,7 @@ struct JobDesc {
   uint8_t* status;
   uint64_t capacity;
   uint64_t* count_out;
+  int32_t* err_out;      // batched calls: the job record's err field
   uint64_t block_begin;  // index of this job's first block in the block space
   uint32_t dtype;
   uint32_t job_id;
@@ -76,6 +77,7 @@ struct QueueEntry {
 struct DeviceState {
   unsigned int error;
   unsigned long long queue_tail;
+  unsigned long long total_blocks;  // batched calls: blocks of all jobs
   unsigned long long counters[8];
 };
 
@@ -94,6 +96,28 @@ struct JobSet {
   uint32_t pad;
   uint64_t total_blocks;             // plain calls
   const uint64_t* total_blocks_dev;  // batched calls
+};
+
+// Public job record (include/ffp.h, struct ffp_job), as the kernels see it.
+struct UserJob {
+  const uint8_t* text;
+  uint64_t nbytes;
+  void* values;
+  uint8_t* status;
+  uint64_t capacity;
+  uint64_t count;
+  int32_t dtype;
+  int32_t err;
+};
+
+struct PrepParams {
+  UserJob* user;
+  uint32_t njobs;
+  uint32_t pad;
+  JobDesc* jobs;
+  DeviceState* st;
+  uint64_t block_cap;  // blocks the scratch can hold
+  uint64_t max_bytes;  // the caller's bound on the sum of nbytes
 };
 
 struct CountParams {

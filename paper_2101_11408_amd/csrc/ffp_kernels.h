@@ -12,6 +12,7 @@ int parse_tile_bytes(int k);
 // Resident workgroups per CU of the parse kernel.
 hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu);
 
+hipError_t launch_prep(const PrepParams& P, hipStream_t s);
 hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipStream_t s);
 hipError_t launch_scan(const ScanParams& P, hipStream_t s);
 hipError_t launch_parse(int k, bool single_delim, const ParseParams& P, int grid, hipStream_t s);

@@ -73,6 +73,10 @@ __device__ __forceinline__ T block_excl_scan(T v, T& total, T* s_tmp) {
   return before + x - v;
 }
 
+// Public error codes written into job records (include/ffp.h).
+constexpr int32_t kErrArg = -1;       // FFP_E_ARG
+constexpr int32_t kErrCapacity = -2;  // FFP_E_CAPACITY
+
 // Job that owns global block b.
 __device__ __forceinline__ JobDesc job_of_block(const JobSet& js, uint64_t b) {
   if (!js.jobs) return js.single;
@@ -265,7 +269,73 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
   for (uint32_t j = tid; j < nj; j += kScanThreads) {
     const JobDesc job = P.js.jobs ? P.js.jobs[j] : P.js.single;
     const uint64_t b0 = job.block_begin, b1 = b0 + job_blocks(job);
-    *job.count_out = P.block_sum[b1] - P.block_sum[b0];
+    const uint64_t count = P.block_sum[b1] - P.block_sum[b0];
+    *job.count_out = count;
+    if (job.err_out && count > job.capacity) *job.err_out = kErrCapacity;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_prep (batched calls): the internal job table, whose block offsets are an
+// exclusive scan of the jobs' block counts, zeroed counts and errors, and the
+// total block count.  A batch beyond the scratch (more bytes than the
+// caller's bound) is turned into empty jobs that report FFP_E_CAPACITY.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kScanThreads) void k_prep(PrepParams P) {
+  __shared__ uint64_t s_scan[kScanThreads / kWave];
+  __shared__ uint64_t s_carry_blocks, s_carry_bytes;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_carry_blocks = 0;
+    s_carry_bytes = 0;
+  }
+  for (uint32_t base = 0; base < P.njobs; base += kScanThreads) {
+    const uint32_t j = base + tid;
+    UserJob u{};
+    if (j < P.njobs) u = P.user[j];
+    const bool ok = j < P.njobs && (u.dtype == kF64 || u.dtype == kF32) &&
+                    u.nbytes < kMaxBytes && (u.nbytes == 0 || u.text != nullptr) &&
+                    (u.capacity == 0 || (u.values != nullptr && u.status != nullptr));
+    const uint64_t nb = ok ? u.nbytes : 0;
+    const uint64_t vend = nb ? nb + ((uint64_t)(uintptr_t)u.text & 15u) : 0;
+    const uint64_t blocks = (vend + kBlockBytes - 1) / kBlockBytes;
+    __syncthreads();  // carries of the previous round are final
+    const uint64_t cb = s_carry_blocks, cbytes = s_carry_bytes;
+    uint64_t tot_blocks, tot_bytes;
+    const uint64_t ex_blocks = block_excl_scan<kScanThreads>(blocks, tot_blocks, s_scan);
+    __syncthreads();
+    (void)block_excl_scan<kScanThreads>(nb, tot_bytes, s_scan);
+    if (j < P.njobs) {
+      JobDesc d{};
+      d.text = u.text;
+      d.nbytes = nb;
+      d.values = u.values;
+      d.status = u.status;
+      d.capacity = ok ? u.capacity : 0;
+      d.count_out = &P.user[j].count;
+      d.err_out = &P.user[j].err;
+      d.block_begin = cb + ex_blocks;
+      d.dtype = ok ? (uint32_t)u.dtype : kF64;
+      d.job_id = j;
+      P.jobs[j] = d;
+      P.user[j].count = 0;
+      P.user[j].err = ok ? 0 : kErrArg;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s_carry_blocks = cb + tot_blocks;
+      s_carry_bytes = cbytes + tot_bytes;
+    }
+  }
+  __syncthreads();
+  const bool over = s_carry_blocks > P.block_cap || s_carry_bytes > P.max_bytes;
+  if (tid == 0) P.st->total_blocks = over ? 0 : s_carry_blocks;
+  if (over) {
+    for (uint32_t j = tid; j < P.njobs; j += kScanThreads) {
+      P.jobs[j].nbytes = 0;
+      P.jobs[j].block_begin = 0;
+      P.user[j].err = kErrCapacity;
+    }
   }
 }
 
@@ -679,6 +749,11 @@ hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipSt
     hipLaunchKernelGGL((k_count<true>), dim3(grid), dim3(kThreads), 0, s, P);
   else
     hipLaunchKernelGGL((k_count<false>), dim3(grid), dim3(kThreads), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(const PrepParams& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3(1), dim3(kScanThreads), 0, s, P);
   return hipGetLastError();
 }
 

@@ -38,6 +38,18 @@ class ffp_options(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class ffp_job(ctypes.Structure):
+    _fields_ = [("text", ctypes.c_void_p), ("nbytes", ctypes.c_uint64),
+                ("values", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("capacity", ctypes.c_uint64), ("count", ctypes.c_uint64),
+                ("dtype", ctypes.c_int32), ("err", ctypes.c_int32)]
+
+
+class ffp_tuning(ctypes.Structure):
+    _fields_ = [("tile_k", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
 _c = ctypes
 _P = _c.c_void_p
 _U64 = _c.c_uint64
@@ -59,6 +71,13 @@ _SIGNATURES = {
     "ffp_timing_read": (_INT, [_P, _c.POINTER(_c.c_double), _c.POINTER(_U64)]),
     "ffp_counters_enable": (_INT, [_P, _INT]),
     "ffp_counters_read": (_INT, [_P, _U64 * 6]),
+    "ffp_parse_batch": (_INT, [_P, _P, _c.c_uint32, _U64, _P]),
+    "ffp_batch_graph_create": (_INT, [_P, _P, _c.c_uint32, _U64, _c.POINTER(_P)]),
+    "ffp_batch_graph_launch": (_INT, [_P, _P]),
+    "ffp_batch_graph_destroy": (None, [_P]),
+    "ffp_get_tuning": (_INT, [_P, _c.POINTER(ffp_tuning)]),
+    "ffp_set_tuning": (_INT, [_P, _c.POINTER(ffp_tuning)]),
+    "ffp_autotune_batch": (_INT, [_P, _P, _c.c_uint32, _U64, _P, _c.POINTER(ffp_tuning)]),
 }
 
 _lib = None
@@ -215,6 +234,29 @@ class Context:
         fn = ffp_parse_f32 if f32 else ffp_parse_f64
         return check(fn(*args), "parse")
 
+    # -- batched calls -------------------------------------------------
+    def parse_batch(self, d_jobs, njobs, max_total_bytes, stream=None):
+        """d_jobs: device tensor holding njobs ffp_job records (JobTable.dev)."""
+        return check(load().ffp_parse_batch(self.handle, d_jobs.data_ptr(), njobs,
+                                            max_total_bytes, _stream_handle(stream)),
+                     "ffp_parse_batch")
+
+    def get_tuning(self):
+        t = ffp_tuning()
+        check(load().ffp_get_tuning(self.handle, ctypes.byref(t)))
+        return t.tile_k, t.blocks_per_cu
+
+    def set_tuning(self, tile_k, blocks_per_cu=0):
+        t = ffp_tuning(tile_k, blocks_per_cu)
+        check(load().ffp_set_tuning(self.handle, ctypes.byref(t)), "ffp_set_tuning")
+
+    def autotune_batch(self, d_jobs, njobs, max_total_bytes, stream=None):
+        t = ffp_tuning()
+        check(load().ffp_autotune_batch(self.handle, d_jobs.data_ptr(), njobs, max_total_bytes,
+                                        _stream_handle(stream), ctypes.byref(t)),
+              "ffp_autotune_batch")
+        return t.tile_k, t.blocks_per_cu
+
     def parse(self, text, dtype=None, capacity=None, stream=None):
         """Parse a device uint8 tensor; returns (values, status) of the exact
         token count (a second pass with a larger capacity if needed)."""
@@ -232,3 +274,66 @@ class Context:
             return self.parse(text, dtype, capacity=total, stream=stream)
         check(n, "parse")
         return values[:n], status[:n]
+
+
+# ---------------------------------------------------------------------------
+# batched calls: job tables and captured graphs
+# ---------------------------------------------------------------------------
+
+class JobTable:
+    """ffp_job records for a list of (text, values, status) device tensors,
+    kept both on the host (ctypes array) and on the device (uint8 tensor)."""
+
+    def __init__(self, texts, values, statuses, device):
+        import torch
+        n = len(texts)
+        self.n = n
+        self.host = (ffp_job * n)()
+        for i, (t, v, st) in enumerate(zip(texts, values, statuses)):
+            self.host[i].text = t.data_ptr() if t.numel() else 0
+            self.host[i].nbytes = t.numel()
+            self.host[i].values = v.data_ptr()
+            self.host[i].status = st.data_ptr()
+            self.host[i].capacity = min(v.numel(), st.numel())
+            self.host[i].dtype = DTYPE_F32 if v.dtype == torch.float32 else DTYPE_F64
+            self.host[i].err = 0
+            self.host[i].count = 0
+        raw = bytes(self.host)
+        self.dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        self.total_bytes = sum(t.numel() for t in texts)
+
+    def upload(self):
+        import torch
+        raw = bytes(self.host)
+        self.dev.copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8))
+
+    def download(self):
+        raw = self.dev.cpu().numpy().tobytes()
+        ctypes.memmove(ctypes.addressof(self.host), raw, len(raw))
+        return [(self.host[i].count, self.host[i].err) for i in range(self.n)]
+
+
+class BatchGraph:
+    """A batched parse captured into a HIP graph (ffp_batch_graph_*)."""
+
+    def __init__(self, ctx, table, max_total_bytes):
+        out = _P()
+        check(load().ffp_batch_graph_create(ctx.handle, table.dev.data_ptr(), table.n,
+                                            max_total_bytes, ctypes.byref(out)),
+              "ffp_batch_graph_create")
+        self.handle = out
+
+    def launch(self, stream=None):
+        check(load().ffp_batch_graph_launch(self.handle, _stream_handle(stream)),
+              "ffp_batch_graph_launch")
+
+    def close(self):
+        if self.handle:
+            load().ffp_batch_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
