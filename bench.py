@@ -1,15 +1,24 @@
-"""Benchmark: exact decimal -> binary64 parsing on one MI355X.
+"""Benchmark: exact decimal -> binary64/binary32 parsing on one MI355X.
 
-Default workload: 10M numbers in one ~198 MB buffer (50% uniform [0,1)
-shortest digits, 25% coordinates with 6-15 fraction digits, 25% random
-finite bit patterns as %.17e), parsed to binary64 with the plain
-single-buffer entry point.  One step = one ffp_parse_f64 call (init, parse
-and fallback kernels) over the whole buffer, text already resident in HBM.
+Default workload (config2): 10M numbers in one ~198 MB buffer (50% uniform
+[0,1) shortest digits, 25% coordinates with 6-15 fraction digits, 25% random
+finite bit patterns as %.17e) parsed to binary64 by the plain single-buffer
+entry point.  One step = one ffp_parse_f64 call (count, scan, parse and
+fallback kernels) over the whole buffer, text already resident in HBM.
+
+Other workloads (--workload):
+  config1   100k uniform [0,1) shortest digits, one 1.93 MB buffer (latency)
+  config3   2M hard cases (long midpoints, subnormals, overflow ...), binary64
+  config4   4096 buffers, lognormal sizes (median 256 KiB, 1 KiB - 16 MiB),
+            mixed formats; plain (one call per buffer) vs batched vs graph
+  config4u  the same buffer sizes filled with config-1-format text (about
+            3 GB, far above the 256 MB Infinity Cache): the HBM target run
+  config5   served requests: see serve_bench.py
 
 Prints one JSON line.  `roofline` reports the parse kernel's algorithmic
-bytes (text read once + 8-byte value + 1-byte status per token) over its
-average duration measured with HIP events on the launch stream;
-`cpu_baseline` times the CPU oracle on a bounded sample of the same text.
+bytes (text read once + value + 1-byte status per token) over its average
+duration measured with HIP events on the launch stream; `cpu_baseline` times
+the CPU oracle on a bounded sample of the same text (config2 only).
 """
 
 import argparse
@@ -28,6 +37,10 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2101_11408_amd/csrc/ffp_kernels.hip",
                   "paper_2101_11408_amd/csrc/ffp_device.h",
                   "paper_2101_11408_amd/csrc/ffp_internal.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -67,7 +80,6 @@ def _oracle_slice(bounds):
 
 def cpu_baseline(buf: bytes, sample_tokens: int):
     global _SAMPLE
-    # the first sample_tokens tokens of the same buffer
     end = 0
     for _ in range(sample_tokens):
         nxt = buf.find(b"\n", end)
@@ -77,7 +89,6 @@ def cpu_baseline(buf: bytes, sample_tokens: int):
         end = nxt + 1
     _SAMPLE = buf[:end]
     cores = max(1, min(16, os.cpu_count() or 1))
-    # split at token boundaries
     step = max(1, end // (cores * 4))
     bounds, a = [], 0
     while a < end:
@@ -102,15 +113,197 @@ def cpu_baseline(buf: bytes, sample_tokens: int):
 
 
 # ---------------------------------------------------------------------------
-# GPU run
+# helpers
 # ---------------------------------------------------------------------------
+
+def roofline(alg_bytes, kern_ms, workload):
+    achieved = alg_bytes / (kern_ms / 1e3) / 1e9
+    return {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": load_traffic(workload),
+        "kernel": "k_parse",
+        "kernel_avg_ms": round(kern_ms, 4),
+        "algorithmic_bytes_per_launch": alg_bytes,
+    }
+
+
+def base_record(args, value, ms, workload, config, dtype="u64"):
+    return {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": dict(workload=workload, **config),
+    }
+
+
+def timed_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps if steps else 0.0
+
+
+# ---------------------------------------------------------------------------
+# single-buffer workloads
+# ---------------------------------------------------------------------------
+
+def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False):
+    import torch
+    from paper_2101_11408_amd import ffp
+    dev = torch.device("cuda", 0)
+    text = torch.frombuffer(bytearray(buf), dtype=torch.uint8).to(dev)
+    dt = torch.float64 if out_dtype == "f64" else torch.float32
+    values = torch.empty(ntok, dtype=dt, device=dev)
+    status = torch.empty(ntok, dtype=torch.uint8, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    ctx = ffp.Context(0)
+    ctx.reserve(len(buf))
+    stream = torch.cuda.current_stream()
+    n = ctx.parse_into(text, values, status, count, stream=stream, sync=True)
+    assert n == ntok, n
+    ms = timed_steps(torch, lambda: ctx.parse_into(text, values, status, count, stream=stream),
+                     0, args.warmup)
+    ctx.timing(True)
+    ctx.timing_read()
+    ms = timed_steps(torch, lambda: ctx.parse_into(text, values, status, count, stream=stream),
+                     args.steps, 0)
+    kern_ms, launches = ctx.timing_read()
+    ctx.timing(False)
+    assert launches == args.steps
+    assert ctx.last_device_error() == 0
+    assert int(count.item()) == ntok
+    kavg = kern_ms / launches
+    vbytes = 8 if out_dtype == "f64" else 4
+    alg = len(buf) + (vbytes + 1) * ntok
+    log("steps done: %.3f ms/step, parse kernel %.3f ms" % (ms, kavg))
+    rec = base_record(args, len(buf) / (ms / 1e3) / 1e9, ms, workload, {
+        "description": desc, "tokens": ntok, "bytes": len(buf),
+        "output": "binary64" if out_dtype == "f64" else "binary32",
+        "parallelism": "single GPU"})
+    rec["mfloats_per_s"] = round(ntok / (ms / 1e3) / 1e6, 1)
+    rec["roofline"] = roofline(alg, kavg, workload)
+    rec["cpu_baseline"] = cpu_baseline(buf, min(args.cpu_sample, ntok)) if cpu else None
+    ctx.close()
+    return rec
+
+
+# ---------------------------------------------------------------------------
+# batched workloads (config 4)
+# ---------------------------------------------------------------------------
+
+def run_batched(args, kind, workload):
+    import numpy as np
+    import torch
+    from gen import workloads as W
+    from paper_2101_11408_amd import ffp
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    sizes = W.config4_sizes(4, args.nbuf)
+    pool = W.token_pool(44, 2_000_000, "mixed" if kind == "mixed" else "uniform")
+    plan = W.slice_plan(np.random.default_rng(4), pool, sizes)
+    pool_dev = torch.frombuffer(bytearray(pool), dtype=torch.uint8).to(dev)
+    texts, values, statuses, counts = [], [], [], []
+    ntok_total = 0
+    for st, ln in plan:
+        t = torch.empty(ln, dtype=torch.uint8, device=dev)
+        t.copy_(pool_dev[st:st + ln])
+        cap = pool.count(b"\n", st, st + ln) + 1
+        ntok_total += cap
+        texts.append(t)
+        values.append(torch.empty(cap, dtype=torch.float64, device=dev))
+        statuses.append(torch.empty(cap, dtype=torch.uint8, device=dev))
+        counts.append(torch.zeros(1, dtype=torch.int64, device=dev))
+    del pool_dev
+    torch.cuda.synchronize()
+    total = int(sum(sizes))
+    log("%d buffers, %.1f MB, built in %.1f s" % (len(texts), total / 1e6, time.time() - t0))
+
+    ctx = ffp.Context(0)
+    table = ffp.JobTable(texts, values, statuses, dev)
+    stream = torch.cuda.current_stream()
+    tune = ctx.autotune_batch(table.dev, table.n, total)
+    log("autotuned schedule (tile_k, workgroups/CU):", tune)
+
+    # plain: one call per buffer, back to back on one stream
+    ctx.reserve(int(max(sizes)))
+
+    def plain_all():
+        for t, v, s, c in zip(texts, values, statuses, counts):
+            ctx.parse_into(t, v, s, c, stream=stream)
+    ms_plain = timed_steps(torch, plain_all, max(1, args.steps // 5), 1)
+
+    # batched (one call) with the parse kernel timed
+    ms_batch = timed_steps(torch, lambda: ctx.parse_batch(table.dev, table.n, total, stream),
+                           0, args.warmup)
+    ctx.timing(True)
+    ctx.timing_read()
+    ms_batch = timed_steps(torch, lambda: ctx.parse_batch(table.dev, table.n, total, stream),
+                           args.steps, 0)
+    kern_ms, launches = ctx.timing_read()
+    ctx.timing(False)
+    kavg = kern_ms / launches
+    res = table.download()
+    ntok = sum(c for c, e in res)
+    assert all(e == 0 for c, e in res), "job errors"
+
+    # captured graph replay
+    graph = ffp.BatchGraph(ctx, table, total)
+    ms_graph = timed_steps(torch, lambda: graph.launch(stream), args.steps, args.warmup)
+    res2 = table.download()
+    assert [c for c, e in res2] == [c for c, e in res] and all(e == 0 for c, e in res2)
+    graph.close()
+    assert ctx.last_device_error() == 0
+
+    alg = total + 9 * ntok
+    gbs = lambda ms: total / (ms / 1e3) / 1e9
+    log("plain %.3f ms, batched %.3f ms, graph %.3f ms, parse kernel %.3f ms"
+        % (ms_plain, ms_batch, ms_graph, kavg))
+    rec = base_record(args, gbs(ms_graph), ms_graph, workload, {
+        "description": "%d independent buffers, lognormal sizes (median 256 KiB, sigma 1.5, "
+                       "1 KiB - 16 MiB), %s text, binary64; value = one replay of the "
+                       "captured batched graph" % (len(texts),
+                                                   "mixed-format" if kind == "mixed"
+                                                   else "uniform [0,1) shortest-digit"),
+        "buffers": len(texts), "tokens": ntok, "bytes": total, "output": "binary64",
+        "parallelism": "single GPU", "schedule": {"tile_k": tune[0], "workgroups_per_cu": tune[1]}})
+    rec["mfloats_per_s"] = round(ntok / (ms_graph / 1e3) / 1e6, 1)
+    rec["compare"] = {
+        "plain_one_call_per_buffer": {"ms": round(ms_plain, 3), "GB/s": round(gbs(ms_plain), 1)},
+        "batched_call": {"ms": round(ms_batch, 3), "GB/s": round(gbs(ms_batch), 1)},
+        "batched_graph": {"ms": round(ms_graph, 3), "GB/s": round(gbs(ms_graph), 1)},
+    }
+    rec["roofline"] = roofline(alg, kavg, workload)
+    rec["cpu_baseline"] = None
+    ctx.close()
+    return rec
+
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--tokens", type=int, default=10_000_000)
+    ap.add_argument("--workload", default="config2",
+                    choices=["config1", "config2", "config3", "config4", "config4u"])
+    ap.add_argument("--tokens", type=int, default=None)
+    ap.add_argument("--nbuf", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     args = ap.parse_args()
@@ -121,99 +314,39 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
     from gen import workloads as W
-    from paper_2101_11408_amd import ffp
 
-    t0 = time.time()
-    buf = W.config2(n=args.tokens)
-    print("generated %d bytes in %.1f s" % (len(buf), time.time() - t0), file=sys.stderr,
-          flush=True)
-    ntok = args.tokens
-    dev = torch.device("cuda", 0)
-    text = torch.frombuffer(bytearray(buf), dtype=torch.uint8).to(dev)
-    values = torch.empty(ntok, dtype=torch.float64, device=dev)
-    status = torch.empty(ntok, dtype=torch.uint8, device=dev)
-    count = torch.zeros(1, dtype=torch.int64, device=dev)
-    ctx = ffp.Context(0)
-    ctx.reserve(len(buf))
-    stream = torch.cuda.current_stream()
-    n = ctx.parse_into(text, values, status, count, stream=stream, sync=True)
-    assert n == ntok, n
-
-    for _ in range(args.warmup):
-        ctx.parse_into(text, values, status, count, stream=stream)
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    ctx.timing_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.parse_into(text, values, status, count, stream=stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kern_ms, launches = ctx.timing_read()
-    ctx.timing(False)
-    assert launches == args.steps
-    err = ctx.last_device_error()
-    assert err == 0, err
-    assert int(count.item()) == ntok
-
-    ms_per_step = dt * 1e3 / args.steps
-    gbs = len(buf) / (ms_per_step / 1e3) / 1e9
-    mfloats = ntok / (ms_per_step / 1e3) / 1e6
-    kern_avg_ms = kern_ms / launches
-    alg_bytes = len(buf) + 9 * ntok
-    achieved = alg_bytes / (kern_avg_ms / 1e3) / 1e9
-    workload = "config2-10M-mixed-binary64-plain"
-    traffic = load_traffic(workload)
-
-    print("steps done: %.3f ms/step, parse kernel %.3f ms" % (ms_per_step, kern_avg_ms),
-          file=sys.stderr, flush=True)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(buf, min(args.cpu_sample, ntok))
-
-    out = {
-        "metric": METRIC,
-        "value": round(gbs, 3),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {
-            "workload": workload,
-            "description": "10M numbers in one %.1f MB buffer: 50%% uniform [0,1) shortest "
-                           "digits, 25%% coordinates (6-15 fraction digits), 25%% random "
-                           "finite bit patterns as %%.17e; binary64 output; one "
-                           "ffp_parse_f64 call per step" % (len(buf) / 1e6),
-            "tokens": ntok,
-            "bytes": len(buf),
-            "output": "binary64",
-            "parallelism": "single GPU",
-        },
-        "mfloats_per_s": round(mfloats, 1),
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": "k_parse",
-            "kernel_avg_ms": round(kern_avg_ms, 4),
-            "algorithmic_bytes_per_launch": alg_bytes,
-        },
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
-    ctx.close()
+    wl = args.workload
+    if wl == "config2":
+        n = args.tokens or 10_000_000
+        t0 = time.time()
+        buf = W.config2(n=n)
+        log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
+        rec = run_plain(args, buf, n, "config2-10M-mixed-binary64-plain",
+                        "10M numbers in one %.1f MB buffer: 50%% uniform [0,1) shortest "
+                        "digits, 25%% coordinates (6-15 fraction digits), 25%% random finite "
+                        "bit patterns as %%.17e; binary64 output; one ffp_parse_f64 call per "
+                        "step" % (len(buf) / 1e6), cpu=not args.no_cpu_baseline)
+    elif wl == "config1":
+        n = args.tokens or 100_000
+        buf = W.config1(n=n)
+        rec = run_plain(args, buf, n, "config1-100k-uniform-binary64-plain",
+                        "100k uniform [0,1) doubles, shortest digits, positional, one "
+                        "%.2f MB buffer; binary64" % (len(buf) / 1e6))
+    elif wl == "config3":
+        n = args.tokens or 2_000_000
+        t0 = time.time()
+        buf = W.config3(n=n)
+        log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
+        rec = run_plain(args, buf, n, "config3-2M-hard-binary64-plain",
+                        "2M hard cases (midpoints +-1 in the last of 20-800 digits, "
+                        "subnormals, overflow, integers to 2^64, sign/zero variants) in one "
+                        "%.1f MB buffer; binary64" % (len(buf) / 1e6))
+    elif wl == "config4":
+        rec = run_batched(args, "mixed", "config4-4096-buffers-mixed-batched")
+    else:
+        rec = run_batched(args, "uniform", "config4u-4096-buffers-uniform-batched")
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":
