@@ -13,7 +13,12 @@ Other workloads (--workload):
             mixed formats; plain (one call per buffer) vs batched vs graph
   config4u  the same buffer sizes filled with config-1-format text (about
             3 GB, far above the 256 MB Infinity Cache): the HBM target run
-  config5   served requests: see serve_bench.py
+  config5   served requests: Poisson open-loop arrivals at several rates,
+            sizes lognormal (median 64 KiB, 512 B - 8 MiB), 90% binary64 /
+            10% binary32, 1% hard cases, under a 32 GiB HBM budget; the
+            continuous-batching server vs the plain one-launch-per-request
+            server on the same arrivals, text on the device and in pinned
+            host memory (H2D copy counted); p50/p99/p99.9 latency and GB/s
 
 Prints one JSON line.  `roofline` reports the parse kernel's algorithmic
 bytes (text read once + value + 1-byte status per token) over its average
@@ -295,17 +300,179 @@ def run_batched(args, kind, workload):
     return rec
 
 
+# ---------------------------------------------------------------------------
+# served workload (config 5)
+# ---------------------------------------------------------------------------
+
+def serve_once(ffp, ctx, reqs, on_device, opts):
+    """Replays one arrival schedule against a fresh server; returns per-request
+    (latency ns, count, batch size) and the wall span."""
+    import ctypes
+    import queue
+    import threading
+    import numpy as np
+    ptrs, sizes, dtypes, arrive = reqs
+    n = len(ptrs)
+    srv = ffp.Server(ctx, **opts)
+    lat = np.zeros(n, dtype=np.int64)
+    t_arr = np.zeros(n, dtype=np.int64)
+    t_done = np.zeros(n, dtype=np.int64)
+    counts = np.zeros(n, dtype=np.int64)
+    batch = np.zeros(n, dtype=np.int64)
+    errs = []
+    tq = queue.SimpleQueue()
+
+    def collector():
+        for i in range(n):
+            tk = tq.get()
+            if tk is None:
+                return
+            r = srv.wait(tk)
+            t_arr[i], t_done[i] = r.t_arrive_ns, r.t_done_ns
+            counts[i], batch[i] = r.count, r.batch_jobs
+            if r.err:
+                errs.append((i, r.err))
+            srv.release(tk)
+
+    th = threading.Thread(target=collector)
+    th.start()
+    lib = ffp.load()
+    submit = lib.ffp_server_submit
+    h = srv.handle
+    tkt = ctypes.c_uint64()
+    ref = ctypes.byref(tkt)
+    clock = time.monotonic_ns  # CLOCK_MONOTONIC, the server's clock
+    assert abs(ffp.clock_ns() - clock()) < 50_000_000
+    base = clock() + 20_000_000
+    ondev = 1 if on_device else 0
+    try:
+        for i in range(n):
+            target = base + int(arrive[i])
+            d = target - clock()
+            if d > 400_000:
+                time.sleep((d - 250_000) / 1e9)
+            while clock() < target:
+                pass
+            rc = submit(h, ptrs[i], int(sizes[i]), ondev, int(dtypes[i]), target, ref)
+            if rc != 0:
+                raise ffp.FFPError(rc, "ffp_server_submit")
+            tq.put(tkt.value)
+    except BaseException:
+        tq.put(None)  # the collector stops after the tickets already queued
+        th.join()
+        srv.close()
+        raise
+    th.join()
+    st = srv.stats()
+    srv.close()
+    assert not errs, errs[:5]
+    lat[:] = t_done - t_arr
+    span = (t_done.max() - t_arr.min()) / 1e9
+    return lat, counts, batch, span, st
+
+
+def summarize(lat, counts, sizes, batch, span, st):
+    import numpy as np
+    q = np.percentile(lat / 1e3, [50, 99, 99.9])
+    return {
+        "p50_us": round(float(q[0]), 1), "p99_us": round(float(q[1]), 1),
+        "p999_us": round(float(q[2]), 1), "mean_us": round(float(lat.mean() / 1e3), 1),
+        "GB/s": round(float(sizes.sum()) / span / 1e9, 3),
+        "Mfloats/s": round(float(counts.sum()) / span / 1e6, 2),
+        "span_s": round(span, 3), "batches": int(st["batches"]),
+        "mean_batch": round(float(len(lat)) / max(1, st["batches"]), 2),
+        "max_batch": int(st["max_batch_seen"]),
+        "arena_peak_MB": round(st["arena_peak_bytes"] / 1e6, 1),
+    }
+
+
+def run_served(args, workload):
+    import numpy as np
+    import torch
+    from gen import workloads as W
+    from paper_2101_11408_amd import ffp
+    sys.setswitchinterval(1e-4)
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    mixed = W.token_pool(55, 1_000_000, "mixed")
+    hard = W.token_pool(56, 40_000, "hard")
+    log("pools: mixed %.1f MB, hard %.1f MB, built in %.1f s"
+        % (len(mixed) / 1e6, len(hard) / 1e6, time.time() - t0))
+    pools = []
+    for host in (mixed, hard):
+        d = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(dev)
+        p = torch.empty(len(host), dtype=torch.uint8, pin_memory=True)
+        p.copy_(torch.frombuffer(bytearray(host), dtype=torch.uint8))
+        pools.append((d, p, len(host)))
+    torch.cuda.synchronize()
+    ctx = ffp.Context(0)
+    budget = 32 << 30
+    batched = dict(hbm_budget_bytes=budget, max_batch_bytes=256 << 20,
+                   streams=args.serve_streams, max_batch_jobs=1024,
+                   use_graph=args.serve_graph)
+    plain = dict(hbm_budget_bytes=budget, max_batch_bytes=256 << 20,
+                 mode=ffp.FFP_SERVE_PLAIN, streams=1)
+    rows = []
+    for ri, rate in enumerate(int(r) for r in args.rates.split(",")):
+        t, sizes, is_f32, is_hard = W.config5_requests(5 + ri, rate, args.requests)
+        rng = np.random.default_rng(500 + ri)
+        which = is_hard.astype(np.int64)
+        lim = np.array([pools[k][2] for k in which])
+        sizes = np.minimum(sizes, lim)
+        starts = (rng.random(len(sizes)) * (lim - sizes + 1)).astype(np.int64)
+        dtypes = is_f32.astype(np.int64)
+        arrive = (t * 1e9).astype(np.int64)
+        row = {"rate_req_s": rate, "requests": len(sizes),
+               "offered_GB/s": round(float(sizes.sum()) / float(t[-1]) / 1e9, 3),
+               "binary32_share": round(float(is_f32.mean()), 3),
+               "hard_share": round(float(is_hard.mean()), 4)}
+        for name, opts, on_device in (("batched", batched, True), ("plain", plain, True),
+                                      ("batched_host_text", batched, False)):
+            ptrs = [(pools[k][0] if on_device else pools[k][1]).data_ptr() + int(s)
+                    for k, s in zip(which, starts)]
+            lat, counts, batch, span, st = serve_once(ffp, ctx, (ptrs, sizes, dtypes, arrive),
+                                                      on_device, opts)
+            row[name] = summarize(lat, counts, sizes, batch, span, st)
+            log("rate %d %s: %s" % (rate, name, json.dumps(row[name])))
+        rows.append(row)
+    ctx.close()
+    top = rows[-1]
+    rec = base_record(args, top["batched"]["GB/s"], top["batched"]["p50_us"] / 1e3, workload, {
+        "description": "served parse requests, Poisson open-loop arrivals at %s req/s, %d "
+                       "requests per rate, sizes lognormal (median 64 KiB, sigma 1.5, 512 B - "
+                       "8 MiB), 90%% binary64 / 10%% binary32, 1%% hard cases, 32 GiB HBM "
+                       "budget; value = GB/s served by the continuous-batching server at the "
+                       "highest rate (device-resident text); ms_per_step = its p50 latency"
+                       % (args.rates, args.requests),
+        "streams": args.serve_streams, "graph": bool(args.serve_graph),
+        "parallelism": "single GPU"})
+    rec["steps"] = args.requests
+    rec["p50_us"] = top["batched"]["p50_us"]
+    rec["p99_us"] = top["batched"]["p99_us"]
+    rec["serve"] = rows
+    rec["roofline"] = None
+    rec["roofline_note"] = ("served batches are small and latency-bound; the parse kernel's "
+                            "HBM roofline is measured on config4u")
+    rec["cpu_baseline"] = None
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config3", "config4", "config4u"])
+                    choices=["config1", "config2", "config3", "config4", "config4u",
+                             "config5"])
     ap.add_argument("--tokens", type=int, default=None)
     ap.add_argument("--nbuf", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--rates", default="2000,5000,10000,20000")
+    ap.add_argument("--requests", type=int, default=60_000)
+    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-graph", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -344,6 +511,8 @@ def main():
                         "%.1f MB buffer; binary64" % (len(buf) / 1e6))
     elif wl == "config4":
         rec = run_batched(args, "mixed", "config4-4096-buffers-mixed-batched")
+    elif wl == "config5":
+        rec = run_served(args, "config5-served-poisson")
     else:
         rec = run_batched(args, "uniform", "config4u-4096-buffers-uniform-batched")
     print(json.dumps(rec), flush=True)

@@ -239,6 +239,116 @@ int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches);
 int ffp_counters_enable(ffp_ctx* ctx, int enable);
 int ffp_counters_read(ffp_ctx* ctx, uint64_t counters[6]);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * A server owns a fixed slice of device memory (the HBM budget, allocated
+ * once at creation) and a dispatcher thread.  Requests (one text buffer
+ * each) are submitted from any host thread and queue in arrival order.  As
+ * soon as one of the server's streams is free, the dispatcher admits the
+ * requests at the head of the queue whose outputs (and, for host text, a
+ * device copy of the text) fit the free part of the budget, and launches
+ * them together as one batched parse (ffp_parse_batch) on that stream;
+ * requests that arrive while batches are on the GPU go into the next batch,
+ * so work of several batches overlaps on the device.  Each request is
+ * parsed exactly as ffp_parse_f64 / ffp_parse_f32 would parse it alone.
+ * A request's outputs stay in the server's memory until it is released.
+ *
+ * Times are CLOCK_MONOTONIC nanoseconds (ffp_clock_ns).
+ * The server is thread-safe, except that ffp_server_destroy must not run
+ * concurrently with any other call on it.
+ * ------------------------------------------------------------------------- */
+typedef struct ffp_server ffp_server;
+
+#define FFP_SERVE_BATCHED 0 /* continuous batching over `streams` streams */
+#define FFP_SERVE_PLAIN 1   /* one plain parse launch per request, in
+                               arrival order (the one-buffer-per-launch
+                               comparison point) */
+
+typedef struct ffp_server_options {
+    uint64_t hbm_budget_bytes; /* device memory of the server: per-stream
+                                  scratch plus the request arena (0 = 32 GiB) */
+    uint64_t max_batch_bytes;  /* text bytes per batch; sizes each stream's
+                                  scratch (0 = 256 MiB); also the largest
+                                  request accepted */
+    uint32_t max_inflight;     /* requests held at once, queued or running or
+                                  done and not yet released (0 = 65536) */
+    uint32_t streams;          /* batches in flight, 1..4 (0 = 2) */
+    uint32_t max_batch_jobs;   /* requests per batch, 1..65535 (0 = 1024) */
+    uint32_t mode;             /* FFP_SERVE_BATCHED or FFP_SERVE_PLAIN */
+    uint32_t use_graph;        /* batched mode: replay a captured graph of the
+                                  batch launch sequence per batch */
+    uint32_t reserved[3];
+} ffp_server_options;
+
+typedef struct ffp_result {
+    const void* values;      /* device: `count` doubles or floats, owned by
+                                the server until ffp_server_release */
+    const uint8_t* status;   /* device: `count` ffp_token_status bytes */
+    uint64_t count;          /* tokens of the request */
+    uint64_t nbytes;         /* text bytes of the request */
+    int32_t dtype;           /* FFP_DTYPE_F64 / FFP_DTYPE_F32 */
+    int32_t err;             /* FFP_SUCCESS, FFP_E_QUEUE, FFP_E_INTERNAL or
+                                FFP_E_HIP */
+    uint64_t t_arrive_ns;    /* arrival time given at submission */
+    uint64_t t_launch_ns;    /* its batch was queued on a stream */
+    uint64_t t_done_ns;      /* the dispatcher saw the batch complete */
+    uint32_t batch_jobs;     /* requests in that batch */
+    uint32_t reserved;
+} ffp_result;
+
+typedef struct ffp_server_stats {
+    uint64_t submitted, completed, batches, bytes;
+    uint64_t arena_bytes;       /* request arena (budget minus scratch) */
+    uint64_t arena_peak_bytes;  /* most arena bytes held at once */
+    uint64_t scratch_bytes;     /* scratch of all streams */
+    uint64_t max_batch_seen;    /* largest batch launched (requests) */
+} ffp_server_stats;
+
+/* Current CLOCK_MONOTONIC time in nanoseconds. */
+uint64_t ffp_clock_ns(void);
+
+/* Create a server with the options and schedule of `ctx` (delimiters,
+ * flags, tuning).  `ctx` is only read; the server makes its own contexts.
+ * NULL options select the defaults.  Returns FFP_E_BUDGET when the budget
+ * cannot hold the scratch plus the largest request, FFP_E_NOMEM when the
+ * budget cannot be allocated, FFP_E_ARG for bad options. */
+int ffp_server_create(ffp_ctx* ctx, const ffp_server_options* opts, ffp_server** out);
+
+/* Submit one request.  `text` holds nbytes bytes, in device memory when
+ * on_device != 0, else in host memory (preferably pinned, e.g. from
+ * hipHostMalloc); either way it must stay valid and unchanged until the
+ * request is done.  arrival_ns = 0 means now.  Writes the request's ticket.
+ * Returns FFP_E_BUDGET when the request can never fit (larger than
+ * max_batch_bytes, or its outputs larger than the arena), FFP_E_BUSY when
+ * max_inflight requests are held, FFP_E_ARG for bad arguments. */
+int ffp_server_submit(ffp_server* srv, const uint8_t* text, uint64_t nbytes, int on_device,
+                      int dtype, uint64_t arrival_ns, uint64_t* ticket);
+
+/* Returns 1 and fills *out when the request is done, 0 while it is queued
+ * or running, FFP_E_ARG for an unknown ticket. */
+int ffp_server_poll(ffp_server* srv, uint64_t ticket, ffp_result* out);
+
+/* Blocks until the request is done, then fills *out.  FFP_E_ARG for an
+ * unknown ticket. */
+int ffp_server_wait(ffp_server* srv, uint64_t ticket, ffp_result* out);
+
+/* Copies min(count, max_count) values and status bytes of a done request to
+ * dst_values / dst_status (device or pinned host memory; either may be
+ * NULL), stream-ordered on `stream`.  FFP_E_BUSY if the request is not done. */
+int ffp_server_copy_result(ffp_server* srv, uint64_t ticket, void* dst_values,
+                           uint8_t* dst_status, uint64_t max_count, void* stream);
+
+/* Frees the request's memory.  A request that is not done yet is detached:
+ * its memory is freed when it completes and its ticket is forgotten now. */
+int ffp_server_release(ffp_server* srv, uint64_t ticket);
+
+int ffp_server_stats_read(ffp_server* srv, ffp_server_stats* out);
+
+/* Stops admitting, waits for the batches on the GPU, frees everything.
+ * Requests still queued are dropped. */
+void ffp_server_destroy(ffp_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

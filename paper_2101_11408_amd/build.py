@@ -16,7 +16,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libffp.so")
 ARCH = os.environ.get("FFP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["ffp_kernels.hip", "ffp_capi.cpp"]
+SOURCES = ["ffp_kernels.hip", "ffp_capi.cpp", "ffp_server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH,
@@ -25,6 +25,7 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
+    "-pthread",
     "-Wno-unused-function",
     "-Wno-unknown-warning-option",
     # keep the compiler from emitting packed fp32 instructions

@@ -14,46 +14,9 @@
 #include <vector>
 
 #include "ffp.h"
+#include "ffp_context.h"
 #include "ffp_internal.h"
 #include "ffp_kernels.h"
-
-using ffp::DelimSet;
-using ffp::DeviceState;
-using ffp::JobDesc;
-using ffp::QueueEntry;
-
-struct ffp_ctx {
-  int device = 0;
-  DelimSet delim{};
-  uint32_t flags = 0;
-  int num_cus = 0;
-  std::string arch;
-  int tile_k = 4;
-  int blocks_per_cu = 1;        // chosen schedule
-  int max_bpc[5] = {0, 0, 0, 0, 0};  // occupancy limit per tile_k
-  int fb_grid = 0;
-
-  uint64_t* d_block_sum = nullptr;  // per-block counts, then their prefix
-  uint64_t block_cap = 0;
-  QueueEntry* d_queue = nullptr;
-  uint64_t queue_cap = 0;
-  JobDesc* d_jobs = nullptr;  // internal job table of batched calls
-  uint64_t jobs_cap = 0;
-  DeviceState* d_state = nullptr;
-
-  bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
-  double timed_ms = 0.0;
-  uint64_t timed_launches = 0;
-
-  bool counters = false;
-};
-
-struct ffp_graph {
-  ffp_ctx* own = nullptr;  // private context: the graph holds its scratch
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
 
 namespace {
 
@@ -304,6 +267,69 @@ std::string tune_key(const ffp_ctx* ctx, uint32_t njobs, uint64_t bytes) {
 
 }  // namespace
 
+namespace ffp {
+
+int ctx_grow(ffp_ctx* ctx, uint64_t bytes, uint64_t njobs) {
+  DeviceGuard g(ctx->device);
+  return grow(ctx, bytes, njobs);
+}
+
+int ctx_parse(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t nbytes,
+              void* d_values, uint8_t* d_status, uint64_t capacity, uint64_t* d_count,
+              hipStream_t s) {
+  return parse_common(ctx, dtype, d_text, nbytes, d_values, d_status, capacity, d_count, s);
+}
+
+int ctx_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
+              hipStream_t s) {
+  return batch_common(ctx, d_jobs, njobs, max_total_bytes, s);
+}
+
+int ctx_clone(const ffp_ctx* src, ffp_ctx** out) {
+  ffp_options o{};
+  for (int i = 0; i < 4; ++i) o.delim_set[i] = src->delim.bits[i];
+  o.flags = src->flags;
+  const int rc = ffp_create(src->device, &o, out);
+  if (rc != FFP_SUCCESS) return rc;
+  (*out)->tile_k = src->tile_k;
+  (*out)->blocks_per_cu = src->blocks_per_cu;
+  return FFP_SUCCESS;
+}
+
+int ctx_capture_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
+                      hipGraph_t* graph, hipGraphExec_t* exec) {
+  DeviceGuard g(ctx->device);
+  *graph = nullptr;
+  *exec = nullptr;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreate(&cs) != hipSuccess) return FFP_E_HIP;
+  int rc = FFP_SUCCESS;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = FFP_E_HIP;
+  } else {
+    const int lrc = batch_common(ctx, d_jobs, njobs, max_total_bytes, cs);
+    const hipError_t ec = hipStreamEndCapture(cs, graph);
+    if (lrc != FFP_SUCCESS) rc = lrc;
+    else if (ec != hipSuccess) rc = FFP_E_HIP;
+    else if (hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0) != hipSuccess) rc = FFP_E_HIP;
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc != FFP_SUCCESS) {
+    if (*exec) (void)hipGraphExecDestroy(*exec);
+    if (*graph) (void)hipGraphDestroy(*graph);
+    *graph = nullptr;
+    *exec = nullptr;
+  }
+  return rc;
+}
+
+uint64_t ctx_scratch_bytes(const ffp_ctx* ctx) {
+  return ctx->block_cap * sizeof(uint64_t) + ctx->queue_cap * sizeof(QueueEntry) +
+         ctx->jobs_cap * sizeof(JobDesc) + sizeof(DeviceState);
+}
+
+}  // namespace ffp
+
 extern "C" {
 
 const char* ffp_strerror(int err) {
@@ -453,33 +479,15 @@ int ffp_batch_graph_create(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs,
   ffp_graph* gr = new (std::nothrow) ffp_graph();
   if (!gr) return FFP_E_NOMEM;
   // a private context with the same options and schedule
-  ffp_options o{};
-  for (int i = 0; i < 4; ++i) o.delim_set[i] = ctx->delim.bits[i];
-  o.flags = ctx->flags;
-  int rc = ffp_create(ctx->device, &o, &gr->own);
+  int rc = ffp::ctx_clone(ctx, &gr->own);
   if (rc != FFP_SUCCESS) {
     delete gr;
     return rc;
   }
-  gr->own->tile_k = ctx->tile_k;
-  gr->own->blocks_per_cu = ctx->blocks_per_cu;
   DeviceGuard g(ctx->device);
   rc = grow(gr->own, max_total_bytes, njobs < 2 ? 2 : njobs);
-  hipStream_t cs = nullptr;
-  if (rc == FFP_SUCCESS && hipStreamCreate(&cs) != hipSuccess) rc = FFP_E_HIP;
-  if (rc == FFP_SUCCESS) {
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      rc = FFP_E_HIP;
-    } else {
-      const int lrc = batch_common(gr->own, d_jobs, njobs, max_total_bytes, cs);
-      const hipError_t ec = hipStreamEndCapture(cs, &gr->graph);
-      if (lrc != FFP_SUCCESS) rc = lrc;
-      else if (ec != hipSuccess) rc = FFP_E_HIP;
-      else if (hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess)
-        rc = FFP_E_HIP;
-    }
-  }
-  if (cs) (void)hipStreamDestroy(cs);
+  if (rc == FFP_SUCCESS)
+    rc = ffp::ctx_capture_batch(gr->own, d_jobs, njobs, max_total_bytes, &gr->graph, &gr->exec);
   if (rc != FFP_SUCCESS) {
     ffp_batch_graph_destroy(gr);
     return rc;

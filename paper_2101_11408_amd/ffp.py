@@ -32,6 +32,9 @@ FFP_REJECT_PLUS = 1
 DTYPE_F64 = 0
 DTYPE_F32 = 1
 
+FFP_SERVE_BATCHED = 0
+FFP_SERVE_PLAIN = 1
+
 
 class ffp_options(ctypes.Structure):
     _fields_ = [("delim_set", ctypes.c_uint64 * 4), ("flags", ctypes.c_uint32),
@@ -48,6 +51,28 @@ class ffp_job(ctypes.Structure):
 class ffp_tuning(ctypes.Structure):
     _fields_ = [("tile_k", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
+
+
+class ffp_server_options(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_batch_bytes", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("max_batch_jobs", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+
+
+class ffp_result(ctypes.Structure):
+    _fields_ = [("values", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("count", ctypes.c_uint64), ("nbytes", ctypes.c_uint64),
+                ("dtype", ctypes.c_int32), ("err", ctypes.c_int32),
+                ("t_arrive_ns", ctypes.c_uint64), ("t_launch_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("batch_jobs", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ffp_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in
+                ("submitted", "completed", "batches", "bytes", "arena_bytes",
+                 "arena_peak_bytes", "scratch_bytes", "max_batch_seen")]
 
 
 _c = ctypes
@@ -78,6 +103,15 @@ _SIGNATURES = {
     "ffp_get_tuning": (_INT, [_P, _c.POINTER(ffp_tuning)]),
     "ffp_set_tuning": (_INT, [_P, _c.POINTER(ffp_tuning)]),
     "ffp_autotune_batch": (_INT, [_P, _P, _c.c_uint32, _U64, _P, _c.POINTER(ffp_tuning)]),
+    "ffp_clock_ns": (_U64, []),
+    "ffp_server_create": (_INT, [_P, _c.POINTER(ffp_server_options), _c.POINTER(_P)]),
+    "ffp_server_submit": (_INT, [_P, _P, _U64, _INT, _INT, _U64, _c.POINTER(_U64)]),
+    "ffp_server_poll": (_INT, [_P, _U64, _c.POINTER(ffp_result)]),
+    "ffp_server_wait": (_INT, [_P, _U64, _c.POINTER(ffp_result)]),
+    "ffp_server_copy_result": (_INT, [_P, _U64, _P, _P, _U64, _P]),
+    "ffp_server_release": (_INT, [_P, _U64]),
+    "ffp_server_stats_read": (_INT, [_P, _c.POINTER(ffp_server_stats)]),
+    "ffp_server_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -330,6 +364,88 @@ class BatchGraph:
     def close(self):
         if self.handle:
             load().ffp_batch_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# serving (ffp_server_*)
+# ---------------------------------------------------------------------------
+
+def clock_ns() -> int:
+    """CLOCK_MONOTONIC nanoseconds, the clock of the server's timestamps."""
+    return load().ffp_clock_ns()
+
+
+class Server:
+    """A request server (continuous batching) created from a Context."""
+
+    def __init__(self, ctx, hbm_budget_bytes=0, max_batch_bytes=0, max_inflight=0, streams=0,
+                 max_batch_jobs=0, mode=FFP_SERVE_BATCHED, use_graph=False):
+        o = ffp_server_options()
+        o.hbm_budget_bytes = hbm_budget_bytes
+        o.max_batch_bytes = max_batch_bytes
+        o.max_inflight = max_inflight
+        o.streams = streams
+        o.max_batch_jobs = max_batch_jobs
+        o.mode = mode
+        o.use_graph = 1 if use_graph else 0
+        out = _P()
+        check(load().ffp_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(out)),
+              "ffp_server_create")
+        self.handle = out
+
+    def submit_ptr(self, ptr, nbytes, on_device, dtype=DTYPE_F64, arrival_ns=0):
+        """Submit raw memory; returns the ticket or raises FFPError."""
+        t = ctypes.c_uint64()
+        check(load().ffp_server_submit(self.handle, ptr, nbytes, 1 if on_device else 0, dtype,
+                                       arrival_ns, ctypes.byref(t)), "ffp_server_submit")
+        return t.value
+
+    def submit(self, text, dtype=DTYPE_F64, arrival_ns=0):
+        """Submit a contiguous uint8 tensor (device, or pinned host)."""
+        return self.submit_ptr(text.data_ptr() if text.numel() else 0, text.numel(),
+                               text.is_cuda, dtype, arrival_ns)
+
+    def poll(self, ticket):
+        r = ffp_result()
+        rc = check(load().ffp_server_poll(self.handle, ticket, ctypes.byref(r)), "poll")
+        return r if rc == 1 else None
+
+    def wait(self, ticket):
+        r = ffp_result()
+        check(load().ffp_server_wait(self.handle, ticket, ctypes.byref(r)), "wait")
+        return r
+
+    def result_tensors(self, ticket, device, stream=None):
+        """Copies a done request's values and status into new device tensors."""
+        import torch
+        r = self.wait(ticket)
+        dt = torch.float32 if r.dtype == DTYPE_F32 else torch.float64
+        values = torch.empty(r.count, dtype=dt, device=device)
+        status = torch.empty(r.count, dtype=torch.uint8, device=device)
+        if r.count:
+            check(load().ffp_server_copy_result(self.handle, ticket, values.data_ptr(),
+                                                status.data_ptr(), r.count,
+                                                _stream_handle(stream)), "copy_result")
+        return r, values, status
+
+    def release(self, ticket):
+        check(load().ffp_server_release(self.handle, ticket), "release")
+
+    def stats(self):
+        st = ffp_server_stats()
+        check(load().ffp_server_stats_read(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ffp_server_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            load().ffp_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,258 @@
+"""The request server (ffp_server_*): continuous batching over several
+streams, admission by HBM budget, back-pressure.  Every request's result must
+be bit-identical whether it ran alone or in a mix with others, and equal to
+the oracle's parse of its text."""
+
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from gen import workloads as W
+from oracle import parse_buffer
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ffpmod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_11408_amd import ffp
+    ffp.load()
+    return ffp
+
+
+@pytest.fixture(scope="module")
+def ctx(ffpmod):
+    c = ffpmod.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def pool():
+    rng = np.random.default_rng(81)
+    toks = W.mixed_tokens(rng, 150_000) + W.hard_tokens(rng, 3000)
+    rng.shuffle(toks)
+    host = W.join_tokens(toks)
+    dev = torch.frombuffer(bytearray(host), dtype=torch.uint8).to("cuda:0")
+    pinned = torch.empty(len(host), dtype=torch.uint8, pin_memory=True)
+    pinned.copy_(torch.frombuffer(bytearray(host), dtype=torch.uint8))
+    return host, dev, pinned
+
+
+def make_requests(pool, n, seed, median=16_000, hi=400_000):
+    """(start, length, on_device, dtype) for n requests over the pool; some
+    start inside a token, some are empty or one byte."""
+    host, _, _ = pool
+    rng = np.random.default_rng(seed)
+    sizes = W.lognormal_sizes(rng, n, median, 1.5, 1, hi)
+    sizes[:3] = [0, 1, 2]
+    plan = W.slice_plan(rng, host, sizes)
+    on_dev = rng.random(n) < 0.5
+    f32 = rng.random(n) < 0.15
+    return [(st, ln, bool(d), 1 if f else 0) for (st, ln), d, f in zip(plan, on_dev, f32)]
+
+
+def submit(srv, pool, req, arrival_ns=0):
+    host, dev, pinned = pool
+    st, ln, on_dev, dtype = req
+    assert 0 <= st and st + ln <= len(host), "request outside the pool"
+    src = dev if on_dev else pinned
+    ptr = src[st:].data_ptr() if ln else 0
+    return srv.submit_ptr(ptr, ln, on_dev, dtype, arrival_ns)
+
+
+def collect(srv, ticket):
+    """(count, err, values bits, status) of a done request, as numpy."""
+    r, values, status = srv.result_tensors(ticket, "cuda:0")
+    ib, npb = (torch.int32, np.uint32) if r.dtype == 1 else (torch.int64, np.uint64)
+    torch.cuda.synchronize()
+    out = (r.count, r.err, values.view(ib).cpu().numpy().view(npb), status.cpu().numpy())
+    srv.release(ticket)
+    return out
+
+
+def run_mix(srv, pool, reqs):
+    tickets = [submit(srv, pool, q) for q in reqs]
+    return [collect(srv, t) for t in tickets]
+
+
+def run_alone(srv, pool, reqs):
+    out = []
+    for q in reqs:
+        t = submit(srv, pool, q)
+        out.append(collect(srv, t))
+    return out
+
+
+def same(a, b):
+    return (a[0] == b[0] and a[1] == b[1] and np.array_equal(a[2], b[2])
+            and np.array_equal(a[3], b[3]))
+
+
+def check_oracle(pool, reqs, results, label):
+    host = pool[0]
+    for i, (q, res) in enumerate(zip(reqs, results)):
+        st, ln, _, dtype = q
+        fmt = "f32" if dtype == 1 else "f64"
+        wb, ws = parse_buffer(host[st:st + ln], fmt)
+        count, err, bits, status = res
+        assert err == 0, (label, i, err)
+        assert count == len(wb), (label, i, count, len(wb))
+        npb = np.uint32 if dtype == 1 else np.uint64
+        assert np.array_equal(bits, np.array(wb, dtype=npb)), (label, i, fmt)
+        assert np.array_equal(status, np.array(ws, dtype=np.uint8)), (label, i, fmt)
+
+
+@pytest.fixture(scope="module")
+def reference(ctx, ffpmod, pool):
+    """Requests and their results when each runs alone on a batched server;
+    checked against the oracle once."""
+    reqs = make_requests(pool, 120, 12)
+    srv = ffpmod.Server(ctx, hbm_budget_bytes=2 << 30, max_batch_bytes=64 << 20,
+                        max_batch_jobs=64)
+    try:
+        alone = run_alone(srv, pool, reqs)
+    finally:
+        srv.close()
+    _log("alone done", len(reqs))
+    check_oracle(pool, reqs, alone, "alone")
+    return reqs, alone
+
+
+def test_mix_equals_alone(ctx, ffpmod, pool, reference):
+    reqs, alone = reference
+    srv = ffpmod.Server(ctx, hbm_budget_bytes=2 << 30, max_batch_bytes=64 << 20,
+                        max_batch_jobs=16, streams=3)
+    try:
+        mix = run_mix(srv, pool, reqs)
+        st = srv.stats()
+    finally:
+        srv.close()
+    _log("mix stats", st)
+    for i, (a, b) in enumerate(zip(alone, mix)):
+        assert same(a, b), i
+    assert st["completed"] == len(reqs)
+    assert st["max_batch_seen"] > 1  # requests were batched together
+
+
+def test_plain_mode_equals_alone(ctx, ffpmod, pool, reference):
+    reqs, alone = reference
+    srv = ffpmod.Server(ctx, hbm_budget_bytes=2 << 30, max_batch_bytes=64 << 20,
+                        mode=ffpmod.FFP_SERVE_PLAIN)
+    try:
+        plain = run_mix(srv, pool, reqs)
+        st = srv.stats()
+    finally:
+        srv.close()
+    for i, (a, b) in enumerate(zip(alone, plain)):
+        assert same(a, b), i
+    assert st["max_batch_seen"] == 1 and st["batches"] == len(reqs)
+
+
+def test_graph_mode_random_arrivals(ctx, ffpmod, pool, reference):
+    """Captured-graph batches replayed many times, requests arriving from
+    another thread while batches run, eager torch work in between."""
+    reqs, alone = reference
+    srv = ffpmod.Server(ctx, hbm_budget_bytes=2 << 30, max_batch_bytes=64 << 20,
+                        max_batch_jobs=32, streams=2, use_graph=True)
+    tickets = [None] * len(reqs)
+    rng = np.random.default_rng(3)
+    gaps = rng.exponential(200e-6, size=len(reqs))
+
+    def producer():
+        for i, q in enumerate(reqs):
+            time.sleep(gaps[i])
+            tickets[i] = submit(srv, pool, q)
+
+    try:
+        th = threading.Thread(target=producer)
+        th.start()
+        for _ in range(20):
+            x = torch.arange(1 << 18, device="cuda:0").sum()
+            _ = x.item()
+        th.join()
+        results = [collect(srv, t) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.close()
+    _log("graph stats", st)
+    for i, (a, b) in enumerate(zip(alone, results)):
+        assert same(a, b), i
+    assert st["batches"] > 1
+
+
+def test_admission_by_budget(ctx, ffpmod, pool):
+    """A request whose memory does not fit waits until a held result is
+    released; a request larger than the arena is refused."""
+    host, dev, pinned = pool
+    n = min(1_500_000, len(host) // 2)
+    cap = (n + 1) // 2
+    r256 = lambda x: (x + 255) // 256 * 256
+    need = r256(n) + r256(8 * cap) + r256(cap)  # host text, binary64
+    opts = dict(max_batch_bytes=2 << 20, max_batch_jobs=8, streams=1)
+    probe = ffpmod.Server(ctx, hbm_budget_bytes=64 << 20, **opts)
+    scratch = probe.stats()["scratch_bytes"]
+    probe.close()
+    # an arena of 1.5 requests: one fits, two do not
+    srv = ffpmod.Server(ctx, hbm_budget_bytes=scratch + need * 3 // 2 + 4096, **opts)
+    try:
+        st = srv.stats()
+        arena = st["arena_bytes"]
+        _log("arena", arena, "scratch", st["scratch_bytes"], "need", need)
+        assert need <= arena < 2 * need
+        a = submit(srv, pool, (0, n, False, 0))
+        ra = srv.wait(a)
+        assert ra.err == 0
+        b = submit(srv, pool, (n, n, False, 0))
+        time.sleep(0.05)
+        assert srv.poll(b) is None  # blocked by the held result of a
+        srv.release(a)
+        rb = srv.wait(b)
+        assert rb.err == 0 and rb.t_launch_ns >= ra.t_done_ns
+        count, err, bits, status = collect(srv, b)
+        wb, ws = parse_buffer(host[n:2 * n], "f64")
+        assert count == len(wb) and np.array_equal(bits, np.array(wb, dtype=np.uint64))
+        with pytest.raises(ffpmod.FFPError) as e:
+            srv.submit_ptr(pinned.data_ptr(), (2 << 20) + 1, False)
+        assert e.value.code == ffpmod.FFP_E_BUDGET
+        # device text is not staged: only its outputs take arena memory
+        t = submit(srv, pool, (0, 2 << 20, True, 1))
+        assert srv.wait(t).err == 0
+        srv.release(t)
+        assert srv.stats()["arena_peak_bytes"] <= arena
+    finally:
+        srv.close()
+
+
+def test_inflight_limit_and_detach(ctx, ffpmod, pool):
+    srv = ffpmod.Server(ctx, hbm_budget_bytes=256 << 20, max_batch_bytes=16 << 20,
+                        max_inflight=2)
+    try:
+        a = submit(srv, pool, (0, 10_000, True, 0))
+        b = submit(srv, pool, (10_000, 10_000, True, 0))
+        with pytest.raises(ffpmod.FFPError) as e:
+            submit(srv, pool, (20_000, 10_000, True, 0))
+        assert e.value.code == ffpmod.FFP_E_BUSY
+        srv.release(a)  # possibly still running: detached
+        c = submit(srv, pool, (20_000, 10_000, True, 0))
+        assert srv.wait(b).err == 0 and srv.wait(c).err == 0
+        srv.release(b)
+        srv.release(c)
+        with pytest.raises(ffpmod.FFPError):
+            srv.poll(a)
+        deadline = time.time() + 10
+        while srv.stats()["completed"] < 3 and time.time() < deadline:
+            time.sleep(0.001)
+        assert srv.stats()["completed"] == 3
+    finally:
+        srv.close()
