@@ -37,6 +37,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+WORKLOAD_NAMES = {
+    "config1": "config1-100k-uniform-binary64-plain",
+    "config2": "config2-10M-mixed-binary64-plain",
+    "config3": "config3-2M-hard-binary64-plain",
+    "config4": "config4-4096-buffers-mixed-batched",
+    "config4u": "config4u-4096-buffers-uniform-batched",
+    "config5": "config5-served-poisson",
+    "copycal": "copy-calibration",
+}
 METRIC = "GB/s input text + Mfloats/s parsed (bit-exact), batched/served vs plain; p50/p99"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2101_11408_amd/csrc/ffp_kernels.hip",
@@ -243,8 +252,13 @@ def run_batched(args, kind, workload):
     ctx = ffp.Context(0)
     table = ffp.JobTable(texts, values, statuses, dev)
     stream = torch.cuda.current_stream()
-    tune = ctx.autotune_batch(table.dev, table.n, total)
-    log("autotuned schedule (tile_k, workgroups/CU):", tune)
+    if args.schedule:
+        ctx.set_tuning(*[int(x) for x in args.schedule.split(",")])
+        tune = ctx.get_tuning()
+        log("fixed schedule (tile_k, workgroups/CU):", tune)
+    else:
+        tune = ctx.autotune_batch(table.dev, table.n, total)
+        log("autotuned schedule (tile_k, workgroups/CU):", tune)
 
     # plain: one call per buffer, back to back on one stream
     ctx.reserve(int(max(sizes)))
@@ -252,7 +266,8 @@ def run_batched(args, kind, workload):
     def plain_all():
         for t, v, s, c in zip(texts, values, statuses, counts):
             ctx.parse_into(t, v, s, c, stream=stream)
-    ms_plain = timed_steps(torch, plain_all, max(1, args.steps // 5), 1)
+    ms_plain = None if args.profile else timed_steps(torch, plain_all,
+                                                     max(1, args.steps // 5), 1)
 
     # batched (one call) with the parse kernel timed
     ms_batch = timed_steps(torch, lambda: ctx.parse_batch(table.dev, table.n, total, stream),
@@ -269,11 +284,14 @@ def run_batched(args, kind, workload):
     assert all(e == 0 for c, e in res), "job errors"
 
     # captured graph replay
-    graph = ffp.BatchGraph(ctx, table, total)
-    ms_graph = timed_steps(torch, lambda: graph.launch(stream), args.steps, args.warmup)
-    res2 = table.download()
-    assert [c for c, e in res2] == [c for c, e in res] and all(e == 0 for c, e in res2)
-    graph.close()
+    if args.profile:
+        ms_plain = ms_graph = ms_batch
+    else:
+        graph = ffp.BatchGraph(ctx, table, total)
+        ms_graph = timed_steps(torch, lambda: graph.launch(stream), args.steps, args.warmup)
+        res2 = table.download()
+        assert [c for c, e in res2] == [c for c, e in res] and all(e == 0 for c, e in res2)
+        graph.close()
     assert ctx.last_device_error() == 0
 
     alg = total + 9 * ntok
@@ -305,70 +323,24 @@ def run_batched(args, kind, workload):
 # ---------------------------------------------------------------------------
 
 def serve_once(ffp, ctx, reqs, on_device, opts):
-    """Replays one arrival schedule against a fresh server; returns per-request
-    (latency ns, count, batch size) and the wall span."""
-    import ctypes
-    import queue
-    import threading
+    """Replays one arrival schedule against a fresh server (ffp_server_replay:
+    submission at each arrival time and in-order collection run in native
+    threads); returns per-request latency (ns), counts, batch sizes, the wall
+    span and the server's statistics."""
     import numpy as np
     ptrs, sizes, dtypes, arrive = reqs
-    n = len(ptrs)
     srv = ffp.Server(ctx, **opts)
-    lat = np.zeros(n, dtype=np.int64)
-    t_arr = np.zeros(n, dtype=np.int64)
-    t_done = np.zeros(n, dtype=np.int64)
-    counts = np.zeros(n, dtype=np.int64)
-    batch = np.zeros(n, dtype=np.int64)
-    errs = []
-    tq = queue.SimpleQueue()
-
-    def collector():
-        for i in range(n):
-            tk = tq.get()
-            if tk is None:
-                return
-            r = srv.wait(tk)
-            t_arr[i], t_done[i] = r.t_arrive_ns, r.t_done_ns
-            counts[i], batch[i] = r.count, r.batch_jobs
-            if r.err:
-                errs.append((i, r.err))
-            srv.release(tk)
-
-    th = threading.Thread(target=collector)
-    th.start()
-    lib = ffp.load()
-    submit = lib.ffp_server_submit
-    h = srv.handle
-    tkt = ctypes.c_uint64()
-    ref = ctypes.byref(tkt)
-    clock = time.monotonic_ns  # CLOCK_MONOTONIC, the server's clock
-    assert abs(ffp.clock_ns() - clock()) < 50_000_000
-    base = clock() + 20_000_000
-    ondev = 1 if on_device else 0
     try:
-        for i in range(n):
-            target = base + int(arrive[i])
-            d = target - clock()
-            if d > 400_000:
-                time.sleep((d - 250_000) / 1e9)
-            while clock() < target:
-                pass
-            rc = submit(h, ptrs[i], int(sizes[i]), ondev, int(dtypes[i]), target, ref)
-            if rc != 0:
-                raise ffp.FFPError(rc, "ffp_server_submit")
-            tq.put(tkt.value)
-    except BaseException:
-        tq.put(None)  # the collector stops after the tickets already queued
-        th.join()
+        base = ffp.clock_ns() + 20_000_000
+        out = srv.replay(ptrs, sizes, 1 if on_device else 0, dtypes, base + arrive)
+        st = srv.stats()
+    finally:
         srv.close()
-        raise
-    th.join()
-    st = srv.stats()
-    srv.close()
-    assert not errs, errs[:5]
-    lat[:] = t_done - t_arr
-    span = (t_done.max() - t_arr.min()) / 1e9
-    return lat, counts, batch, span, st
+    bad = np.flatnonzero(out["err"] != 0)
+    assert bad.size == 0, ("request errors", bad[:5], out["err"][bad[:5]])
+    lat = out["t_done_ns"].astype(np.int64) - out["t_arrive_ns"].astype(np.int64)
+    span = (int(out["t_done_ns"].max()) - int(out["t_arrive_ns"].min())) / 1e9
+    return lat, out["count"].astype(np.int64), out["batch_jobs"], span, st
 
 
 def summarize(lat, counts, sizes, batch, span, st):
@@ -391,7 +363,6 @@ def run_served(args, workload):
     import torch
     from gen import workloads as W
     from paper_2101_11408_amd import ffp
-    sys.setswitchinterval(1e-4)
     dev = torch.device("cuda", 0)
     t0 = time.time()
     mixed = W.token_pool(55, 1_000_000, "mixed")
@@ -457,6 +428,127 @@ def run_served(args, workload):
     return rec
 
 
+# ---------------------------------------------------------------------------
+# HBM traffic from rocprofv3 counters
+# ---------------------------------------------------------------------------
+CAL_BYTES = 1 << 30
+
+
+def run_copycal(args):
+    """A plain streaming kernel of known size (read 1 GiB, write 1 GiB), the
+    calibration point of the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(CAL_BYTES // 8, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(max(1, args.steps)):
+        torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    return {"calibration": "bitwise_not int64", "read_bytes": CAL_BYTES,
+            "write_bytes": CAL_BYTES, "launches": max(1, args.steps)}
+
+
+def _counter_rows(csv_path, counter, match):
+    import csv
+    vals = []
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] == counter and match(row["Kernel_Name"]):
+                vals.append(float(row["Counter_Value"]))
+    if not vals:
+        raise SystemExit("no %s rows for the kernel in %s" % (counter, csv_path))
+    return vals
+
+
+def reduce_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, command):
+    """profiles/traffic.json[workload] = HBM bytes per parse-kernel launch:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over dispatches),
+    each scaled by bytes / counter of the calibration kernel."""
+    is_parse = lambda n: "k_parse" in n
+    is_cal = lambda n: "bitwise_not" in n or "BitwiseNot" in n
+    mean = lambda v: sum(v) / len(v)
+    f_k = mean(_counter_rows(fetch_csv, "FETCH_SIZE", is_parse))
+    w_k = mean(_counter_rows(write_csv, "WRITE_SIZE", is_parse))
+    f_c = mean(_counter_rows(cal_fetch_csv, "FETCH_SIZE", is_cal))
+    w_c = mean(_counter_rows(cal_write_csv, "WRITE_SIZE", is_cal))
+    ff = CAL_BYTES / (f_c * 1024.0)
+    fw = CAL_BYTES / (w_c * 1024.0)
+    ent = {
+        "kernel_hash": kernel_hash(),
+        "bytes_per_launch": round(f_k * 1024.0 * ff + w_k * 1024.0 * fw),
+        "fetch_bytes": round(f_k * 1024.0 * ff),
+        "write_bytes": round(w_k * 1024.0 * fw),
+        "fetch_kib_raw": f_k, "write_kib_raw": w_k,
+        "calibration_fetch_factor": round(ff, 4), "calibration_write_factor": round(fw, 4),
+        "command": command,
+    }
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data[workload] = ent
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return ent
+
+
+def summarize_trace(workload, trace_dir, command, bench_json=None):
+    """profiles/<kernel>_<workload>.md from a rocprofv3 --kernel-trace --stats
+    run: the per-kernel table, the parse kernel's dispatches grouped by grid
+    size, and the bench's own HIP-event average for comparison."""
+    import csv
+    import glob
+    stats = glob.glob(os.path.join(trace_dir, "*kernel_stats.csv"))[0]
+    trace = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0]
+    lines = ["# rocprofv3 kernel trace: %s" % workload, "",
+             "Command (from the repository root, on one MI355X):", "",
+             "    " + command, "",
+             "## Per-kernel statistics (`--stats`)", "",
+             "| kernel | calls | avg us | min us | max us | share % |",
+             "|---|---|---|---|---|---|"]
+    with open(stats) as f:
+        rows = list(csv.DictReader(f))
+    for r in rows[:10]:
+        lines.append("| `%s` | %s | %.1f | %.1f | %.1f | %s |" % (
+            r["Name"][:70], r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, r["Percentage"]))
+    groups = {}
+    with open(trace) as f:
+        for r in csv.DictReader(f):
+            if "k_parse" not in r["Kernel_Name"]:
+                continue
+            key = (r["Kernel_Name"], int(r["Grid_Size_X"]))
+            groups.setdefault(key, []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines += ["", "## Parse kernel dispatches by grid size (`kernel_trace.csv`)", "",
+              "| kernel | grid (threads) | dispatches | avg us | min us | max us |",
+              "|---|---|---|---|---|---|"]
+    ranked = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+    for (name, grid), d in ranked[:8]:
+        lines.append("| `%s` | %d | %d | %.1f | %.1f | %.1f |" % (
+            name[:40], grid, len(d), sum(d) / len(d), min(d), max(d)))
+    rest = [x for _, d in ranked[8:] for x in d]
+    if rest:
+        lines.append("| %d other grid sizes | | %d | %.1f | %.1f | %.1f |" % (
+            len(ranked) - 8, len(rest), sum(rest) / len(rest), min(rest), max(rest)))
+    if bench_json:
+        with open(bench_json) as f:
+            rec = json.loads(f.read().strip().splitlines()[-1])
+        rf = rec.get("roofline") or {}
+        lines += ["", "## The same run's bench line", "",
+                  "HIP-event average of the parse kernel over the timed steps: %.1f us; "
+                  "value %s %s; ms_per_step %s." % (
+                      rf.get("kernel_avg_ms", float("nan")) * 1e3, rec["value"], rec["unit"],
+                      rec["ms_per_step"])]
+        if rec.get("config", {}).get("schedule"):
+            lines.append("Schedule chosen by the autotuner: %s." % rec["config"]["schedule"])
+    name = "k_parse_%s.md" % workload
+    with open(os.path.join(ROOT, "profiles", name), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return name
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -464,7 +556,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config4u",
-                             "config5"])
+                             "config5", "copycal"])
     ap.add_argument("--tokens", type=int, default=None)
     ap.add_argument("--nbuf", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -473,7 +565,30 @@ def main():
     ap.add_argument("--requests", type=int, default=60_000)
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-graph", type=int, default=0)
+    ap.add_argument("--schedule", default="",
+                    help="batched workloads: tile_k,workgroups_per_cu instead of the autotuner")
+    ap.add_argument("--profile", action="store_true",
+                    help="batched workloads: only the timed batched calls (for counter runs)")
+    ap.add_argument("--reduce-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
+                                                          "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
+                    help="write profiles/traffic.json for --workload from rocprofv3 "
+                         "counter CSVs (no GPU needed)")
+    ap.add_argument("--traffic-command", default="")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="write profiles/k_parse_<workload>.md from a rocprofv3 kernel "
+                         "trace of the bench command given by --traffic-command")
     args = ap.parse_args()
+
+    if args.summarize_trace:
+        print(summarize_trace(WORKLOAD_NAMES[args.workload], args.summarize_trace[0],
+                              args.traffic_command, args.summarize_trace[1]))
+        return
+
+    if args.reduce_traffic:
+        ent = reduce_traffic(WORKLOAD_NAMES[args.workload], *args.reduce_traffic,
+                             args.traffic_command)
+        print(json.dumps(ent), flush=True)
+        return
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the parser's multi-GPU split is a design "
@@ -489,7 +604,7 @@ def main():
         t0 = time.time()
         buf = W.config2(n=n)
         log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
-        rec = run_plain(args, buf, n, "config2-10M-mixed-binary64-plain",
+        rec = run_plain(args, buf, n, WORKLOAD_NAMES[wl],
                         "10M numbers in one %.1f MB buffer: 50%% uniform [0,1) shortest "
                         "digits, 25%% coordinates (6-15 fraction digits), 25%% random finite "
                         "bit patterns as %%.17e; binary64 output; one ffp_parse_f64 call per "
@@ -497,7 +612,7 @@ def main():
     elif wl == "config1":
         n = args.tokens or 100_000
         buf = W.config1(n=n)
-        rec = run_plain(args, buf, n, "config1-100k-uniform-binary64-plain",
+        rec = run_plain(args, buf, n, WORKLOAD_NAMES[wl],
                         "100k uniform [0,1) doubles, shortest digits, positional, one "
                         "%.2f MB buffer; binary64" % (len(buf) / 1e6))
     elif wl == "config3":
@@ -505,16 +620,18 @@ def main():
         t0 = time.time()
         buf = W.config3(n=n)
         log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
-        rec = run_plain(args, buf, n, "config3-2M-hard-binary64-plain",
+        rec = run_plain(args, buf, n, WORKLOAD_NAMES[wl],
                         "2M hard cases (midpoints +-1 in the last of 20-800 digits, "
                         "subnormals, overflow, integers to 2^64, sign/zero variants) in one "
                         "%.1f MB buffer; binary64" % (len(buf) / 1e6))
     elif wl == "config4":
-        rec = run_batched(args, "mixed", "config4-4096-buffers-mixed-batched")
+        rec = run_batched(args, "mixed", WORKLOAD_NAMES[wl])
     elif wl == "config5":
-        rec = run_served(args, "config5-served-poisson")
+        rec = run_served(args, WORKLOAD_NAMES[wl])
+    elif wl == "copycal":
+        rec = run_copycal(args)
     else:
-        rec = run_batched(args, "uniform", "config4u-4096-buffers-uniform-batched")
+        rec = run_batched(args, "uniform", WORKLOAD_NAMES[wl])
     print(json.dumps(rec), flush=True)
 
 

@@ -349,6 +349,31 @@ int ffp_server_stats_read(ffp_server* srv, ffp_server_stats* out);
  * Requests still queued are dropped. */
 void ffp_server_destroy(ffp_server* srv);
 
+/* Replay of an arrival trace (capacity planning and benchmarks): a
+ * submitting thread submits request i at its arrival time (spinning for the
+ * last few hundred microseconds; retrying while the server answers
+ * FFP_E_BUSY), a collecting thread waits for the requests in submission
+ * order, records their timestamps and releases them (the parsed values are
+ * discarded).  Blocks until every request is done.  Returns FFP_SUCCESS or
+ * the first submission error. */
+typedef struct ffp_replay_request {
+    const uint8_t* text;
+    uint64_t nbytes;
+    int32_t on_device;
+    int32_t dtype;
+    uint64_t arrival_ns;  /* CLOCK_MONOTONIC */
+} ffp_replay_request;
+
+typedef struct ffp_replay_result {
+    uint64_t t_arrive_ns, t_launch_ns, t_done_ns;
+    uint64_t count;
+    int32_t err;
+    uint32_t batch_jobs;
+} ffp_replay_result;
+
+int ffp_server_replay(ffp_server* srv, const ffp_replay_request* reqs, uint64_t n,
+                      ffp_replay_result* out);
+
 #ifdef __cplusplus
 }
 #endif

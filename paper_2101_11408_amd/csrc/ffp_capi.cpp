@@ -396,7 +396,7 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
     if (v == 1 || v == 2 || v == 4) ctx->tile_k = v;
   }
   ctx->blocks_per_cu = ctx->max_bpc[ctx->tile_k];
-  ctx->fb_grid = ctx->num_cus * 2;
+  ctx->fb_grid = ctx->num_cus * 4;
   if (hipMalloc(&ctx->d_state, sizeof(DeviceState)) != hipSuccess) {
     delete ctx;
     return FFP_E_NOMEM;

@@ -1,6 +1,5 @@
 // Device-side building blocks of the parser: format constants, the
-// 64x64->128-bit product, Algorithm 1 of the paper, the token lexer and the
-// big-integer helpers of the exact fallback.
+// 64x64->128-bit product, Algorithm 1 of the paper and the token lexer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -276,83 +275,6 @@ struct GlobalSrc {
 };
 
 // ---------------------------------------------------------------------------
-// Big unsigned integers for the exact fallback: little-endian 32-bit limbs.
-// On the GPU they live in LDS with a stride of one wavefront (limb i of lane
-// l at base[i * 64 + l]), so that lanes never share a bank.
-// ---------------------------------------------------------------------------
-struct BigRef {
-  uint32_t* base;
-  int n;       // limbs in use (no leading zero limb)
-  int stride;  // distance between limbs (the wavefront size in LDS)
-  FFP_HD uint32_t& operator[](int i) const { return base[i * stride]; }
-};
-
-// x = x * m + a; returns false on overflow of kBigLimbs.
-FFP_HD bool big_mul_add(BigRef& x, uint32_t m, uint32_t a) {
-  uint64_t carry = a;
-  for (int i = 0; i < x.n; ++i) {
-    const uint64_t t = (uint64_t)x[i] * m + carry;
-    x[i] = (uint32_t)t;
-    carry = t >> 32;
-  }
-  if (carry) {
-    if (x.n >= kBigLimbs) return false;
-    x[x.n] = (uint32_t)carry;
-    ++x.n;
-  }
-  return true;
-}
-
-// dst = src * (b1:b0) for a 64-bit multiplier.
-FFP_HD bool big_mul_u64(BigRef& dst, const BigRef& src, uint64_t b) {
-  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-  if (src.n + 2 > kBigLimbs) return false;
-  uint64_t c0 = 0, c1 = 0;
-  // two passes of a 1-limb multiply-accumulate
-  for (int i = 0; i < src.n; ++i) {
-    const uint64_t t = (uint64_t)src[i] * b0 + c0;
-    dst[i] = (uint32_t)t;
-    c0 = t >> 32;
-  }
-  dst[src.n] = (uint32_t)c0;
-  dst[src.n + 1] = 0;
-  if (b1) {
-    for (int i = 0; i < src.n; ++i) {
-      const uint64_t t = (uint64_t)src[i] * b1 + dst[i + 1] + c1;
-      dst[i + 1] = (uint32_t)t;
-      c1 = t >> 32;
-    }
-    dst[src.n + 1] = (uint32_t)c1;
-  }
-  int n = src.n + 2;
-  while (n > 0 && dst[n - 1] == 0) --n;
-  dst.n = n;
-  return true;
-}
-
-// sign(a - (c << s)) for s >= 0, without materialising the shift.
-FFP_HD int big_cmp_shl(const BigRef& a, const BigRef& c, int s) {
-  const int ws = s >> 5, bs = s & 31;
-  const int nc = c.n + ws + 1;
-  int top = a.n > nc ? a.n : nc;
-  for (int i = top - 1; i >= 0; --i) {
-    const uint32_t ai = i < a.n ? a[i] : 0u;
-    const int j = i - ws;
-    uint32_t ci = 0;
-    if (j >= 0 && j < c.n) ci = c[j] << bs;
-    if (bs && j - 1 >= 0 && j - 1 < c.n) ci |= c[j - 1] >> (32 - bs);
-    if (ai != ci) return ai > ci ? 1 : -1;
-  }
-  return 0;
-}
-
-// sign(a * 2^ea - c * 2^ec)
-FFP_HD int big_cmp_pow2(const BigRef& a, int ea, const BigRef& c, int ec) {
-  if (ea >= ec) return -big_cmp_shl(c, a, ea - ec);
-  return big_cmp_shl(a, c, ec - ea);
-}
-
-// ---------------------------------------------------------------------------
 // Decision for one lexed token: Algorithm 1 on w (and on w+1 when digits
 // beyond the 19th were dropped and not all zero, Section 11).
 // ---------------------------------------------------------------------------
@@ -400,20 +322,7 @@ FFP_HD Decision<F> decide_lexed(const Lexed& L, const unsigned long long* table)
 }
 
 // ---------------------------------------------------------------------------
-// Exact fallback for one token (the paper asks for an exact higher-precision
-// method here and leaves the method open, Section 11).
-//
-// The token's first 769 significant digits form the integer P; a nonzero
-// digit beyond them appends a sticky 1, so that v = P * 10^f decides every
-// comparison with a midpoint exactly.  A candidate b comes from Algorithm 1
-// on the first 19 digits; v is then compared with the halfway points
-// (2m+1) * 2^(e-1) between b and its neighbours until b is the nearest value,
-// ties to even.  Encodings are used as integers, so "next value up" is
-// bits + 1 across binades and into infinity.
-//
-// limbs points at 3 * kBigLimbs limbs spaced `stride` apart.  Returns false
-// if a big integer outgrew kBigLimbs (cannot happen for tokens that reach the
-// fallback; reported as an internal error).
+// Significand and binary exponent of an encoding (value = m * 2^e).
 // ---------------------------------------------------------------------------
 template <class F>
 FFP_HD void decode_bits(typename F::bits_t b, uint64_t& m, int& e) {
@@ -426,172 +335,6 @@ FFP_HD void decode_bits(typename F::bits_t b, uint64_t& m, int& e) {
     m = frac | (1ull << F::kMant);
     e = (int)field - F::kBias - F::kMant;
   }
-}
-
-template <class F>
-FFP_HD bool fallback_decide(const GlobalSrc& src, uint64_t pos, const unsigned long long* table,
-                            uint32_t* limbs, int stride, typename F::bits_t& out_bits,
-                            uint32_t& out_status) {
-  using Bits = typename F::bits_t;
-  BigRef X{limbs, 0, stride};                          // P, or P * 5^f when f >= 0
-  BigRef Y{limbs + kBigLimbs * stride, 0, stride};     // 5^-f when f < 0
-  BigRef T{limbs + 2 * kBigLimbs * stride, 0, stride}; // 2m+1 or (2m+1) * 5^-f
-
-  uint32_t c = src(pos);
-  bool neg = false;
-  if (c == '-') {
-    neg = true;
-    c = src(++pos);
-  } else if (c == '+') {
-    c = src(++pos);
-  }
-  uint64_t w = 0;
-  int nw = 0;
-  int64_t dropped_w = 0, dropped = 0, nfrac = 0;
-  int kept = 0;
-  bool sticky = false, in_frac = false;
-  uint32_t chunk = 0, chunk_pow = 1;
-  bool ok = true;
-  for (;;) {
-    if (c == '.' && !in_frac) {
-      in_frac = true;
-      c = src(++pos);
-      continue;
-    }
-    if (!is_digit(c)) break;
-    const uint32_t dg = c - '0';
-    if (in_frac) ++nfrac;
-    if (kept == 0 && dg == 0) {
-      c = src(++pos);
-      continue;
-    }
-    if (nw < 19) {
-      w = w * 10 + dg;
-      ++nw;
-    } else {
-      ++dropped_w;
-    }
-    if (kept < kFallbackDigits) {
-      chunk = chunk * 10 + dg;
-      chunk_pow *= 10;
-      ++kept;
-      if (chunk_pow == 1000000000u) {
-        ok &= big_mul_add(X, chunk_pow, chunk);
-        chunk = 0;
-        chunk_pow = 1;
-      }
-    } else {
-      ++dropped;
-      sticky |= dg != 0;
-    }
-    c = src(++pos);
-  }
-  if (chunk_pow > 1) ok &= big_mul_add(X, chunk_pow, chunk);
-  int64_t e10 = 0;
-  if ((c | 0x20u) == 'e') {
-    c = src(++pos);
-    bool eneg = false;
-    if (c == '-') {
-      eneg = true;
-      c = src(++pos);
-    } else if (c == '+') {
-      c = src(++pos);
-    }
-    while (is_digit(c)) {
-      if (e10 < kExpCap) e10 = e10 * 10 + (c - '0');
-      c = src(++pos);
-    }
-    if (eneg) e10 = -e10;
-  }
-  const int64_t q64 = e10 - nfrac + dropped_w;
-  int64_t f64v = e10 - nfrac + dropped;
-  if (sticky) {
-    ok &= big_mul_add(X, 10, 1);
-    f64v -= 1;
-  }
-
-  Bits bits;
-  uint32_t status = kStOk;
-  if (w == 0) {
-    bits = 0;
-  } else if (q64 < kQMin) {
-    bits = 0;
-    status = kStRange;
-  } else if (q64 > kQMax) {
-    bits = F::kInf;
-    status = kStRange;
-  } else {
-    const int q = (int)q64;
-    const int f = (int)f64v;  // in [q - 750, q] since at most 769 digits are kept
-    bool ab;
-    uint32_t st1;
-    bits = alg1<F>(w, q, table[2 * (q - kQMin)], table[2 * (q - kQMin) + 1], ab, st1);
-    if (f >= 0) {  // X = P * 5^f, v = X * 2^f
-      for (int k = 0; k < f; k += 13) {
-        const int sh = f - k < 13 ? f - k : 13;
-        uint32_t p5 = 1;
-        for (int t = 0; t < sh; ++t) p5 *= 5;
-        ok &= big_mul_add(X, p5, 0);
-      }
-    } else {  // Y = 5^-f, v = P * 2^f / Y
-      Y[0] = 1;
-      Y.n = 1;
-      for (int k = 0; k < -f; k += 13) {
-        const int sh = -f - k < 13 ? -f - k : 13;
-        uint32_t p5 = 1;
-        for (int t = 0; t < sh; ++t) p5 *= 5;
-        ok &= big_mul_add(Y, p5, 0);
-      }
-    }
-    if (bits == F::kInf) bits = F::kInf - 1;
-    for (int iter = 0; iter < 8 && ok; ++iter) {
-      if (bits < F::kInf) {
-        // sign(v - midpoint(bits, bits + 1))
-        uint64_t m;
-        int e;
-        decode_bits<F>(bits, m, e);
-        const uint64_t h = 2 * m + 1;
-        if (f >= 0) {
-          T[0] = (uint32_t)h;
-          T[1] = (uint32_t)(h >> 32);
-          T.n = T[1] ? 2 : 1;
-        } else {
-          ok &= big_mul_u64(T, Y, h);
-        }
-        const int up = big_cmp_pow2(X, f, T, e - 1);
-        if (up > 0 || (up == 0 && (bits & 1))) {
-          bits += 1;
-          if (bits == F::kInf) break;
-          continue;
-        }
-      }
-      if (bits > 0) {
-        // sign(v - midpoint(bits - 1, bits))
-        uint64_t m;
-        int e;
-        decode_bits<F>(bits - 1, m, e);
-        const uint64_t h = 2 * m + 1;
-        if (f >= 0) {
-          T[0] = (uint32_t)h;
-          T[1] = (uint32_t)(h >> 32);
-          T.n = T[1] ? 2 : 1;
-        } else {
-          ok &= big_mul_u64(T, Y, h);
-        }
-        const int dn = big_cmp_pow2(X, f, T, e - 1);
-        if (dn < 0 || (dn == 0 && ((bits - 1) & 1) == 0)) {
-          bits -= 1;
-          continue;
-        }
-      }
-      break;
-    }
-    if (bits == F::kInf || bits == 0) status = kStRange;
-  }
-  if (neg) bits |= F::kSign;
-  out_bits = bits;
-  out_status = status;
-  return ok;
 }
 
 }  // namespace ffp

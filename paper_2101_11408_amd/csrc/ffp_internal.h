@@ -28,10 +28,6 @@ constexpr uint64_t kBlockBytes = 64 * 1024;
 // (Section 11), so 769 digits plus a sticky digit decide every comparison.
 constexpr int kFallbackDigits = 769;
 
-// Limbs (32-bit) of the fallback's big integers: the largest operand is
-// (2m+1) * 5^1093 < 2^2594.
-constexpr int kBigLimbs = 84;
-
 // Maximum buffer size accepted (keeps saturated exponents exact, see the
 // lexer).
 constexpr uint64_t kMaxBytes = 1ull << 47;

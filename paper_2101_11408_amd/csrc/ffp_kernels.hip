@@ -11,13 +11,14 @@
 //               token starts, then one lane per token: lexing (Section 4),
 //               Algorithm 1 (Sections 5-10) and the w / w+1 test for long
 //               significands (Section 11).  Undecided tokens go to a queue;
-//   k_fallback  exact decision for the queued tokens by big-integer
-//               comparison with the halfway points between neighbouring
-//               binary values.
+//   k_fallback  exact decision for the queued tokens, one wavefront per
+//               token: big-integer comparison with the halfway points
+//               between neighbouring binary values.
 // No workgroup ever waits for another one.
 #include <hip/hip_runtime.h>
 
 #include "ffp_device.h"
+#include "ffp_fallback.h"
 #include "ffp_internal.h"
 #include "ffp_kernels.h"
 #include "ffp_table.inc"
@@ -688,38 +689,40 @@ __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
 }
 
 // ---------------------------------------------------------------------------
-// k_fallback: one lane per queued token (see fallback_decide); each lane keeps
-// its three big integers in LDS, limbs one wavefront apart.
+// k_fallback: one wavefront per queued token (fb_decide), wavefronts striding
+// over the queue.
 // ---------------------------------------------------------------------------
-constexpr int kFbThreads = kWave;
+constexpr int kFbThreads = 256;
+constexpr int kFbWaves = kFbThreads / kWave;
 
 template <class F>
-__device__ void fallback_token(const JobDesc& job, uint64_t pos, uint64_t idx,
-                               const DelimSet& delim, DeviceState* st, uint32_t* lds) {
+__device__ __forceinline__ void fallback_token(const JobDesc& job, uint64_t pos, uint64_t idx,
+                                               FbLds* lds) {
   typename F::bits_t bits;
   uint32_t status;
-  const GlobalSrc src{job.text, job.nbytes, delim};
-  if (!fallback_decide<F>(src, pos, g_table, lds, kWave, bits, status))
-    atomicOr(&st->error, (unsigned)kDevInternal);
-  gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, bits);
-  gstore(job.status + idx, (uint8_t)status);
+  fb_decide<F>(job.text, job.nbytes, pos, g_table, lds, bits, status);
+  if (fb_lane() == 0) {
+    gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, bits);
+    gstore(job.status + idx, (uint8_t)status);
+  }
 }
 
 __global__ __launch_bounds__(kFbThreads) void k_fallback(FallbackParams P) {
-  __shared__ uint32_t lds[3 * kBigLimbs * kWave];
+  __shared__ FbLds lds[kFbWaves];
   const unsigned long long tail = P.st->queue_tail;
   const uint64_t n = tail < P.queue_cap ? tail : P.queue_cap;
-  uint32_t* mine = lds + threadIdx.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * kFbThreads + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * kFbThreads) {
+  const int wid = threadIdx.x / kWave;
+  const uint64_t stride = (uint64_t)gridDim.x * kFbWaves;
+  for (uint64_t i = (uint64_t)blockIdx.x * kFbWaves + wid; i < n; i += stride) {
     const QueueEntry e = P.queue[i];
     const uint32_t job_id = (uint32_t)(e.index_job >> 48);
     const uint64_t idx = e.index_job & ((1ull << 48) - 1);
     const JobDesc job = P.js.jobs ? P.js.jobs[job_id] : P.js.single;
+    fb_wave_sync();  // the previous token's LDS reads are done
     if (job.dtype == kF64) {
-      fallback_token<F64>(job, e.offset, idx, P.delim, P.st, mine);
+      fallback_token<F64>(job, e.offset, idx, &lds[wid]);
     } else {
-      fallback_token<F32>(job, e.offset, idx, P.delim, P.st, mine);
+      fallback_token<F32>(job, e.offset, idx, &lds[wid]);
     }
   }
 }

@@ -17,6 +17,8 @@
 #include <time.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -517,6 +519,59 @@ int ffp_server_stats_read(ffp_server* srv, ffp_server_stats* out) {
   out->scratch_bytes = srv->scratch_bytes;
   out->max_batch_seen = srv->max_batch_seen;
   return FFP_SUCCESS;
+}
+
+int ffp_server_replay(ffp_server* srv, const ffp_replay_request* reqs, uint64_t n,
+                      ffp_replay_result* out) {
+  if (!srv || (n && (!reqs || !out))) return FFP_E_ARG;
+  std::vector<uint64_t> tickets(n, 0);
+  std::atomic<uint64_t> submitted{0};
+  std::atomic<bool> stop{false};
+  std::thread collector([&] {
+    for (uint64_t i = 0; i < n; ++i) {
+      while (submitted.load(std::memory_order_acquire) <= i) {
+        if (stop.load(std::memory_order_acquire)) return;
+        std::this_thread::yield();
+      }
+      ffp_result r;
+      ffp_replay_result& o = out[i];
+      if (ffp_server_wait(srv, tickets[i], &r) == FFP_SUCCESS) {
+        o.t_arrive_ns = r.t_arrive_ns;
+        o.t_launch_ns = r.t_launch_ns;
+        o.t_done_ns = r.t_done_ns;
+        o.count = r.count;
+        o.err = r.err;
+        o.batch_jobs = r.batch_jobs;
+      } else {
+        o = ffp_replay_result{};
+        o.err = FFP_E_ARG;
+      }
+      (void)ffp_server_release(srv, tickets[i]);
+    }
+  });
+  int rc = FFP_SUCCESS;
+  for (uint64_t i = 0; i < n && rc == FFP_SUCCESS; ++i) {
+    const uint64_t t = reqs[i].arrival_ns;
+    for (;;) {
+      const uint64_t now = now_ns();
+      if (now >= t) break;
+      if (t - now > 300000) std::this_thread::sleep_for(std::chrono::nanoseconds(t - now - 200000));
+    }
+    uint64_t tk = 0;
+    for (;;) {
+      rc = ffp_server_submit(srv, reqs[i].text, reqs[i].nbytes, reqs[i].on_device, reqs[i].dtype,
+                             t, &tk);
+      if (rc != FFP_E_BUSY) break;
+      std::this_thread::yield();
+    }
+    if (rc == FFP_SUCCESS) {
+      tickets[i] = tk;
+      submitted.store(i + 1, std::memory_order_release);
+    }
+  }
+  stop.store(true, std::memory_order_release);
+  collector.join();
+  return rc;
 }
 
 void ffp_server_destroy(ffp_server* srv) {

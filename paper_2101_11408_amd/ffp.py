@@ -69,6 +69,18 @@ class ffp_result(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class ffp_replay_request(ctypes.Structure):
+    _fields_ = [("text", ctypes.c_void_p), ("nbytes", ctypes.c_uint64),
+                ("on_device", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("arrival_ns", ctypes.c_uint64)]
+
+
+class ffp_replay_result(ctypes.Structure):
+    _fields_ = [("t_arrive_ns", ctypes.c_uint64), ("t_launch_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("count", ctypes.c_uint64),
+                ("err", ctypes.c_int32), ("batch_jobs", ctypes.c_uint32)]
+
+
 class ffp_server_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("submitted", "completed", "batches", "bytes", "arena_bytes",
@@ -112,6 +124,7 @@ _SIGNATURES = {
     "ffp_server_release": (_INT, [_P, _U64]),
     "ffp_server_stats_read": (_INT, [_P, _c.POINTER(ffp_server_stats)]),
     "ffp_server_destroy": (None, [_P]),
+    "ffp_server_replay": (_INT, [_P, _P, _U64, _P]),
 }
 
 _lib = None
@@ -437,6 +450,28 @@ class Server:
 
     def release(self, ticket):
         check(load().ffp_server_release(self.handle, ticket), "release")
+
+    def replay(self, ptrs, sizes, on_device, dtypes, arrival_ns):
+        """Replays an arrival trace (ffp_server_replay); returns a numpy
+        structured array of per-request results."""
+        import numpy as np
+        n = len(ptrs)
+        req = np.zeros(n, dtype=np.dtype([("text", "<u8"), ("nbytes", "<u8"),
+                                          ("on_device", "<i4"), ("dtype", "<i4"),
+                                          ("arrival_ns", "<u8")]))
+        req["text"] = ptrs
+        req["nbytes"] = sizes
+        req["on_device"] = on_device
+        req["dtype"] = dtypes
+        req["arrival_ns"] = arrival_ns
+        out = np.zeros(n, dtype=np.dtype([("t_arrive_ns", "<u8"), ("t_launch_ns", "<u8"),
+                                          ("t_done_ns", "<u8"), ("count", "<u8"),
+                                          ("err", "<i4"), ("batch_jobs", "<u4")]))
+        assert req.itemsize == ctypes.sizeof(ffp_replay_request)
+        assert out.itemsize == ctypes.sizeof(ffp_replay_result)
+        check(load().ffp_server_replay(self.handle, req.ctypes.data, n, out.ctypes.data),
+              "ffp_server_replay")
+        return out
 
     def stats(self):
         st = ffp_server_stats()

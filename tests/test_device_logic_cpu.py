@@ -1,7 +1,8 @@
-"""The library's per-token logic (ffp_device.h: lexer, Algorithm 1, the
-w / w+1 test and the exact big-integer fallback), compiled for the host and
-compared bit for bit with the oracle.  No GPU involved; the tile scan and
-the kernels themselves are covered by the GPU tests."""
+"""The library's per-token logic (ffp_device.h: lexer, Algorithm 1 and the
+w / w+1 test), compiled for the host and compared bit for bit with the
+oracle on every token it decides.  Tokens it sends to the exact fallback (a
+wavefront-cooperative GPU kernel) carry status 255 and are counted; they,
+the tile scan and the kernels themselves are covered by the GPU tests."""
 
 import os
 import subprocess
@@ -56,7 +57,9 @@ def check(exe, buf, fmt, label, **kw):
     assert len(bits) == len(wb), label
     wb = np.array(wb, dtype=np.uint64)
     ws = np.array(ws, dtype=np.uint8)
-    bad = np.flatnonzero((bits != wb) | (st != ws))
+    decided = st != 255
+    assert int((~decided).sum()) == nfb, label
+    bad = np.flatnonzero(decided & ((bits != wb) | (st != ws)))
     if bad.size:
         toks = [t for t in buf.split(b"\n") if t] if kw.get("delims", b"\n") == b"\n" else None
         i = int(bad[0])

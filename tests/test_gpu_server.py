@@ -256,3 +256,27 @@ def test_inflight_limit_and_detach(ctx, ffpmod, pool):
         assert srv.stats()["completed"] == 3
     finally:
         srv.close()
+
+
+def test_replay_trace(ctx, ffpmod, pool, reference):
+    """ffp_server_replay: open-loop arrivals submitted and collected by native
+    threads; every request completes with the count it has alone."""
+    reqs, alone = reference
+    _, dev, pinned = pool
+    rng = np.random.default_rng(21)
+    arrive = np.cumsum(rng.exponential(100e-6, size=len(reqs))) * 1e9
+    ptrs = [(dev if q[2] else pinned)[q[0]:].data_ptr() if q[1] else 0 for q in reqs]
+    srv = ffpmod.Server(ctx, hbm_budget_bytes=2 << 30, max_batch_bytes=64 << 20,
+                        max_batch_jobs=32)
+    try:
+        base = ffpmod.clock_ns() + 5_000_000
+        out = srv.replay(ptrs, [q[1] for q in reqs], [1 if q[2] else 0 for q in reqs],
+                         [q[3] for q in reqs], (base + arrive).astype(np.uint64))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert (out["err"] == 0).all()
+    assert list(out["count"]) == [a[0] for a in alone]
+    assert (out["t_done_ns"] >= out["t_launch_ns"]).all()
+    assert (out["t_launch_ns"] >= out["t_arrive_ns"]).all()
+    assert st["completed"] == len(reqs)
