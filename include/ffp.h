@@ -199,12 +199,16 @@ int ffp_batch_graph_launch(ffp_graph* g, void* stream);
 void ffp_batch_graph_destroy(ffp_graph* g);
 
 /* Launch schedule of the parse kernel: tile bytes per workgroup step
- * (4096 * tile_k, tile_k in {1, 2, 4}) and resident workgroups per CU
- * (1 .. the occupancy limit; 0 = the limit). */
+ * (4096 * tile_k, tile_k in {1, 2, 4}), resident workgroups per CU
+ * (1 .. the occupancy limit; 0 = the limit) and the block size in KiB
+ * (4, 16 or 64; 0 = chosen per call: the largest block that still gives
+ * every parse workgroup two blocks, so that small inputs spread over many
+ * workgroups).  A call never uses tiles larger than its blocks. */
 typedef struct ffp_tuning {
     int32_t tile_k;
     int32_t blocks_per_cu;
-    int32_t reserved[2];
+    int32_t block_kib;
+    int32_t reserved;
 } ffp_tuning;
 
 int ffp_get_tuning(ffp_ctx* ctx, ffp_tuning* out);

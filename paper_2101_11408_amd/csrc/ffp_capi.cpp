@@ -57,7 +57,7 @@ int grow_array(T** p, uint64_t* cap, uint64_t need) {
 int grow(ffp_ctx* ctx, uint64_t bytes, uint64_t njobs) {
   // every job may start 15 bytes into its first block and end in a partial
   // block; one more entry holds the grand total
-  const uint64_t blocks = (bytes + 15 * njobs) / ffp::kBlockBytes + 2 * njobs + 1;
+  const uint64_t blocks = ((bytes + 15 * njobs) >> ffp::kMinBlockShift) + 2 * njobs + 1;
   // A token that reaches the fallback through the w / w+1 test has more than
   // 19 significant digits, hence at least 20 bytes plus a delimiter (except
   // the last token of a job): (bytes + njobs) / 21 bounds their number.  The
@@ -73,16 +73,51 @@ int grow(ffp_ctx* ctx, uint64_t bytes, uint64_t njobs) {
   return rc;
 }
 
-int parse_grid(const ffp_ctx* ctx) {
+// Launch shape of one call: block size, tile size and workgroups.
+struct CallShape {
+  uint32_t block_shift;
+  int tile_k;
+  int grid;  // parse workgroups before clipping to the block count
+};
+
+// The largest block (64, 16 or 4 KiB) that still gives every parse
+// workgroup two blocks; small inputs get small blocks (and tiles no larger
+// than a block) so that they spread over many workgroups.
+CallShape call_shape(const ffp_ctx* ctx, uint64_t bytes) {
+  CallShape cs{};
+  int k = ctx->tile_k;
   int bpc = ctx->blocks_per_cu;
-  const int lim = ctx->max_bpc[ctx->tile_k];
-  if (bpc < 1 || bpc > lim) bpc = lim;
-  return ctx->num_cus * (bpc < 1 ? 1 : bpc);
+  auto grid_for = [&](int kk, int b) {
+    const int lim = ctx->max_bpc[kk];
+    if (b < 1 || b > lim) b = lim;
+    return ctx->num_cus * (b < 1 ? 1 : b);
+  };
+  uint32_t shift = ffp::kMinBlockShift;
+  if (ctx->block_kib) {
+    shift = ctx->block_kib == 64 ? 16 : ctx->block_kib == 16 ? 14 : 12;
+  } else {
+    const uint64_t g = (uint64_t)grid_for(k, bpc);
+    for (uint32_t sh = ffp::kMaxBlockShift; sh > ffp::kMinBlockShift; sh -= 2) {
+      if ((bytes >> sh) >= 2 * g) {
+        shift = sh;
+        break;
+      }
+    }
+  }
+  while (k > 1 && (4096u * (uint32_t)k) > (1u << shift)) {
+    k >>= 1;
+    bpc = 0;  // the tuned count belongs to the larger tile
+  }
+  cs.block_shift = shift;
+  cs.tile_k = k;
+  cs.grid = grid_for(k, bpc);
+  return cs;
 }
 
 // count -> scan -> parse -> fallback for a job set whose block count is
 // `nblocks` (plain calls) or on the device (batched calls, nblocks = ~0).
-int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, uint64_t nblocks, hipStream_t s) {
+int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uint64_t nblocks,
+                hipStream_t s) {
   ffp::ScanParams sp{};
   sp.js = js;
   sp.block_sum = ctx->d_block_sum;
@@ -108,7 +143,7 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, uint64_t nblocks, hipStream
   P.delim = ctx->delim;
   P.flags = ctx->flags;
   P.count_paths = ctx->counters ? 1u : 0u;
-  uint64_t grid = (uint64_t)parse_grid(ctx);
+  uint64_t grid = (uint64_t)shape.grid;
   if (grid > nblocks) grid = nblocks;
 
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
@@ -122,7 +157,7 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, uint64_t nblocks, hipStream
     }
     if (hipEventRecord(ev.first, s) != hipSuccess) return FFP_E_HIP;
   }
-  if (ffp::launch_parse(ctx->tile_k, ctx->delim.single != 0, P, (int)grid, s) != hipSuccess)
+  if (ffp::launch_parse(shape.tile_k, ctx->delim.single != 0, P, (int)grid, s) != hipSuccess)
     return FFP_E_HIP;
   if (ctx->timing) {
     if (hipEventRecord(ev.second, s) != hipSuccess) return FFP_E_HIP;
@@ -161,17 +196,19 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   job.block_begin = 0;
   job.dtype = dtype;
   job.job_id = 0;
+  const CallShape shape = call_shape(ctx, nbytes);
   // blocks start at the 16-byte boundary at or below d_text
   const uint64_t vbytes = nbytes ? nbytes + ((uintptr_t)d_text & 15u) : 0;
-  const uint64_t nblocks = (vbytes + ffp::kBlockBytes - 1) / ffp::kBlockBytes;
+  const uint64_t nblocks = (vbytes + (1ull << shape.block_shift) - 1) >> shape.block_shift;
 
   ffp::JobSet js{};
   js.single = job;
   js.jobs = nullptr;
   js.njobs = 1;
+  js.block_shift = shape.block_shift;
   js.total_blocks = nblocks;
   js.total_blocks_dev = nullptr;
-  return launch_jobs(ctx, js, nblocks, (hipStream_t)stream);
+  return launch_jobs(ctx, js, shape, nblocks, (hipStream_t)stream);
 }
 
 int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
@@ -182,9 +219,11 @@ int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_tot
   // at least two jobs' worth of job table, so that grow() sizes it
   int rc = grow(ctx, max_total_bytes, njobs < 2 ? 2 : njobs);
   if (rc != FFP_SUCCESS) return rc;
+  const CallShape shape = call_shape(ctx, max_total_bytes);
   ffp::PrepParams pp{};
   pp.user = reinterpret_cast<ffp::UserJob*>(d_jobs);
   pp.njobs = njobs;
+  pp.block_shift = shape.block_shift;
   pp.jobs = ctx->d_jobs;
   pp.st = ctx->d_state;
   pp.block_cap = ctx->block_cap - 1;
@@ -193,11 +232,12 @@ int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_tot
   ffp::JobSet js{};
   js.jobs = ctx->d_jobs;
   js.njobs = njobs;
+  js.block_shift = shape.block_shift;
   js.total_blocks = 0;
   js.total_blocks_dev = reinterpret_cast<const uint64_t*>(&ctx->d_state->total_blocks);
   // grids are sized for the largest batch the scratch allows; kernels read
   // the true block count on the device
-  return launch_jobs(ctx, js, ctx->block_cap - 1, s);
+  return launch_jobs(ctx, js, shape, ctx->block_cap - 1, s);
 }
 
 int64_t finish_sync(ffp_ctx* ctx, int rc, uint64_t capacity, uint64_t* d_count, void* stream) {
@@ -293,6 +333,7 @@ int ctx_clone(const ffp_ctx* src, ffp_ctx** out) {
   if (rc != FFP_SUCCESS) return rc;
   (*out)->tile_k = src->tile_k;
   (*out)->blocks_per_cu = src->blocks_per_cu;
+  (*out)->block_kib = src->block_kib;
   return FFP_SUCCESS;
 }
 
@@ -519,6 +560,7 @@ int ffp_get_tuning(ffp_ctx* ctx, ffp_tuning* out) {
   memset(out, 0, sizeof *out);
   out->tile_k = ctx->tile_k;
   out->blocks_per_cu = ctx->blocks_per_cu;
+  out->block_kib = ctx->block_kib;
   return FFP_SUCCESS;
 }
 
@@ -526,6 +568,9 @@ int ffp_set_tuning(ffp_ctx* ctx, const ffp_tuning* t) {
   if (!ctx || !t) return FFP_E_ARG;
   if (t->tile_k != 1 && t->tile_k != 2 && t->tile_k != 4) return FFP_E_ARG;
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > ctx->max_bpc[t->tile_k]) return FFP_E_ARG;
+  if (t->block_kib != 0 && t->block_kib != 4 && t->block_kib != 16 && t->block_kib != 64)
+    return FFP_E_ARG;
+  ctx->block_kib = t->block_kib;
   ctx->tile_k = t->tile_k;
   ctx->blocks_per_cu = t->blocks_per_cu == 0 ? ctx->max_bpc[t->tile_k] : t->blocks_per_cu;
   return FFP_SUCCESS;

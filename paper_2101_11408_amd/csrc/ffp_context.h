@@ -24,6 +24,7 @@ struct ffp_ctx {
   std::string arch;
   int tile_k = 4;
   int blocks_per_cu = 1;        // chosen schedule
+  int block_kib = 0;            // 0: chosen per call from its size
   int max_bpc[5] = {0, 0, 0, 0, 0};  // occupancy limit per tile_k
   int fb_grid = 0;
 

@@ -16,12 +16,13 @@ constexpr int kWave = 64;
 // decided by the fallback kernel; never visible after a completed call.
 constexpr uint8_t kPending = 3;
 
-// The text of a job is cut into blocks of kBlockBytes (counted from the
-// 16-byte boundary at or below its first byte).  The count kernel gives the
-// number of tokens starting in each block, a scan turns those into the index
-// of each block's first token, and the parse kernel walks a block in tiles of
-// kThreads * kChunk * K bytes.
-constexpr uint64_t kBlockBytes = 64 * 1024;
+// The text of a job is cut into blocks of 2^block_shift bytes (4, 16 or
+// 64 KiB, chosen per call; counted from the 16-byte boundary at or below the
+// job's first byte).  The count kernel gives the number of tokens starting in
+// each block, a scan turns those into the index of each block's first token,
+// and the parse kernel walks a block in tiles of kThreads * kChunk * K bytes.
+constexpr int kMinBlockShift = 12;
+constexpr int kMaxBlockShift = 16;
 
 // Significant decimal digits kept by the exact fallback.  Any midpoint
 // between neighbouring binary64 values needs at most 768 significant digits
@@ -89,7 +90,7 @@ struct JobSet {
   JobDesc single;
   const JobDesc* jobs;      // null for plain calls
   uint32_t njobs;
-  uint32_t pad;
+  uint32_t block_shift;
   uint64_t total_blocks;             // plain calls
   const uint64_t* total_blocks_dev;  // batched calls
 };
@@ -109,7 +110,7 @@ struct UserJob {
 struct PrepParams {
   UserJob* user;
   uint32_t njobs;
-  uint32_t pad;
+  uint32_t block_shift;
   JobDesc* jobs;
   DeviceState* st;
   uint64_t block_cap;  // blocks the scratch can hold

@@ -94,10 +94,10 @@ __device__ __forceinline__ uint64_t total_blocks_of(const JobSet& js) {
 }
 
 // Blocks of a job: its text starts `align` bytes into the first block.
-__device__ __forceinline__ uint64_t job_blocks(const JobDesc& job) {
+__device__ __forceinline__ uint64_t job_blocks(const JobDesc& job, uint32_t shift) {
   if (job.nbytes == 0) return 0;
   const uint64_t vend = job.nbytes + ((uint64_t)(uintptr_t)job.text & 15u);
-  return (vend + kBlockBytes - 1) / kBlockBytes;
+  return (vend + (1ull << shift) - 1) >> shift;
 }
 
 // High bit of each byte of x set for non-delimiter bytes (single delimiter
@@ -171,14 +171,14 @@ __device__ __forceinline__ uint32_t prev_nondelim(const uint8_t* vbase, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// k_count: tokens starting in each block.  Each thread classifies 16 chunks
-// of 16 bytes; the start mask of a chunk needs the last bit of the chunk
-// before it, exchanged through LDS.
+// k_count: tokens starting in each block.  Each thread classifies kRows
+// chunks of 16 bytes (kRows = block bytes / 4 KiB); the start mask of a chunk
+// needs the last bit of the chunk before it, exchanged through LDS.
 // ---------------------------------------------------------------------------
-constexpr int kCountRows = (int)(kBlockBytes / (kThreads * kChunk));  // 16
-
-template <bool kSingle>
+template <bool kSingle, int kRows>
 __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
+  constexpr int kCountRows = kRows;
+  constexpr uint32_t kShift = kRows == 1 ? 12 : (kRows == 4 ? 14 : 16);
   __shared__ uint16_t s_nd[kCountRows * kThreads];
   __shared__ uint8_t s_lut[256];
   __shared__ uint32_t s_scan[kThreads / kWave];
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
     const uint64_t align = (uint64_t)(uintptr_t)job.text & 15u;
     const uint8_t* vbase = job.text - align;
     const uint64_t vend = job.nbytes + align;
-    const uint64_t bstart = (b - job.block_begin) * kBlockBytes;
+    const uint64_t bstart = (b - job.block_begin) << kShift;
     __syncthreads();  // s_nd / s_prev of the previous block are consumed
     uint32_t m[kCountRows];
 #pragma unroll
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
   const uint32_t nj = P.js.jobs ? P.js.njobs : 1;
   for (uint32_t j = tid; j < nj; j += kScanThreads) {
     const JobDesc job = P.js.jobs ? P.js.jobs[j] : P.js.single;
-    const uint64_t b0 = job.block_begin, b1 = b0 + job_blocks(job);
+    const uint64_t b0 = job.block_begin, b1 = b0 + job_blocks(job, P.js.block_shift);
     const uint64_t count = P.block_sum[b1] - P.block_sum[b0];
     *job.count_out = count;
     if (job.err_out && count > job.capacity) *job.err_out = kErrCapacity;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kScanThreads) void k_prep(PrepParams P) {
                     (u.capacity == 0 || (u.values != nullptr && u.status != nullptr));
     const uint64_t nb = ok ? u.nbytes : 0;
     const uint64_t vend = nb ? nb + ((uint64_t)(uintptr_t)u.text & 15u) : 0;
-    const uint64_t blocks = (vend + kBlockBytes - 1) / kBlockBytes;
+    const uint64_t blocks = (vend + (1ull << P.block_shift) - 1) >> P.block_shift;
     __syncthreads();  // carries of the previous round are final
     const uint64_t cb = s_carry_blocks, cbytes = s_carry_bytes;
     uint64_t tot_blocks, tot_bytes;
@@ -347,7 +347,6 @@ template <int K>
 struct TileSmem {
   static constexpr int kBytes = kThreads * kChunk * K;
   static constexpr int kChunks = kThreads * K;
-  static constexpr int kTiles = (int)(kBlockBytes / kBytes);
   // The fast lexer reads up to 24 bytes before and 36 bytes after a token
   // start; the pads keep those reads inside the array (their contents are
   // masked off).
@@ -548,6 +547,8 @@ __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
   }
   const uint32_t drep = P.delim.byte * 0x01010101u;
   const uint64_t nblk = total_blocks_of(P.js);
+  // tiles per block (the host keeps blocks at least one tile long)
+  const int ntiles = (int)((1u << P.js.block_shift) / S::kBytes);
   // path counters, kept in scalars (a runtime-indexed array would live in
   // scratch memory)
   uint32_t c_tok = 0, c_inv = 0, c_early = 0, c_one = 0, c_two = 0, c_fb = 0;
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
     const uint8_t* vbase = job.text - align;
     const uint64_t nbytes = job.nbytes;
     const uint64_t vend = nbytes + align;
-    const uint64_t bstart = (blk - job.block_begin) * kBlockBytes;
+    const uint64_t bstart = (blk - job.block_begin) << P.js.block_shift;
     uint64_t next_idx = P.block_prefix[blk] - P.block_prefix[job.block_begin];
     const GlobalSrc gsrc{job.text, nbytes, P.delim};
 
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
     for (int c = 0; c < K; ++c)
       pre[c] = load_chunk(vbase, bstart + (uint64_t)(c * kThreads + tid) * kChunk, align, vend,
                           P.delim.byte);
-    for (int t = 0; t < S::kTiles; ++t) {
+    for (int t = 0; t < ntiles; ++t) {
       const uint64_t tile_start = bstart + (uint64_t)t * S::kBytes;  // virtual
       if (tile_start >= vend) break;
       __syncthreads();  // LDS of the previous tile is consumed
@@ -588,7 +589,7 @@ __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
                                                 digit_word(v.z), digit_word(v.w));
       }
       const uint64_t next_start = tile_start + S::kBytes;
-      if (t + 1 < S::kTiles && next_start < vend) {
+      if (t + 1 < ntiles && next_start < vend) {
 #pragma unroll
         for (int c = 0; c < K; ++c)
           pre[c] = load_chunk(vbase, next_start + (uint64_t)(c * kThreads + tid) * kChunk, align,
@@ -747,11 +748,21 @@ hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu) {
   }
 }
 
-hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipStream_t s) {
+template <int kRows>
+static void launch_count_rows(bool single_delim, const CountParams& P, int grid, hipStream_t s) {
   if (single_delim)
-    hipLaunchKernelGGL((k_count<true>), dim3(grid), dim3(kThreads), 0, s, P);
+    hipLaunchKernelGGL((k_count<true, kRows>), dim3(grid), dim3(kThreads), 0, s, P);
   else
-    hipLaunchKernelGGL((k_count<false>), dim3(grid), dim3(kThreads), 0, s, P);
+    hipLaunchKernelGGL((k_count<false, kRows>), dim3(grid), dim3(kThreads), 0, s, P);
+}
+
+hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipStream_t s) {
+  switch (P.js.block_shift) {
+    case 12: launch_count_rows<1>(single_delim, P, grid, s); break;
+    case 14: launch_count_rows<4>(single_delim, P, grid, s); break;
+    case 16: launch_count_rows<16>(single_delim, P, grid, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

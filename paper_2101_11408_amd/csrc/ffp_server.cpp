@@ -197,7 +197,11 @@ struct ffp_server {
       if (use_graph) {
         if (hipGraphLaunch(s.exec, s.stream) != hipSuccess) return FFP_E_HIP;
       } else {
-        const int rc = ffp::ctx_batch(s.ctx, s.d_jobs, n, max_batch_bytes, s.stream);
+        // the batch's own size picks the block size (small batches spread
+        // over many workgroups)
+        uint64_t bytes = 0;
+        for (const Req* r : s.reqs) bytes += r->nbytes;
+        const int rc = ffp::ctx_batch(s.ctx, s.d_jobs, n, bytes, s.stream);
         if (rc != FFP_SUCCESS) return rc;
       }
     }

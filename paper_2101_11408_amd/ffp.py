@@ -50,7 +50,7 @@ class ffp_job(ctypes.Structure):
 
 class ffp_tuning(ctypes.Structure):
     _fields_ = [("tile_k", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("block_kib", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ffp_server_options(ctypes.Structure):
@@ -293,8 +293,8 @@ class Context:
         check(load().ffp_get_tuning(self.handle, ctypes.byref(t)))
         return t.tile_k, t.blocks_per_cu
 
-    def set_tuning(self, tile_k, blocks_per_cu=0):
-        t = ffp_tuning(tile_k, blocks_per_cu)
+    def set_tuning(self, tile_k, blocks_per_cu=0, block_kib=0):
+        t = ffp_tuning(tile_k, blocks_per_cu, block_kib)
         check(load().ffp_set_tuning(self.handle, ctypes.byref(t)), "ffp_set_tuning")
 
     def autotune_batch(self, d_jobs, njobs, max_total_bytes, stream=None):

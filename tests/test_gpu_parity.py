@@ -34,10 +34,12 @@ def ctx(ffpmod):
     c.close()
 
 
-def run_gpu(ctx, buf: bytes, fmt: str, capacity=None):
+def run_gpu(ctx, buf: bytes, fmt: str, capacity=None, offset=0):
+    """Parses buf on the GPU; with offset > 0 the device text starts that many
+    bytes past an allocation boundary."""
     dev = torch.device("cuda", 0)
-    text = torch.frombuffer(bytearray(buf), dtype=torch.uint8).to(dev) if buf else \
-        torch.empty(0, dtype=torch.uint8, device=dev)
+    text = torch.frombuffer(bytearray(b"\n" * offset + buf), dtype=torch.uint8).to(dev)[offset:] \
+        if buf else torch.empty(0, dtype=torch.uint8, device=dev)
     dt = torch.float64 if fmt == "f64" else torch.float32
     if capacity is None:
         capacity = len(buf) // 2 + 1
@@ -142,6 +144,40 @@ def test_tile_sizes(ffpmod, tile_k):
         buf = W.join_tokens(toks)
         compare_full(c, buf, "f64", "tile-k%d" % tile_k)
         compare_full(c, buf, "f32", "tile-k%d" % tile_k)
+    finally:
+        c.close()
+
+
+@pytest.fixture(scope="module")
+def ragged_blocks_case():
+    """About 1.4 MB of mixed and hard tokens behind runs of 1-3 delimiters,
+    starting 3 bytes into the buffer, with the oracle's answer."""
+    rng = np.random.default_rng(12)
+    toks = W.mixed_tokens(rng, 50_000) + W.hard_tokens(rng, 1500)
+    rng.shuffle(toks)
+    seps = rng.integers(1, 4, size=len(toks))
+    buf = b"7\n\n" + b"".join(t.encode() + b"\n" * int(k) for t, k in zip(toks, seps))
+    buf = buf[3:]
+    return buf, {fmt: parse_buffer(buf, fmt) for fmt in ("f64", "f32")}
+
+
+@pytest.mark.parametrize("block_kib,tile_k", [(4, 1), (16, 1), (16, 2), (16, 4), (64, 1),
+                                              (64, 2), (64, 4)])
+def test_block_sizes(ffpmod, ragged_blocks_case, block_kib, tile_k):
+    """Every block size with every tile size that fits it, forced through the
+    tuning call; parse and batched calls."""
+    buf, want = ragged_blocks_case
+    c = ffpmod.Context(0)
+    try:
+        c.set_tuning(tile_k, 0, block_kib)
+        for fmt in ("f64", "f32"):
+            _log("case blocks", block_kib, "tile_k", tile_k, fmt)
+            rc, n, bits, status = run_gpu(c, buf, fmt, offset=5)
+            wb, ws = want[fmt]
+            assert rc == len(wb) and n == len(wb)
+            dt = np.uint64 if fmt == "f64" else np.uint32
+            assert np.array_equal(bits[:n], np.array(wb, dtype=dt)), (block_kib, tile_k, fmt)
+            assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8))
     finally:
         c.close()
 
