@@ -338,8 +338,20 @@ def serve_once(ffp, ctx, reqs, on_device, opts):
         srv.close()
     bad = np.flatnonzero(out["err"] != 0)
     assert bad.size == 0, ("request errors", bad[:5], out["err"][bad[:5]])
-    lat = out["t_done_ns"].astype(np.int64) - out["t_arrive_ns"].astype(np.int64)
-    span = (int(out["t_done_ns"].max()) - int(out["t_arrive_ns"].min())) / 1e9
+    ta = out["t_arrive_ns"].astype(np.int64)
+    td = out["t_done_ns"].astype(np.int64)
+    lat = td - ta
+    exp = (base + arrive).astype(np.int64)
+    off = np.flatnonzero(ta != exp)
+    if off.size:
+        log("arrival mismatch at %d requests, first %s: got %d want %d (done %d launch %d "
+            "count %d err %d)" % (off.size, off[:5].tolist(), int(ta[off[0]]), int(exp[off[0]]),
+                                  int(td[off[0]]), int(out["t_launch_ns"][off[0]]),
+                                  int(out["count"][off[0]]), int(out["err"][off[0]])))
+    log("  arrivals %d..%d done %d..%d max latency %.1f us at %d"
+        % (int(ta.min()) - int(base), int(ta.max()) - int(base), int(td.min()) - int(base),
+           int(td.max()) - int(base), lat.max() / 1e3, int(lat.argmax())))
+    span = (int(td.max()) - int(ta.min())) / 1e9
     return lat, out["count"].astype(np.int64), out["batch_jobs"], span, st
 
 

@@ -180,8 +180,9 @@ typedef struct ffp_job {
     uint64_t count;       /* out: true number of tokens */
     int32_t dtype;        /* FFP_DTYPE_F64 or FFP_DTYPE_F32 */
     int32_t err;          /* out: FFP_SUCCESS, FFP_E_CAPACITY (count >
-                             capacity, or max_total_bytes exceeded) or
-                             FFP_E_ARG (unknown dtype) */
+                             capacity, or max_total_bytes exceeded),
+                             FFP_E_ARG (unknown dtype) or FFP_E_QUEUE (the
+                             fallback queue overflowed on this job) */
 } ffp_job;
 
 int ffp_parse_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,

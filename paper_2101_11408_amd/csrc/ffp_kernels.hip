@@ -77,6 +77,7 @@ __device__ __forceinline__ T block_excl_scan(T v, T& total, T* s_tmp) {
 // Public error codes written into job records (include/ffp.h).
 constexpr int32_t kErrArg = -1;       // FFP_E_ARG
 constexpr int32_t kErrCapacity = -2;  // FFP_E_CAPACITY
+constexpr int32_t kErrQueue = -7;     // FFP_E_QUEUE
 
 // Job that owns global block b.
 __device__ __forceinline__ JobDesc job_of_block(const JobSet& js, uint64_t b) {
@@ -518,6 +519,7 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
       P.queue[slot] = e;
     } else {
       atomicOr(&P.st->error, (unsigned)kDevQueue);
+      if (job.err_out) *job.err_out = kErrQueue;
     }
     st = kPending;
   }

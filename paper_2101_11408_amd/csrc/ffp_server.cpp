@@ -4,11 +4,11 @@
 // whenever a stream is free, the dispatcher admits requests from the head of
 // the queue while their memory fits the free part of the arena (first fit
 // over address-ordered free ranges), stages host text with an async copy,
-// uploads the batch's job records and queues one batched parse on that
-// stream, followed by the copy of the records (counts, errors) and of the
-// context's device error word back to pinned host memory and an event.  The
-// dispatcher polls the events of the busy streams; a completed batch marks
-// its requests done and wakes the waiters.  With several streams, the
+// writes the batch's job records into the stream's host-mapped record array
+// (the kernels read them and write counts and errors back in place, so no
+// copy is queued for them) and queues one batched parse on that stream,
+// followed by an event.  The dispatcher polls the events of the busy
+// streams; a completed batch marks its requests done and wakes the waiters.  With several streams, the
 // batches launched while earlier ones run queue behind them on the device
 // and start as soon as compute units free up.
 #include <hip/hip_runtime.h>
@@ -78,10 +78,8 @@ struct Slot {
   ffp_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  ffp_job* h_jobs = nullptr;  // pinned: records to upload
-  ffp_job* h_out = nullptr;   // pinned: records read back
-  uint32_t* h_err = nullptr;  // pinned: device error word read back
-  ffp_job* d_jobs = nullptr;
+  ffp_job* h_jobs = nullptr;  // pinned, host-mapped job records
+  ffp_job* d_jobs = nullptr;  // the same records as the kernels address them
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<Req*> reqs;
@@ -177,6 +175,7 @@ struct ffp_server {
       j.err = 0;
     }
     if (mode == FFP_SERVE_PLAIN) {
+      std::atomic_thread_fence(std::memory_order_release);
       Req* r = s.reqs[0];
       const uint8_t* text = r->on_device ? r->text : r->d_text;
       const int rc = ffp::ctx_parse(s.ctx, r->dtype == FFP_DTYPE_F32 ? ffp::kF32 : ffp::kF64,
@@ -186,14 +185,10 @@ struct ffp_server {
     } else {
       // records past this batch must be empty jobs when the graph replays a
       // fixed job count
-      const uint32_t upload = use_graph ? std::max(n, s.prev_n) : n;
-      for (uint32_t i = n; i < upload; ++i) {
-        memset(&s.h_jobs[i], 0, sizeof(ffp_job));
-      }
-      if (hipMemcpyAsync(s.d_jobs, s.h_jobs, upload * sizeof(ffp_job), hipMemcpyHostToDevice,
-                         s.stream) != hipSuccess)
-        return FFP_E_HIP;
+      if (use_graph)
+        for (uint32_t i = n; i < s.prev_n; ++i) memset(&s.h_jobs[i], 0, sizeof(ffp_job));
       s.prev_n = n;
+      std::atomic_thread_fence(std::memory_order_release);
       if (use_graph) {
         if (hipGraphLaunch(s.exec, s.stream) != hipSuccess) return FFP_E_HIP;
       } else {
@@ -205,12 +200,6 @@ struct ffp_server {
         if (rc != FFP_SUCCESS) return rc;
       }
     }
-    if (hipMemcpyAsync(s.h_out, s.d_jobs, n * sizeof(ffp_job), hipMemcpyDeviceToHost,
-                       s.stream) != hipSuccess)
-      return FFP_E_HIP;
-    if (hipMemcpyAsync(s.h_err, &s.ctx->d_state->error, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                       s.stream) != hipSuccess)
-      return FFP_E_HIP;
     if (hipEventRecord(s.done, s.stream) != hipSuccess) return FFP_E_HIP;
     return FFP_SUCCESS;
   }
@@ -220,16 +209,15 @@ struct ffp_server {
     const uint64_t t = now_ns();
     {
       std::lock_guard<std::mutex> lk(mu);
-      const uint32_t dev_err = fail_rc == FFP_SUCCESS ? *s.h_err : 0u;
+      std::atomic_thread_fence(std::memory_order_acquire);
       for (size_t i = 0; i < s.reqs.size(); ++i) {
         Req* r = s.reqs[i];
         if (fail_rc != FFP_SUCCESS) {
           r->err = fail_rc;
         } else {
-          r->count = s.h_out[i].count;
-          r->err = s.h_out[i].err;
-          if (dev_err & ffp::kDevInternal) r->err = FFP_E_INTERNAL;
-          else if (dev_err & ffp::kDevQueue) r->err = FFP_E_QUEUE;
+          const volatile ffp_job& j = s.h_jobs[i];
+          r->count = j.count;
+          r->err = j.err;
         }
         r->t_done = t;
         r->state = kDone;
@@ -298,9 +286,6 @@ struct ffp_server {
       if (s.done) (void)hipEventDestroy(s.done);
       if (s.stream) (void)hipStreamDestroy(s.stream);
       if (s.h_jobs) (void)hipHostFree(s.h_jobs);
-      if (s.h_out) (void)hipHostFree(s.h_out);
-      if (s.h_err) (void)hipHostFree(s.h_err);
-      if (s.d_jobs) (void)hipFree(s.d_jobs);
       if (s.ctx) ffp_destroy(s.ctx);
     }
     slots.clear();
@@ -349,22 +334,16 @@ int ffp_server_create(ffp_ctx* ctx, const ffp_server_options* opts, ffp_server**
          hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess))
       rc = FFP_E_HIP;
     if (rc == FFP_SUCCESS &&
-        (hipHostMalloc(reinterpret_cast<void**>(&s.h_jobs), jobs * sizeof(ffp_job)) != hipSuccess ||
-         hipHostMalloc(reinterpret_cast<void**>(&s.h_out), jobs * sizeof(ffp_job)) != hipSuccess ||
-         hipHostMalloc(reinterpret_cast<void**>(&s.h_err), sizeof(uint32_t)) != hipSuccess))
+        hipHostMalloc(reinterpret_cast<void**>(&s.h_jobs), jobs * sizeof(ffp_job),
+                      hipHostMallocMapped) != hipSuccess)
       rc = FFP_E_NOMEM;
-    if (rc == FFP_SUCCESS && hipMalloc(&s.d_jobs, jobs * sizeof(ffp_job)) != hipSuccess)
-      rc = FFP_E_NOMEM;
-    if (rc == FFP_SUCCESS) {
-      memset(s.h_jobs, 0, jobs * sizeof(ffp_job));
-      if (hipMemcpy(s.d_jobs, s.h_jobs, jobs * sizeof(ffp_job), hipMemcpyHostToDevice) !=
-          hipSuccess)
-        rc = FFP_E_HIP;
-    }
+    if (rc == FFP_SUCCESS &&
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&s.d_jobs), s.h_jobs, 0) != hipSuccess)
+      rc = FFP_E_HIP;
+    if (rc == FFP_SUCCESS) memset(s.h_jobs, 0, jobs * sizeof(ffp_job));
     if (rc == FFP_SUCCESS && srv->use_graph)
       rc = ffp::ctx_capture_batch(s.ctx, s.d_jobs, jobs, batch_bytes, &s.graph, &s.exec);
-    if (rc == FFP_SUCCESS)
-      srv->scratch_bytes += ffp::ctx_scratch_bytes(s.ctx) + jobs * sizeof(ffp_job);
+    if (rc == FFP_SUCCESS) srv->scratch_bytes += ffp::ctx_scratch_bytes(s.ctx);
   }
   if (rc == FFP_SUCCESS && srv->scratch_bytes + kAlign > budget) rc = FFP_E_BUDGET;
   if (rc == FFP_SUCCESS) {
