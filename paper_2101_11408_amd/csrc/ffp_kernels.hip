@@ -430,9 +430,9 @@ __device__ __forceinline__ uint64_t digits_before(const TileSmem<K>& sm, int end
   if (__any(n > 8)) {
     const int n1 = n > 16 ? 8 : (n > 8 ? n - 8 : 0);
     v += (uint64_t)digits8_before<K>(sm, end - 8, n1) * 100000000ull;
-    if (__any(n > 16)) {
+    if (__any(n > 16)) {  // at most 3 more digits (n <= 19)
       const int n2 = n > 16 ? n - 16 : 0;
-      v += (uint64_t)digits8_before<K>(sm, end - 16, n2) * 10000000000000000ull;
+      v += (uint64_t)digits4_before<K>(sm, end - 16, n2) * 10000000000000000ull;
     }
   }
   return v;
