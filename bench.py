@@ -344,7 +344,8 @@ def serve_once(ffp, ctx, reqs, on_device, opts):
     exp = (base + arrive).astype(np.int64)
     off = np.flatnonzero(ta != exp)
     if off.size:
-        log("arrival mismatch at %d requests, first %s: got %d want %d (done %d launch %d "
+        raise AssertionError(
+            "arrival mismatch at %d requests, first %s: got %d want %d (done %d launch %d "
             "count %d err %d)" % (off.size, off[:5].tolist(), int(ta[off[0]]), int(exp[off[0]]),
                                   int(td[off[0]]), int(out["t_launch_ns"][off[0]]),
                                   int(out["count"][off[0]]), int(out["err"][off[0]])))
@@ -502,6 +503,20 @@ def reduce_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv,
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
         f.write("\n")
+    md = ["# HBM traffic of the parse kernel: %s" % workload, "",
+          "Commands (from the repository root, on one MI355X):", "", "    " + command, "",
+          "| quantity | value |", "|---|---|",
+          "| FETCH_SIZE per dispatch (raw, KiB) | %.1f |" % f_k,
+          "| WRITE_SIZE per dispatch (raw, KiB) | %.1f |" % w_k,
+          "| calibration kernel (bitwise NOT of 1 GiB int64) FETCH_SIZE, WRITE_SIZE (KiB) | "
+          "%.1f, %.1f |" % (f_c, w_c),
+          "| factors (true bytes / counter bytes) fetch, write | %.4f, %.4f |" % (ff, fw),
+          "| HBM bytes fetched per launch | %d |" % ent["fetch_bytes"],
+          "| HBM bytes written per launch | %d |" % ent["write_bytes"],
+          "| total (bench.py roofline.traffic) | %d |" % ent["bytes_per_launch"],
+          "| kernel source hash | %s |" % ent["kernel_hash"], ""]
+    with open(os.path.join(ROOT, "profiles", "k_parse_%s_traffic.md" % workload), "w") as f:
+        f.write("\n".join(md))
     return ent
 
 

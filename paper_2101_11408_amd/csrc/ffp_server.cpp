@@ -513,7 +513,11 @@ int ffp_server_replay(ffp_server* srv, const ffp_replay_request* reqs, uint64_t 
   std::thread collector([&] {
     for (uint64_t i = 0; i < n; ++i) {
       while (submitted.load(std::memory_order_acquire) <= i) {
-        if (stop.load(std::memory_order_acquire)) return;
+        // stop is set after the last submission is published: once it is
+        // seen, the count read after it is final
+        if (stop.load(std::memory_order_acquire) &&
+            submitted.load(std::memory_order_acquire) <= i)
+          return;
         std::this_thread::yield();
       }
       ffp_result r;

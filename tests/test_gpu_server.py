@@ -276,6 +276,8 @@ def test_replay_trace(ctx, ffpmod, pool, reference):
     finally:
         srv.close()
     assert (out["err"] == 0).all()
+    # every request was collected, the last one included
+    assert (out["t_arrive_ns"] == (base + arrive).astype(np.uint64)).all()
     assert list(out["count"]) == [a[0] for a in alone]
     assert (out["t_done_ns"] >= out["t_launch_ns"]).all()
     assert (out["t_launch_ns"] >= out["t_arrive_ns"]).all()
