@@ -12,6 +12,8 @@ them open) and are pinned by golden files only.
 """
 
 from .exact import (
+    BFLOAT16,
+    BINARY16,
     BINARY32,
     BINARY64,
     FORMATS,
@@ -30,6 +32,8 @@ from .grammar import (
 )
 
 __all__ = [
+    "BFLOAT16",
+    "BINARY16",
     "BINARY32",
     "BINARY64",
     "FLAG_REJECT_PLUS",

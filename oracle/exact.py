@@ -84,7 +84,12 @@ class Format:
 # -1022..+1023; binary32 has 24 bits and -126..+127.
 BINARY64 = Format("binary64", 53, -1022, 1023, 11)
 BINARY32 = Format("binary32", 24, -126, 127, 8)
-FORMATS = {"f64": BINARY64, "f32": BINARY32}
+# The paper names binary16 among the standard formats (Section 2); bfloat16
+# keeps binary32's exponent range with an 8-bit significand.  Both follow
+# the same definition of rounding.
+BINARY16 = Format("binary16", 11, -14, 15, 5)
+BFLOAT16 = Format("bfloat16", 8, -126, 127, 8)
+FORMATS = {"f64": BINARY64, "f32": BINARY32, "f16": BINARY16, "bf16": BFLOAT16}
 
 
 def _decimal_digits(n: int) -> int:

@@ -14,6 +14,8 @@ import numpy as np
 import pytest
 
 from oracle import (
+    BFLOAT16,
+    BINARY16,
     BINARY32,
     BINARY64,
     FLAG_REJECT_PLUS,
@@ -248,6 +250,110 @@ def test_bruteforce_mini_format(fmt):
                     assert st == STATUS_OUT_OF_RANGE
                 else:
                     assert st == STATUS_OK
+
+
+# ---------------------------------------------------------------------------
+# binary16 and bfloat16: brute force over every representable value, and the
+# library conversions of exactly representable midpoints
+# ---------------------------------------------------------------------------
+
+def _exact_decimal(v: Fraction):
+    """(D, E) with D * 10^E == v for a dyadic rational v >= 0."""
+    k = v.denominator.bit_length() - 1  # denominator is a power of two
+    return v.numerator * 5 ** k, -k
+
+
+def _small_format_cases(fmt, seed, stride):
+    """Every representable value, every midpoint of neighbours (and the
+    midpoint nudged up and down by one unit of a digit far below it), random
+    decimals across the format's range."""
+    table = _representables(fmt)
+    keys = [t[0] for t in table]
+    cases = []
+    for i in range(0, len(table) - 1, stride):
+        a, b = keys[i], keys[i + 1]
+        D, E = _exact_decimal(a)
+        cases.append((D, E))
+        D, E = _exact_decimal((a + b) / 2)
+        cases += [(D, E), (D * 1000 + 1, E - 3), (D * 1000 - 1, E - 3)]
+    rng = np.random.default_rng(seed)
+    lo = int(math.floor(math.log10(float(keys[1])))) - 2
+    hi = int(math.ceil(math.log10(float(keys[-1])))) + 1
+    for d, e in zip(rng.integers(1, 10 ** 9, 6000), rng.integers(lo - 9, hi - 8, 6000)):
+        cases.append((int(d), int(e)))
+    return table, keys, cases
+
+
+@pytest.mark.parametrize("fmt,stride", [(BINARY16, 1), (BFLOAT16, 3)],
+                         ids=["binary16", "bfloat16"])
+def test_bruteforce_half_formats(fmt, stride):
+    table, keys, cases = _small_format_cases(fmt, 99, stride)
+    inf_value = keys[-1]
+    for D, E in cases:
+        v = Fraction(D) * Fraction(10) ** E
+        want = _brute_nearest(v, table, keys)
+        bits, st = round_decimal(False, D, E, fmt)
+        got = decode_value(bits, fmt)
+        if want == inf_value:
+            assert got == math.inf and st == STATUS_OUT_OF_RANGE, (D, E)
+        else:
+            assert got == want, (D, E, fmt.name)
+            assert st == (STATUS_OUT_OF_RANGE if want == 0 and D else STATUS_OK)
+
+
+def test_binary16_matches_numpy_on_midpoints():
+    """numpy rounds binary64 -> binary16 to nearest, ties to even; every
+    binary16 value and midpoint is exact in binary64."""
+    table = _representables(BINARY16)
+    vals = []
+    for (a, _), (b, _) in zip(table[:-1], table[1:]):
+        vals += [a, (a + b) / 2]
+    for v in vals:
+        D, E = _exact_decimal(v)
+        bits, _ = round_decimal(False, D, E, BINARY16)
+        with np.errstate(over="ignore"):  # 65520 rounds to infinity
+            want = int(np.array([float(v)], dtype=np.float64).astype(np.float16).view(np.uint16)[0])
+        assert bits == want, (float(v), hex(bits), hex(want))
+
+
+def test_bfloat16_matches_torch_on_midpoints():
+    """torch rounds binary32 -> bfloat16 to nearest, ties to even; bfloat16
+    values and midpoints are exact in binary32 (below its overflow)."""
+    torch = pytest.importorskip("torch")
+    table = _representables(BFLOAT16)
+    vals = []
+    for (a, _), (b, _) in zip(table[:-1], table[1:]):
+        if b < Fraction(2) ** 127 * 2:
+            vals += [a, (a + b) / 2]
+    vals = vals[::5]
+    x = torch.tensor([float(v) for v in vals], dtype=torch.float32)
+    want = x.to(torch.bfloat16).view(torch.int16).numpy().astype(np.uint16)
+    for v, w in zip(vals, want.tolist()):
+        D, E = _exact_decimal(v)
+        bits, _ = round_decimal(False, D, E, BFLOAT16)
+        assert bits == w, (float(v), hex(bits), hex(w))
+
+
+def test_half_format_specials():
+    cases = [
+        ("65504", BINARY16, 0x7BFF, STATUS_OK),
+        ("65519.99", BINARY16, 0x7BFF, STATUS_OK),
+        ("65520", BINARY16, 0x7C00, STATUS_OUT_OF_RANGE),  # tie with 2^16: even = infinity
+        ("5.9604644775390625e-8", BINARY16, 0x0001, STATUS_OK),  # 2^-24
+        ("2.98023223876953125e-8", BINARY16, 0x0000, STATUS_OUT_OF_RANGE),  # 2^-25, tie to 0
+        ("2.9802322387695313e-8", BINARY16, 0x0001, STATUS_OK),
+        ("6.103515625e-5", BINARY16, 0x0400, STATUS_OK),  # 2^-14, smallest normal
+        ("1", BINARY16, 0x3C00, STATUS_OK),
+        ("-2", BINARY16, 0xC000, STATUS_OK),
+        ("1", BFLOAT16, 0x3F80, STATUS_OK),
+        ("3.3895313892515355e38", BFLOAT16, 0x7F7F, STATUS_OK),
+        ("3.40e38", BFLOAT16, 0x7F80, STATUS_OUT_OF_RANGE),
+        ("1.00390625", BFLOAT16, 0x3F80, STATUS_OK),  # 1 + 2^-8: tie, even is 1
+        ("1.01171875", BFLOAT16, 0x3F82, STATUS_OK),  # 1 + 3*2^-8: tie, even is up
+    ]
+    for tok, fmt, bits, st in cases:
+        got = parse_token(tok.encode(), fmt)
+        assert got == (bits, st), (tok, fmt.name, hex(got[0]), got[1])
 
 
 # ---------------------------------------------------------------------------
