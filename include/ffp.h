@@ -150,6 +150,25 @@ int64_t ffp_parse_f32_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
                            float* d_values, uint8_t* d_status, uint64_t capacity,
                            uint64_t* d_count, void* stream);
 
+/* The same parse with binary16 (IEEE half) or bfloat16 results: the 16-bit
+ * encodings, nearest value with ties to even.  The paper names binary16
+ * among the standard formats (Section 2) and writes Algorithm 1 for any
+ * significand width; these calls use the same table and steps, and send
+ * every product that may be an exact midpoint to the exact fallback (the
+ * paper's tie windows are derived for binary64 and binary32 only). */
+int ffp_parse_f16(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                  uint16_t* d_values, uint8_t* d_status, uint64_t capacity,
+                  uint64_t* d_count, void* stream);
+int ffp_parse_bf16(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                   uint16_t* d_values, uint8_t* d_status, uint64_t capacity,
+                   uint64_t* d_count, void* stream);
+int64_t ffp_parse_f16_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                           uint16_t* d_values, uint8_t* d_status, uint64_t capacity,
+                           uint64_t* d_count, void* stream);
+int64_t ffp_parse_bf16_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                            uint16_t* d_values, uint8_t* d_status, uint64_t capacity,
+                            uint64_t* d_count, void* stream);
+
 /* Device-side error word of the last call on this context, read after the
  * caller has synchronised its stream: FFP_SUCCESS, FFP_E_QUEUE or
  * FFP_E_INTERNAL.  Blocks on the context's own copy stream. */
@@ -170,15 +189,17 @@ int ffp_last_device_error(ffp_ctx* ctx);
  * ------------------------------------------------------------------------- */
 #define FFP_DTYPE_F64 0
 #define FFP_DTYPE_F32 1
+#define FFP_DTYPE_F16 2   /* binary16, 2-byte values */
+#define FFP_DTYPE_BF16 3  /* bfloat16, 2-byte values */
 
 typedef struct ffp_job {
     const uint8_t* text;  /* device text of this job (any alignment) */
     uint64_t nbytes;
-    void* values;         /* device: capacity doubles or floats (dtype) */
+    void* values;         /* device: capacity values of the dtype */
     uint8_t* status;      /* device: capacity bytes */
     uint64_t capacity;
     uint64_t count;       /* out: true number of tokens */
-    int32_t dtype;        /* FFP_DTYPE_F64 or FFP_DTYPE_F32 */
+    int32_t dtype;        /* FFP_DTYPE_F64, _F32, _F16 or _BF16 */
     int32_t err;          /* out: FFP_SUCCESS, FFP_E_CAPACITY (count >
                              capacity, or max_total_bytes exceeded),
                              FFP_E_ARG (unknown dtype) or FFP_E_QUEUE (the
@@ -287,12 +308,12 @@ typedef struct ffp_server_options {
 } ffp_server_options;
 
 typedef struct ffp_result {
-    const void* values;      /* device: `count` doubles or floats, owned by
-                                the server until ffp_server_release */
+    const void* values;      /* device: `count` values of the dtype, owned
+                                by the server until ffp_server_release */
     const uint8_t* status;   /* device: `count` ffp_token_status bytes */
     uint64_t count;          /* tokens of the request */
     uint64_t nbytes;         /* text bytes of the request */
-    int32_t dtype;           /* FFP_DTYPE_F64 / FFP_DTYPE_F32 */
+    int32_t dtype;           /* FFP_DTYPE_* */
     int32_t err;             /* FFP_SUCCESS, FFP_E_QUEUE, FFP_E_INTERNAL or
                                 FFP_E_HIP */
     uint64_t t_arrive_ns;    /* arrival time given at submission */

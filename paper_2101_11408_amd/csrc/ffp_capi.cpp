@@ -506,6 +506,34 @@ int64_t ffp_parse_f32_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
   return finish_sync(ctx, rc, capacity, d_count, stream);
 }
 
+int ffp_parse_f16(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes, uint16_t* d_values,
+                  uint8_t* d_status, uint64_t capacity, uint64_t* d_count, void* stream) {
+  return parse_common(ctx, ffp::kF16, d_text, nbytes, d_values, d_status, capacity, d_count,
+                      stream);
+}
+
+int ffp_parse_bf16(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes, uint16_t* d_values,
+                   uint8_t* d_status, uint64_t capacity, uint64_t* d_count, void* stream) {
+  return parse_common(ctx, ffp::kBF16, d_text, nbytes, d_values, d_status, capacity, d_count,
+                      stream);
+}
+
+int64_t ffp_parse_f16_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                           uint16_t* d_values, uint8_t* d_status, uint64_t capacity,
+                           uint64_t* d_count, void* stream) {
+  const int rc = parse_common(ctx, ffp::kF16, d_text, nbytes, d_values, d_status, capacity,
+                              d_count, stream);
+  return finish_sync(ctx, rc, capacity, d_count, stream);
+}
+
+int64_t ffp_parse_bf16_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                            uint16_t* d_values, uint8_t* d_status, uint64_t capacity,
+                            uint64_t* d_count, void* stream) {
+  const int rc = parse_common(ctx, ffp::kBF16, d_text, nbytes, d_values, d_status, capacity,
+                              d_count, stream);
+  return finish_sync(ctx, rc, capacity, d_count, stream);
+}
+
 int ffp_parse_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
                     void* stream) {
   return batch_common(ctx, d_jobs, njobs, max_total_bytes, (hipStream_t)stream);

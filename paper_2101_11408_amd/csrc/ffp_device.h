@@ -31,6 +31,7 @@ struct F64 {
   static constexpr uint64_t kInf = 0x7FF0000000000000ull;
   static constexpr uint64_t kQNaN = 0x7FF8000000000000ull;
   static constexpr uint64_t kSign = 1ull << 63;
+  static constexpr bool kTieFallback = false;
 };
 
 struct F32 {
@@ -47,7 +48,70 @@ struct F32 {
   static constexpr uint32_t kInf = 0x7F800000u;
   static constexpr uint32_t kQNaN = 0x7FC00000u;
   static constexpr uint32_t kSign = 1u << 31;
+  static constexpr bool kTieFallback = false;
 };
+
+// binary16 and bfloat16 use the same table and steps.  The tie windows and
+// the round-half-up subnormal step above rest on the paper's proofs for
+// binary64 and binary32 (a short decimal is never an exact midpoint outside
+// the windows, nor among subnormals); for binary16 that fails (2^-25 has 18
+// significant digits), so every product that may be an exact midpoint goes
+// to the exact fallback instead (kTieFallback).
+struct F16 {
+  using bits_t = uint16_t;
+  static constexpr int kMant = 10;
+  static constexpr int kShift = 51;        // z_hi >> (u + 51) keeps 12 bits
+  static constexpr int kMinExp = -14;
+  static constexpr int kMaxExp = 15;
+  static constexpr int kBias = 15;
+  static constexpr int kTieLo = 0;         // unused (kTieFallback)
+  static constexpr int kTieHi = -1;
+  static constexpr int kSubExp = -24;
+  static constexpr uint64_t kSecondMask = (1ull << 51) - 1;
+  static constexpr uint16_t kInf = 0x7C00u;
+  static constexpr uint16_t kQNaN = 0x7E00u;
+  static constexpr uint16_t kSign = 0x8000u;
+  static constexpr bool kTieFallback = true;
+};
+
+struct BF16 {
+  using bits_t = uint16_t;
+  static constexpr int kMant = 7;
+  static constexpr int kShift = 54;        // z_hi >> (u + 54) keeps 9 bits
+  static constexpr int kMinExp = -126;
+  static constexpr int kMaxExp = 127;
+  static constexpr int kBias = 127;
+  static constexpr int kTieLo = 0;         // unused (kTieFallback)
+  static constexpr int kTieHi = -1;
+  static constexpr int kSubExp = -133;
+  static constexpr uint64_t kSecondMask = (1ull << 54) - 1;
+  static constexpr uint16_t kInf = 0x7F80u;
+  static constexpr uint16_t kQNaN = 0x7FC0u;
+  static constexpr uint16_t kSign = 0x8000u;
+  static constexpr bool kTieFallback = true;
+};
+
+// The constants of a format as values, so that one inlined copy of
+// Algorithm 1 serves every format a kernel may meet (the format of a job is
+// the same for all lanes of a wavefront).
+struct FormatRT {
+  int32_t mant;
+  int32_t shift;
+  int32_t min_exp;
+  int32_t max_exp;
+  int32_t bias;
+  int32_t tie_lo;
+  int32_t tie_hi;
+  int32_t tie_fallback;
+  uint64_t second_mask;
+  uint64_t inf;
+};
+
+template <class F>
+FFP_HD constexpr FormatRT format_of() {
+  return FormatRT{F::kMant,  F::kShift, F::kMinExp,         F::kMaxExp,      F::kBias,
+                  F::kTieLo, F::kTieHi, F::kTieFallback ? 1 : 0, F::kSecondMask, F::kInf};
+}
 
 constexpr int kQMin = -342;  // table range, Section 5 and Appendix B
 constexpr int kQMax = 308;
@@ -93,11 +157,8 @@ constexpr uint32_t kStRange = 2;
 // disagrees with Section 9.3 (subnormal below 2^-1022) and with the
 // exponent of Example 4, and halves every subnormal.
 // ---------------------------------------------------------------------------
-template <class F>
-FFP_HD typename F::bits_t alg1(uint64_t w, int q, uint64_t thi,
-                                                   uint64_t tlo, bool& abort,
-                                                   uint32_t& st) {
-  using B = typename F::bits_t;
+FFP_HD uint64_t alg1_rt(uint64_t w, int q, uint64_t thi, uint64_t tlo, const FormatRT& F,
+                       bool& abort, uint32_t& st) {
   abort = false;
   st = kStOk;
   if (q < kQMin) {  // w * 10^q < 2^-1075 for every w < 2^64
@@ -106,13 +167,13 @@ FFP_HD typename F::bits_t alg1(uint64_t w, int q, uint64_t thi,
   }
   if (q > kQMax) {  // beyond 2^1024 for every w >= 1
     st = kStRange;
-    return F::kInf;
+    return F.inf;
   }
   const int l = __builtin_clzll(w);
   w <<= l;
   uint64_t zh, zl;
   mul_64x64(w, thi, zh, zl);
-  if ((zh & F::kSecondMask) == F::kSecondMask) {
+  if ((zh & F.second_mask) == F.second_mask) {
     uint64_t ph, pl;
     mul_64x64(w, tlo, ph, pl);
     zl += ph;
@@ -120,32 +181,46 @@ FFP_HD typename F::bits_t alg1(uint64_t w, int q, uint64_t thi,
   }
   abort = (zl == ~0ull) && (q < -27 || q > 55);
   const int u = (int)(zh >> 63);
-  uint64_t m = zh >> (u + F::kShift);
+  uint64_t m = zh >> (u + F.shift);
   int p = ((217706 * q) >> 16) + 63 - l + u;  // arithmetic shift = floor
-  if (p <= F::kMinExp - 64) {
+  if (p <= F.min_exp - 64) {
     st = kStRange;
     return 0;
   }
-  if (p < F::kMinExp) {
-    m >>= (F::kMinExp - p);
+  if (p < F.min_exp) {
+    const int s = F.min_exp - p;
+    m >>= s;
+    if (F.tie_fallback && (m & 1) && zl <= 1 && u + F.shift + s < 64 &&
+        (zh & ((1ull << (u + F.shift + s)) - 1)) == 0)
+      abort = true;  // may be an exact midpoint between subnormals
     m = (m + (m & 1)) >> 1;
     if (m == 0) st = kStRange;
-    return (B)m;  // exponent field 0; m == 2^kMant encodes the smallest normal
+    return m;  // exponent field 0; m == 2^mant encodes the smallest normal
   }
-  if (zl <= 1 && (m & 1) && !(m & 2) && q >= F::kTieLo && q <= F::kTieHi &&
-      (m << (u + F::kShift)) == zh) {
-    m -= 1;  // exact tie with an even lower neighbour: do not round up
+  if (zl <= 1 && (m & 1) && (m << (u + F.shift)) == zh) {
+    if (F.tie_fallback) {
+      abort = true;  // may be an exact midpoint
+    } else if (!(m & 2) && q >= F.tie_lo && q <= F.tie_hi) {
+      m -= 1;  // exact tie with an even lower neighbour: do not round up
+    }
   }
   m = (m + (m & 1)) >> 1;
-  if (m == (2ull << F::kMant)) {
+  if (m == (2ull << F.mant)) {
     m >>= 1;
     p += 1;
   }
-  if (p > F::kMaxExp) {
+  if (p > F.max_exp) {
     st = kStRange;
-    return F::kInf;
+    return F.inf;
   }
-  return ((B)(p + F::kBias) << F::kMant) | ((B)m & (((B)1 << F::kMant) - 1));
+  return ((uint64_t)(p + F.bias) << F.mant) | (m & ((1ull << F.mant) - 1));
+}
+
+template <class F>
+FFP_HD typename F::bits_t alg1(uint64_t w, int q, uint64_t thi, uint64_t tlo, bool& abort,
+                               uint32_t& st) {
+  constexpr FormatRT fmt = format_of<F>();
+  return (typename F::bits_t)alg1_rt(w, q, thi, tlo, fmt, abort, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -278,6 +353,49 @@ struct GlobalSrc {
 // Decision for one lexed token: Algorithm 1 on w (and on w+1 when digits
 // beyond the 19th were dropped and not all zero, Section 11).
 // ---------------------------------------------------------------------------
+struct DecisionRT {
+  uint64_t bits;      // sign applied (sign_bit = 1 << (format width - 1))
+  uint32_t status;    // kStOk / kStInvalid / kStRange
+  uint32_t path;      // Counter index
+  bool fallback;      // undecided: needs the exact fallback
+};
+
+// qnan / sign: the format's canonical quiet NaN and sign bit.
+FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* table,
+                                  const FormatRT& fmt, uint64_t qnan, uint64_t sign) {
+  DecisionRT d;
+  d.fallback = false;
+  if (L.kind == kLexInvalid) {
+    d.bits = qnan;
+    d.status = kStInvalid;
+    d.path = kCntInvalid;
+    return d;
+  }
+  if (L.w == 0) {
+    d.bits = L.neg ? sign : 0;
+    d.status = kStOk;
+    d.path = kCntEarly;
+    return d;
+  }
+  const int qi = L.q < kQMin ? kQMin : (L.q > kQMax ? kQMax : L.q);
+  const uint64_t thi = table[2 * (qi - kQMin)];
+  const uint64_t tlo = table[2 * (qi - kQMin) + 1];
+  bool ab;
+  d.bits = alg1_rt(L.w, L.q, thi, tlo, fmt, ab, d.status);
+  d.fallback = ab;
+  d.path = (L.q < kQMin || L.q > kQMax) ? kCntEarly : kCntOne;
+  if (L.kind == kLexTruncated) {
+    bool ab2;
+    uint32_t st2;
+    const uint64_t b2 = alg1_rt(L.w + 1, L.q, thi, tlo, fmt, ab2, st2);
+    d.fallback = d.fallback || ab2 || b2 != d.bits;
+    d.path = kCntTwo;
+  }
+  if (L.neg) d.bits |= sign;
+  if (d.fallback) d.path = kCntFallback;
+  return d;
+}
+
 template <class F>
 struct Decision {
   typename F::bits_t bits;  // sign applied
@@ -288,36 +406,13 @@ struct Decision {
 
 template <class F>
 FFP_HD Decision<F> decide_lexed(const Lexed& L, const unsigned long long* table) {
+  constexpr FormatRT fmt = format_of<F>();
+  const DecisionRT r = decide_lexed_rt(L, table, fmt, F::kQNaN, F::kSign);
   Decision<F> d;
-  d.fallback = false;
-  if (L.kind == kLexInvalid) {
-    d.bits = F::kQNaN;
-    d.status = kStInvalid;
-    d.path = kCntInvalid;
-    return d;
-  }
-  if (L.w == 0) {
-    d.bits = L.neg ? F::kSign : 0;
-    d.status = kStOk;
-    d.path = kCntEarly;
-    return d;
-  }
-  const int qi = L.q < kQMin ? kQMin : (L.q > kQMax ? kQMax : L.q);
-  const uint64_t thi = table[2 * (qi - kQMin)];
-  const uint64_t tlo = table[2 * (qi - kQMin) + 1];
-  bool ab;
-  d.bits = alg1<F>(L.w, L.q, thi, tlo, ab, d.status);
-  d.fallback = ab;
-  d.path = (L.q < kQMin || L.q > kQMax) ? kCntEarly : kCntOne;
-  if (L.kind == kLexTruncated) {
-    bool ab2;
-    uint32_t st2;
-    const typename F::bits_t b2 = alg1<F>(L.w + 1, L.q, thi, tlo, ab2, st2);
-    d.fallback = d.fallback || ab2 || b2 != d.bits;
-    d.path = kCntTwo;
-  }
-  if (L.neg) d.bits |= F::kSign;
-  if (d.fallback) d.path = kCntFallback;
+  d.bits = (typename F::bits_t)r.bits;
+  d.status = r.status;
+  d.path = r.path;
+  d.fallback = r.fallback;
   return d;
 }
 

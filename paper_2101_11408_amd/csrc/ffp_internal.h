@@ -37,7 +37,7 @@ constexpr uint64_t kMaxBytes = 1ull << 47;
 // Algorithm 1 on top of the provable bound for long tokens.
 constexpr uint64_t kAbortReserve = 65536;
 
-enum DType : uint32_t { kF64 = 0, kF32 = 1 };
+enum DType : uint32_t { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
 enum DevError : uint32_t { kDevOk = 0, kDevQueue = 1, kDevInternal = 2 };
 

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kScanThreads) void k_prep(PrepParams P) {
     const uint32_t j = base + tid;
     UserJob u{};
     if (j < P.njobs) u = P.user[j];
-    const bool ok = j < P.njobs && (u.dtype == kF64 || u.dtype == kF32) &&
+    const bool ok = j < P.njobs && u.dtype >= kF64 && u.dtype <= kBF16 &&
                     u.nbytes < kMaxBytes && (u.nbytes == 0 || u.text != nullptr) &&
                     (u.capacity == 0 || (u.values != nullptr && u.status != nullptr));
     const uint64_t nb = ok ? u.nbytes : 0;
@@ -529,7 +529,8 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
 }
 
 template <int K, bool kSingle>
-__global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
+// Four workgroups per CU (the LDS allows four): keep registers within 128.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_parse(ParseParams P) {
   using S = TileSmem<K>;
   using Packed = typename S::Packed;
   __shared__ S sm;
@@ -669,8 +670,13 @@ __global__ __launch_bounds__(kThreads) void k_parse(ParseParams P) {
           L.neg = fl.neg;
           L.kind = fl.code == kFastInvalid ? kLexInvalid : kLexExact;
         }
-        const int path = job.dtype == kF64 ? finish_token<F64>(L, pos, job, idx, table, P)
-                                           : finish_token<F32>(L, pos, job, idx, table, P);
+        int path;
+        switch (job.dtype) {
+          case kF64: path = finish_token<F64>(L, pos, job, idx, table, P); break;
+          case kF32: path = finish_token<F32>(L, pos, job, idx, table, P); break;
+          case kF16: path = finish_token<F16>(L, pos, job, idx, table, P); break;
+          default: path = finish_token<BF16>(L, pos, job, idx, table, P); break;
+        }
         if (P.count_paths) {
           c_tok += 1;
           c_inv += path == kCntInvalid;
@@ -726,10 +732,11 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(FallbackParams P) {
     const uint64_t idx = e.index_job & ((1ull << 48) - 1);
     const JobDesc job = P.js.jobs ? P.js.jobs[job_id] : P.js.single;
     fb_wave_sync();  // the previous token's LDS reads are done
-    if (job.dtype == kF64) {
-      fallback_token<F64>(job, e.offset, idx, &lds[wid]);
-    } else {
-      fallback_token<F32>(job, e.offset, idx, &lds[wid]);
+    switch (job.dtype) {
+      case kF64: fallback_token<F64>(job, e.offset, idx, &lds[wid]); break;
+      case kF32: fallback_token<F32>(job, e.offset, idx, &lds[wid]); break;
+      case kF16: fallback_token<F16>(job, e.offset, idx, &lds[wid]); break;
+      default: fallback_token<BF16>(job, e.offset, idx, &lds[wid]); break;
     }
   }
 }

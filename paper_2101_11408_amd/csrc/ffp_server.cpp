@@ -46,6 +46,10 @@ constexpr uint32_t kMaxBatchJobs = 65535;
 
 uint64_t round_up(uint64_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
+uint64_t value_bytes(int dtype) {
+  return dtype == FFP_DTYPE_F64 ? 8 : dtype == FFP_DTYPE_F32 ? 4 : 2;
+}
+
 uint64_t now_ns() {
   timespec ts;
   clock_gettime(CLOCK_MONOTONIC, &ts);
@@ -113,8 +117,8 @@ struct ffp_server {
 
   uint64_t need_of(uint64_t nbytes, bool on_device, int dtype, uint64_t* cap) const {
     *cap = nbytes ? (nbytes + 1) / 2 : 0;
-    const uint64_t vsize = dtype == FFP_DTYPE_F32 ? 4 : 8;
-    return (on_device ? 0 : round_up(nbytes)) + round_up(*cap * vsize) + round_up(*cap);
+    return (on_device ? 0 : round_up(nbytes)) + round_up(*cap * value_bytes(dtype)) +
+           round_up(*cap);
   }
 
   // Frees a request's arena range (caller holds mu).
@@ -142,7 +146,7 @@ struct ffp_server {
           p += round_up(r->nbytes);
         }
         r->d_values = p;
-        p += round_up(r->capacity * (r->dtype == FFP_DTYPE_F32 ? 4 : 8));
+        p += round_up(r->capacity * value_bytes(r->dtype));
         r->d_status = p;
       }
       queue.pop_front();
@@ -178,7 +182,7 @@ struct ffp_server {
       std::atomic_thread_fence(std::memory_order_release);
       Req* r = s.reqs[0];
       const uint8_t* text = r->on_device ? r->text : r->d_text;
-      const int rc = ffp::ctx_parse(s.ctx, r->dtype == FFP_DTYPE_F32 ? ffp::kF32 : ffp::kF64,
+      const int rc = ffp::ctx_parse(s.ctx, (uint32_t)r->dtype,
                                     r->nbytes ? text : nullptr, r->nbytes, r->d_values,
                                     r->d_status, r->capacity, &s.d_jobs[0].count, s.stream);
       if (rc != FFP_SUCCESS) return rc;
@@ -367,7 +371,7 @@ int ffp_server_create(ffp_ctx* ctx, const ffp_server_options* opts, ffp_server**
 int ffp_server_submit(ffp_server* srv, const uint8_t* text, uint64_t nbytes, int on_device,
                       int dtype, uint64_t arrival_ns, uint64_t* ticket) {
   if (!srv || !ticket) return FFP_E_ARG;
-  if (dtype != FFP_DTYPE_F64 && dtype != FFP_DTYPE_F32) return FFP_E_ARG;
+  if (dtype < FFP_DTYPE_F64 || dtype > FFP_DTYPE_BF16) return FFP_E_ARG;
   if (nbytes > 0 && !text) return FFP_E_ARG;
   if (nbytes > srv->max_batch_bytes) return FFP_E_BUDGET;
   uint64_t cap = 0;
@@ -447,7 +451,7 @@ int ffp_server_copy_result(ffp_server* srv, uint64_t ticket, void* dst_values,
     const Req* r = it->second;
     if (r->state != kDone) return FFP_E_BUSY;
     n = std::min(r->count, max_count);
-    vsize = r->dtype == FFP_DTYPE_F32 ? 4 : 8;
+    vsize = value_bytes(r->dtype);
     src_v = r->d_values;
     src_s = r->d_status;
   }

@@ -31,6 +31,8 @@ FFP_REJECT_PLUS = 1
 
 DTYPE_F64 = 0
 DTYPE_F32 = 1
+DTYPE_F16 = 2
+DTYPE_BF16 = 3
 
 FFP_SERVE_BATCHED = 0
 FFP_SERVE_PLAIN = 1
@@ -103,6 +105,10 @@ _SIGNATURES = {
     "ffp_parse_f32": (_INT, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
     "ffp_parse_f64_sync": (_I64, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
     "ffp_parse_f32_sync": (_I64, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_parse_f16": (_INT, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_parse_bf16": (_INT, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_parse_f16_sync": (_I64, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_parse_bf16_sync": (_I64, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
     "ffp_last_device_error": (_INT, [_P]),
     "ffp_timing_enable": (_INT, [_P, _INT]),
     "ffp_timing_read": (_INT, [_P, _c.POINTER(_c.c_double), _c.POINTER(_U64)]),
@@ -265,21 +271,20 @@ class Context:
 
     def parse_into(self, text, values, status, count, nbytes=None, stream=None,
                    sync=False):
-        """Parse device uint8 tensor `text` into preallocated device tensors."""
+        """Parse device uint8 tensor `text` into preallocated device tensors;
+        the values tensor's dtype (float64, float32, float16, bfloat16) picks
+        the output format."""
         import torch
         assert text.is_cuda and text.dtype == torch.uint8 and text.is_contiguous()
-        f32 = values.dtype == torch.float32
-        if not f32:
-            assert values.dtype == torch.float64
+        name = {torch.float64: "f64", torch.float32: "f32", torch.float16: "f16",
+                torch.bfloat16: "bf16"}[values.dtype]
         nb = text.numel() if nbytes is None else nbytes
         cap = min(values.numel(), status.numel())
-        args = (self.handle, text.data_ptr(), nb, values.data_ptr(), status.data_ptr(), cap,
-                count.data_ptr(), stream)
-        if sync:
-            fn = ffp_parse_f32_sync if f32 else ffp_parse_f64_sync
-            return fn(*args)
-        fn = ffp_parse_f32 if f32 else ffp_parse_f64
-        return check(fn(*args), "parse")
+        lib = load()
+        fn = getattr(lib, "ffp_parse_%s%s" % (name, "_sync" if sync else ""))
+        rc = fn(self.handle, text.data_ptr(), nb, values.data_ptr(), status.data_ptr(), cap,
+                count.data_ptr(), _stream_handle(stream))
+        return rc if sync else check(rc, "parse")
 
     # -- batched calls -------------------------------------------------
     def parse_batch(self, d_jobs, njobs, max_total_bytes, stream=None):
@@ -342,7 +347,9 @@ class JobTable:
             self.host[i].values = v.data_ptr()
             self.host[i].status = st.data_ptr()
             self.host[i].capacity = min(v.numel(), st.numel())
-            self.host[i].dtype = DTYPE_F32 if v.dtype == torch.float32 else DTYPE_F64
+            self.host[i].dtype = {torch.float64: DTYPE_F64, torch.float32: DTYPE_F32,
+                                  torch.float16: DTYPE_F16,
+                                  torch.bfloat16: DTYPE_BF16}[v.dtype]
             self.host[i].err = 0
             self.host[i].count = 0
         raw = bytes(self.host)
@@ -439,7 +446,8 @@ class Server:
         """Copies a done request's values and status into new device tensors."""
         import torch
         r = self.wait(ticket)
-        dt = torch.float32 if r.dtype == DTYPE_F32 else torch.float64
+        dt = {DTYPE_F64: torch.float64, DTYPE_F32: torch.float32, DTYPE_F16: torch.float16,
+              DTYPE_BF16: torch.bfloat16}[r.dtype]
         values = torch.empty(r.count, dtype=dt, device=device)
         status = torch.empty(r.count, dtype=torch.uint8, device=device)
         if r.count:

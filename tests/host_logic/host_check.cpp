@@ -5,8 +5,8 @@
 // status 255; they, the tile scan and every other part of the kernels are
 // covered by the GPU tests.
 //
-// usage: host_check <text file> <f64|f32> <flags> <out file> [delimiters]
-// writes, per token, the 64-bit encoding (f32 zero-extended) and a status
+// usage: host_check <text file> <f64|f32|f16|bf16> <flags> <out file> [delimiters]
+// writes, per token, the encoding zero-extended to 64 bits and a status
 // byte; prints the number of tokens and of fallback decisions.
 #include <hip/hip_runtime.h>
 
@@ -49,7 +49,7 @@ static void run(const std::vector<uint8_t>& buf, const ffp::DelimSet& ds, uint32
 
 int main(int argc, char** argv) {
   if (argc < 5) {
-    fprintf(stderr, "usage: %s text f64|f32 flags out [delims]\n", argv[0]);
+    fprintf(stderr, "usage: %s text f64|f32|f16|bf16 flags out [delims]\n", argv[0]);
     return 2;
   }
   FILE* f = fopen(argv[1], "rb");
@@ -75,8 +75,12 @@ int main(int argc, char** argv) {
   long ntok = 0, nfb = 0;
   if (strcmp(argv[2], "f64") == 0)
     run<ffp::F64>(buf, ds, flags, out, &ntok, &nfb);
-  else
+  else if (strcmp(argv[2], "f32") == 0)
     run<ffp::F32>(buf, ds, flags, out, &ntok, &nfb);
+  else if (strcmp(argv[2], "f16") == 0)
+    run<ffp::F16>(buf, ds, flags, out, &ntok, &nfb);
+  else
+    run<ffp::BF16>(buf, ds, flags, out, &ntok, &nfb);
   fclose(out);
   printf("%ld %ld\n", ntok, nfb);
   return 0;

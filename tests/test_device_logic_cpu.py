@@ -126,3 +126,21 @@ def test_exact_ties_near_one(host_check):
     buf = W.join_tokens(toks)
     for fmt in ("f64", "f32"):
         check(host_check, buf, fmt, "ties")
+
+
+def test_half_formats(host_check):
+    """binary16 and bfloat16 through the same logic (exact-midpoint candidates
+    go to the fallback)."""
+    rng = np.random.default_rng(48)
+    toks = W.mixed_tokens(rng, 20_000) + W.hard_tokens(rng, 1000)
+    toks += ["65504", "65519.99", "65520", "5.9604644775390625e-8", "2.98023223876953125e-8",
+             "6.103515625e-5", "1.00390625", "1.01171875", "3.3895313892515355e38", "1e-40",
+             "9.18354961579912115600575419704879435795832466228193376178712270530013483949005e-41"]
+    # small integers and short decimals, the range binary16 represents
+    toks += [str(int(v)) for v in rng.integers(0, 70_000, 5000)]
+    toks += ["%.*f" % (int(k), float(x)) for k, x in zip(rng.integers(0, 8, 5000),
+                                                         rng.random(5000) * 1000)]
+    buf = W.join_tokens(toks)
+    for fmt in ("f16", "bf16"):
+        nfb = check(host_check, buf, fmt, "half")
+        assert nfb > 0

@@ -44,7 +44,13 @@ def pool():
     return host, dev
 
 
-def build_jobs(ffpmod, pool, sizes, f32_mask, seed):
+FMT_OF = {torch.float64: "f64", torch.float32: "f32", torch.float16: "f16",
+          torch.bfloat16: "bf16"}
+INT_OF = {"f64": (torch.int64, np.uint64), "f32": (torch.int32, np.uint32),
+          "f16": (torch.int16, np.uint16), "bf16": (torch.int16, np.uint16)}
+
+
+def build_jobs(ffpmod, pool, sizes, f32_mask, seed, dtypes=None):
     host, dev = pool
     rng = np.random.default_rng(seed)
     plan = W.slice_plan(rng, host, sizes)
@@ -55,7 +61,7 @@ def build_jobs(ffpmod, pool, sizes, f32_mask, seed):
             st, ln = st + 1, ln - 1
         texts.append(dev[st:st + ln])
         cap = ln // 2 + 1
-        dt = torch.float32 if f32_mask[i] else torch.float64
+        dt = dtypes[i] if dtypes is not None else (torch.float32 if f32_mask[i] else torch.float64)
         values.append(torch.empty(cap, dtype=dt, device="cuda:0"))
         statuses.append(torch.full((cap,), 255, dtype=torch.uint8, device="cuda:0"))
         spans.append((st, ln))
@@ -68,14 +74,14 @@ def check_jobs(pool, table, values, statuses, spans, label):
     res = table.download()
     for i, ((st, ln), (count, err)) in enumerate(zip(spans, res)):
         buf = host[st:st + ln]
-        fmt = "f32" if values[i].dtype == torch.float32 else "f64"
+        fmt = FMT_OF[values[i].dtype]
         wb, ws = parse_buffer(buf, fmt)
         assert count == len(wb), (label, i, count, len(wb))
         assert err == 0, (label, i, err)
         n = len(wb)
         if n == 0:
             continue
-        ib, npb = (torch.int32, np.uint32) if fmt == "f32" else (torch.int64, np.uint64)
+        ib, npb = INT_OF[fmt]
         got = values[i][:n].view(ib).cpu().numpy().view(npb)
         gs = statuses[i][:n].cpu().numpy()
         bad = np.flatnonzero((got != np.array(wb, dtype=npb)) | (gs != np.array(ws, dtype=np.uint8)))
@@ -200,3 +206,16 @@ def test_autotune_and_cache(ffpmod, pool, tmp_path):
         c2.close()
     finally:
         del os.environ["FFP_TUNE_CACHE"]
+
+
+def test_batch_all_output_types(ctx, ffpmod, pool):
+    """Jobs of the four output types in one batch."""
+    rng = np.random.default_rng(15)
+    n = 160
+    sizes = W.lognormal_sizes(rng, n, 8000, 1.5, 1, 120_000)
+    kinds = [torch.float64, torch.float32, torch.float16, torch.bfloat16]
+    dtypes = [kinds[int(k)] for k in rng.integers(0, 4, n)]
+    table, values, statuses, spans = build_jobs(ffpmod, pool, sizes, None, 16, dtypes)
+    ctx.parse_batch(table.dev, table.n, table.total_bytes)
+    torch.cuda.synchronize()
+    check_jobs(pool, table, values, statuses, spans, "four-types")

@@ -34,13 +34,19 @@ def ctx(ffpmod):
     c.close()
 
 
+TORCH_DT = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
+            "bf16": torch.bfloat16}
+INT_DT = {"f64": torch.int64, "f32": torch.int32, "f16": torch.int16, "bf16": torch.int16}
+NP_DT = {"f64": np.uint64, "f32": np.uint32, "f16": np.uint16, "bf16": np.uint16}
+
+
 def run_gpu(ctx, buf: bytes, fmt: str, capacity=None, offset=0):
     """Parses buf on the GPU; with offset > 0 the device text starts that many
     bytes past an allocation boundary."""
     dev = torch.device("cuda", 0)
     text = torch.frombuffer(bytearray(b"\n" * offset + buf), dtype=torch.uint8).to(dev)[offset:] \
         if buf else torch.empty(0, dtype=torch.uint8, device=dev)
-    dt = torch.float64 if fmt == "f64" else torch.float32
+    dt = TORCH_DT[fmt]
     if capacity is None:
         capacity = len(buf) // 2 + 1
     values = torch.empty(max(capacity, 1), dtype=dt, device=dev)
@@ -49,12 +55,7 @@ def run_gpu(ctx, buf: bytes, fmt: str, capacity=None, offset=0):
     rc = ctx.parse_into(text, values, status, count, sync=True) if len(buf) else \
         ctx.parse_into(text, values, status, count, nbytes=0, sync=True)
     n = int(count.item())
-    ib = torch.int64 if fmt == "f64" else torch.int32
-    bits = values.view(ib).cpu().numpy()
-    if fmt == "f64":
-        bits = bits.view(np.uint64)
-    else:
-        bits = bits.view(np.uint32)
+    bits = values.view(INT_DT[fmt]).cpu().numpy().view(NP_DT[fmt])
     return rc, n, bits, status.cpu().numpy()
 
 
@@ -64,8 +65,7 @@ def compare_full(ctx, buf: bytes, fmt: str, label: str):
     want_bits, want_st = parse_buffer(buf, fmt)
     assert rc == len(want_bits), (label, rc)
     assert n == len(want_bits)
-    dt = np.uint64 if fmt == "f64" else np.uint32
-    wb = np.array(want_bits, dtype=dt)
+    wb = np.array(want_bits, dtype=NP_DT[fmt])
     ws = np.array(want_st, dtype=np.uint8)
     bad = np.flatnonzero((bits[:n] != wb) | (status[:n] != ws))
     if bad.size:
@@ -175,8 +175,8 @@ def test_block_sizes(ffpmod, ragged_blocks_case, block_kib, tile_k):
             rc, n, bits, status = run_gpu(c, buf, fmt, offset=5)
             wb, ws = want[fmt]
             assert rc == len(wb) and n == len(wb)
-            dt = np.uint64 if fmt == "f64" else np.uint32
-            assert np.array_equal(bits[:n], np.array(wb, dtype=dt)), (block_kib, tile_k, fmt)
+            assert np.array_equal(bits[:n], np.array(wb, dtype=NP_DT[fmt])), (block_kib, tile_k,
+                                                                              fmt)
             assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8))
     finally:
         c.close()
@@ -284,3 +284,67 @@ def test_config3_full_size_sampled(ctx):
     buf = W.config3()
     compare_sampled(ctx, buf, "f64", "config3-full", 20_000, 31)
     compare_sampled(ctx, buf, "f32", "config3-full", 20_000, 32)
+
+
+# ---------------------------------------------------------------------------
+# binary16 and bfloat16 results
+# ---------------------------------------------------------------------------
+
+def test_half_formats_mixed_and_hard(ctx):
+    rng = np.random.default_rng(61)
+    toks = W.mixed_tokens(rng, 40_000) + W.hard_tokens(rng, 2000)
+    toks += [str(int(v)) for v in rng.integers(0, 70_000, 10_000)]
+    toks += ["%.*f" % (int(k), float(x)) for k, x in zip(rng.integers(0, 8, 10_000),
+                                                         rng.random(10_000) * 1000)]
+    rng.shuffle(toks)
+    buf = W.join_tokens(toks)
+    for fmt in ("f16", "bf16"):
+        compare_full(ctx, buf, fmt, "half-mixed")
+
+
+def _dyadic_decimal(num: int, den_log2: int) -> str:
+    """num / 2^den_log2 written exactly: (num * 5^k)e-k."""
+    return "%de-%d" % (num * 5 ** den_log2, den_log2) if den_log2 > 0 else str(num << -den_log2)
+
+
+def _value_and_midpoint_tokens(p, emin, emax, stride):
+    """Every stride-th finite non-negative value of a format as an exact
+    decimal, the exact midpoints of neighbours and the midpoints nudged by a
+    digit far below them, both signs."""
+    q0 = emin - p + 1
+    vals = [(m, -q0) for m in range(0, 1 << (p - 1))]  # subnormals and zero: m * 2^q0
+    for e in range(emin, emax + 1):
+        vals += [(m, -(e - p + 1)) for m in range(1 << (p - 1), 1 << p)]
+    vals.append((1, -(emax + 1)))  # 2^(emax+1): the midpoint above the largest is needed
+    toks = []
+    for i in range(0, len(vals) - 1, stride):
+        (ma, ka), (mb, kb) = vals[i], vals[i + 1]
+        k = max(ka, kb) + 1  # both neighbours as integers over 2^k
+        a = ma * 2 ** (k - ka)
+        b = mb * 2 ** (k - kb)
+        mid = a + b  # midpoint = (a + b) / 2^(k+1)
+        toks.append(_dyadic_decimal(a, k))
+        m_str = _dyadic_decimal(mid, k + 1)
+        toks.append(m_str)
+        if "e" in m_str:
+            d, e = m_str.split("e")
+            toks.append("%s1e%d" % (d, int(e) - 1))      # nudged up
+            toks.append("%se%d" % (str(int(d) * 10 - 1), int(e) - 1))  # nudged down
+    return toks + ["-" + t for t in toks[::7]]
+
+
+def test_binary16_every_value_and_midpoint(ctx):
+    toks = _value_and_midpoint_tokens(11, -14, 15, 1)
+    # shortest round-trip digits of every finite binary16 value
+    allh = np.arange(0, 0x7C00, dtype=np.uint16).view(np.float16)
+    toks += [repr(float(x)) for x in allh[::3]]
+    buf = W.join_tokens(toks)
+    _log("binary16 tokens", len(toks))
+    compare_full(ctx, buf, "f16", "binary16-exhaustive")
+
+
+def test_bfloat16_values_and_midpoints(ctx):
+    toks = _value_and_midpoint_tokens(8, -126, 127, 5)
+    buf = W.join_tokens(toks)
+    _log("bfloat16 tokens", len(toks))
+    compare_full(ctx, buf, "bf16", "bfloat16-sampled")
