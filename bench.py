@@ -46,11 +46,17 @@ WORKLOAD_NAMES = {
     "config5": "config5-served-poisson",
     "copycal": "copy-calibration",
 }
+OUT_NAMES = {"f64": "binary64", "f32": "binary32", "f16": "binary16", "bf16": "bfloat16"}
 METRIC = "GB/s input text + Mfloats/s parsed (bit-exact), batched/served vs plain; p50/p99"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2101_11408_amd/csrc/ffp_kernels.hip",
                   "paper_2101_11408_amd/csrc/ffp_device.h",
                   "paper_2101_11408_amd/csrc/ffp_internal.h"]
+
+
+def out_name(wl, out):
+    """Workload name with the output format of a plain run."""
+    return WORKLOAD_NAMES[wl].replace("binary64", OUT_NAMES[out])
 
 
 def log(*a):
@@ -183,7 +189,8 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False):
     from paper_2101_11408_amd import ffp
     dev = torch.device("cuda", 0)
     text = torch.frombuffer(bytearray(buf), dtype=torch.uint8).to(dev)
-    dt = torch.float64 if out_dtype == "f64" else torch.float32
+    dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
+          "bf16": torch.bfloat16}[out_dtype]
     values = torch.empty(ntok, dtype=dt, device=dev)
     status = torch.empty(ntok, dtype=torch.uint8, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -204,13 +211,12 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False):
     assert ctx.last_device_error() == 0
     assert int(count.item()) == ntok
     kavg = kern_ms / launches
-    vbytes = 8 if out_dtype == "f64" else 4
+    vbytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[out_dtype]
     alg = len(buf) + (vbytes + 1) * ntok
     log("steps done: %.3f ms/step, parse kernel %.3f ms" % (ms, kavg))
     rec = base_record(args, len(buf) / (ms / 1e3) / 1e9, ms, workload, {
         "description": desc, "tokens": ntok, "bytes": len(buf),
-        "output": "binary64" if out_dtype == "f64" else "binary32",
-        "parallelism": "single GPU"})
+        "output": OUT_NAMES[out_dtype], "parallelism": "single GPU"})
     rec["mfloats_per_s"] = round(ntok / (ms / 1e3) / 1e6, 1)
     rec["roofline"] = roofline(alg, kavg, workload)
     rec["cpu_baseline"] = cpu_baseline(buf, min(args.cpu_sample, ntok)) if cpu else None
@@ -589,6 +595,8 @@ def main():
                              "config5", "copycal"])
     ap.add_argument("--tokens", type=int, default=None)
     ap.add_argument("--nbuf", type=int, default=4096)
+    ap.add_argument("--out", default="f64", choices=["f64", "f32", "f16", "bf16"],
+                    help="plain workloads: output format")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--rates", default="2000,5000,10000,20000")
@@ -637,26 +645,29 @@ def main():
         t0 = time.time()
         buf = W.config2(n=n)
         log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
-        rec = run_plain(args, buf, n, WORKLOAD_NAMES[wl],
+        rec = run_plain(args, buf, n, out_name(wl, args.out),
                         "10M numbers in one %.1f MB buffer: 50%% uniform [0,1) shortest "
                         "digits, 25%% coordinates (6-15 fraction digits), 25%% random finite "
-                        "bit patterns as %%.17e; binary64 output; one ffp_parse_f64 call per "
-                        "step" % (len(buf) / 1e6), cpu=not args.no_cpu_baseline)
+                        "bit patterns as %%.17e; %s output; one parse call per step"
+                        % (len(buf) / 1e6, OUT_NAMES[args.out]), out_dtype=args.out,
+                        cpu=not args.no_cpu_baseline and args.out == "f64")
     elif wl == "config1":
         n = args.tokens or 100_000
         buf = W.config1(n=n)
-        rec = run_plain(args, buf, n, WORKLOAD_NAMES[wl],
+        rec = run_plain(args, buf, n, out_name(wl, args.out),
                         "100k uniform [0,1) doubles, shortest digits, positional, one "
-                        "%.2f MB buffer; binary64" % (len(buf) / 1e6))
+                        "%.2f MB buffer; %s" % (len(buf) / 1e6, OUT_NAMES[args.out]),
+                        out_dtype=args.out)
     elif wl == "config3":
         n = args.tokens or 2_000_000
         t0 = time.time()
         buf = W.config3(n=n)
         log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
-        rec = run_plain(args, buf, n, WORKLOAD_NAMES[wl],
+        rec = run_plain(args, buf, n, out_name(wl, args.out),
                         "2M hard cases (midpoints +-1 in the last of 20-800 digits, "
                         "subnormals, overflow, integers to 2^64, sign/zero variants) in one "
-                        "%.1f MB buffer; binary64" % (len(buf) / 1e6))
+                        "%.1f MB buffer; %s" % (len(buf) / 1e6, OUT_NAMES[args.out]),
+                        out_dtype=args.out)
     elif wl == "config4":
         rec = run_batched(args, "mixed", WORKLOAD_NAMES[wl])
     elif wl == "config5":
