@@ -24,6 +24,8 @@ from .exact import (
     round_decimal,
 )
 from .grammar import (
+    FLAG_INFNAN,
+    FLAG_JSON,
     FLAG_REJECT_PLUS,
     decompose,
     parse_buffer,
@@ -36,6 +38,8 @@ __all__ = [
     "BINARY16",
     "BINARY32",
     "BINARY64",
+    "FLAG_INFNAN",
+    "FLAG_JSON",
     "FLAG_REJECT_PLUS",
     "FORMATS",
     "Format",

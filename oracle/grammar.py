@@ -19,7 +19,7 @@ library contract; the paper does not fix them.
 
 import re
 
-from .exact import BINARY32, BINARY64, FORMATS, STATUS_INVALID, round_decimal
+from .exact import BINARY32, BINARY64, FORMATS, STATUS_INVALID, STATUS_OK, round_decimal
 
 # [+-]? ( D+ ('.' D*)? | '.' D+ ) ( [eE] [+-]? D+ )?   -- whole token
 _TOKEN_RE = re.compile(
@@ -27,12 +27,24 @@ _TOKEN_RE = re.compile(
 )
 
 FLAG_REJECT_PLUS = 1
+# JSON numbers: the number grammar of the JSON specification (RFC 8259,
+# section 6): no '+' (the JSON rule the paper mentions in Section 4), no
+# leading zeros, at least one digit on each side of a '.'.
+FLAG_JSON = 2
+# inf, infinity and nan in any letter case, with an optional sign: +-infinity
+# and the quiet NaN (the sign bit follows the sign).
+FLAG_INFNAN = 4
+
+_JSON_RE = re.compile(rb"-?(?:0|[1-9][0-9]*)(?:\.[0-9]+)?(?:[eE][+-]?[0-9]+)?")
+_INFNAN_RE = re.compile(rb"([+-]?)(?:inf|infinity|nan)", re.IGNORECASE)
 
 
 def decompose(tok: bytes, flags: int = 0):
     """Return (neg, D, E) with value (-1)^neg * D * 10^E, or None if invalid."""
     m = _TOKEN_RE.fullmatch(tok)
     if m is None:
+        return None
+    if (flags & FLAG_JSON) and _JSON_RE.fullmatch(tok) is None:
         return None
     sign, int_digits, frac_digits, only_frac, exp = m.groups()
     if sign == b"+" and (flags & FLAG_REJECT_PLUS):
@@ -51,6 +63,12 @@ def parse_token(tok: bytes, fmt=BINARY64, flags: int = 0):
     """(bits, status) for one token."""
     if isinstance(fmt, str):
         fmt = FORMATS[fmt]
+    if flags & FLAG_INFNAN:
+        m = _INFNAN_RE.fullmatch(tok)
+        if m is not None and not (m.group(1) == b"+" and flags & (FLAG_REJECT_PLUS | FLAG_JSON)):
+            sign = fmt.sign_bit if m.group(1) == b"-" else 0
+            special = fmt.qnan_bits if tok[-1:] in (b"n", b"N") else fmt.inf_bits
+            return sign | special, STATUS_OK
     parts = decompose(tok, flags)
     if parts is None:
         return fmt.qnan_bits, STATUS_INVALID
@@ -87,6 +105,8 @@ def parse_buffer(buf: bytes, fmt="f64", delims: bytes = b"\n", flags: int = 0):
 __all__ = [
     "BINARY32",
     "BINARY64",
+    "FLAG_INFNAN",
+    "FLAG_JSON",
     "FLAG_REJECT_PLUS",
     "decompose",
     "parse_buffer",

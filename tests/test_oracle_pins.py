@@ -519,3 +519,77 @@ def test_split_tokens():
     bits, st = parse_buffer(b"1\n\nx\n2.5", "f64")
     assert st == [STATUS_OK, STATUS_INVALID, STATUS_OK]
     assert bits[2] == f64_bits(2.5)
+
+
+# ---------------------------------------------------------------------------
+# JSON grammar and inf/nan tokens (library contract)
+# ---------------------------------------------------------------------------
+
+def test_json_and_infnan_golden(golden_dir):
+    rows = []
+    with open(os.path.join(golden_dir, "grammar_json_infnan.tsv")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            tok, flags, st, bits = line.rstrip("\n").split("\t")
+            rows.append((tok, int(flags), int(st), int(bits, 16)))
+    assert len(rows) > 30
+    for tok, flags, st, bits in rows:
+        assert parse_token(tok.encode(), BINARY64, flags) == (bits, st), (tok, flags)
+
+
+def _mutated_numbers(rng, n):
+    """Number-like strings from the alphabet of the grammar, biased toward
+    the edge cases of the JSON rules."""
+    parts = ["", "-", "+", "0", "00", "1", "01", "9", "12", ".", ".5", "5.", "e", "E",
+             "e+", "e-", "3", "0.", ".0"]
+    out = []
+    for _ in range(n):
+        k = int(rng.integers(1, 5))
+        out.append("".join(parts[int(i)] for i in rng.integers(0, len(parts), k)))
+    return [t for t in out if t]
+
+
+def test_json_acceptance_matches_json_module():
+    """A token is a JSON number exactly when Python's json module reads it as
+    a number (json also reads NaN/Infinity literals: none are generated)."""
+    import json
+    rng = np.random.default_rng(5)
+    for tok in set(_mutated_numbers(rng, 20_000)):
+        try:
+            v = json.loads(tok)
+            ok = isinstance(v, (int, float)) and not isinstance(v, bool)
+        except ValueError:
+            ok = False
+        _, st = parse_token(tok.encode(), BINARY64, 2)
+        assert (st != 1) == ok, tok
+
+
+def test_infnan_acceptance_matches_float():
+    """Letter tokens: accepted with the inf/nan flag exactly when float()
+    reads them (float also accepts blanks and digit separators: none are
+    generated), and then to the same infinity or NaN."""
+    rng = np.random.default_rng(6)
+    pieces = ["", "-", "+", "i", "I", "n", "N", "f", "F", "a", "A", "in", "nan", "inf",
+              "ity", "ini", "t", "y"]
+    toks = set()
+    for _ in range(20_000):
+        k = int(rng.integers(1, 5))
+        toks.add("".join(pieces[int(i)] for i in rng.integers(0, len(pieces), k)))
+    for tok in toks:
+        if not tok:
+            continue
+        try:
+            v = float(tok)
+            ok = True
+        except ValueError:
+            ok = False
+        bits, st = parse_token(tok.encode(), BINARY64, 4)
+        assert (st == 0) == ok, tok
+        if ok:
+            want = struct.unpack("<Q", struct.pack("<d", v))[0]
+            if math.isnan(v):
+                assert bits & 0x7FFFFFFFFFFFFFFF == 0x7FF8000000000000, tok
+                assert bool(bits >> 63) == tok.startswith("-"), tok
+            else:
+                assert bits == want, tok
