@@ -63,6 +63,16 @@ enum ffp_error {
 
 /* Reject a leading '+' sign, as JSON does (Section 4). */
 #define FFP_REJECT_PLUS 1u
+/* JSON numbers: the number grammar of the JSON specification, i.e. the
+ * grammar below without '+', without leading zeros ("01") and with digits on
+ * both sides of a '.' (".5" and "1." are rejected).  With delimiters such as
+ * "[],: \n" the numbers of a JSON document of arrays (the paper's canada
+ * test file, Section 12) are its tokens; other tokens come back invalid. */
+#define FFP_JSON 2u
+/* Accept inf, infinity and nan in any letter case with an optional sign:
+ * +-infinity (status FFP_OK) and the canonical quiet NaN with the token's
+ * sign (status FFP_OK). */
+#define FFP_INFNAN 4u
 
 /* ---------------------------------------------------------------------------
  * Options.  delim_set is a 256-bit set of delimiter bytes: byte c is a

@@ -245,7 +245,27 @@ FFP_HD bool is_digit(uint32_t c) { return (c - '0') < 10u; }
 // position past the end of the buffer, so the lexer never needs the token
 // length: it consumes the grammar and then requires a delimiter.
 // ---------------------------------------------------------------------------
-enum LexKind : uint32_t { kLexExact = 0, kLexTruncated = 1, kLexInvalid = 2 };
+enum LexKind : uint32_t {
+  kLexExact = 0,
+  kLexTruncated = 1,
+  kLexInvalid = 2,
+  kLexInf = 3,  // inf / infinity (flag FFP_INFNAN)
+  kLexNaN = 4   // nan (flag FFP_INFNAN)
+};
+
+// Grammar flags (public values of include/ffp.h).
+constexpr uint32_t kFlagRejectPlus = 1;
+constexpr uint32_t kFlagJson = 2;    // JSON number grammar
+constexpr uint32_t kFlagInfNan = 4;  // inf, infinity, nan in any case
+
+// Case-insensitive match of the letters of `word` at pos; returns the
+// position after them, or 0 if they do not match.
+template <class Src>
+FFP_HD uint64_t match_word(const Src& src, uint64_t pos, const char* word) {
+  for (; *word; ++word, ++pos)
+    if ((src(pos) | 0x20u) != (uint32_t)*word) return 0;
+  return pos;
+}
 
 struct Lexed {
   uint64_t w;
@@ -270,15 +290,31 @@ FFP_HD Lexed lex_token(const Src& src, uint64_t pos, uint32_t flags) {
     r.neg = 1;
     c = src(++pos);
   } else if (c == '+') {
-    if (flags & 1u) r.kind = kLexInvalid;
+    if (flags & (kFlagRejectPlus | kFlagJson)) r.kind = kLexInvalid;
     c = src(++pos);
   }
+  if ((flags & kFlagInfNan) && ((c | 0x20u) == 'i' || (c | 0x20u) == 'n')) {
+    uint64_t e = 0;
+    uint32_t kind = kLexInvalid;
+    if ((e = match_word(src, pos, "infinity")) && src.is_end(src(e))) {
+      kind = kLexInf;
+    } else if ((e = match_word(src, pos, "inf")) && src.is_end(src(e))) {
+      kind = kLexInf;
+    } else if ((e = match_word(src, pos, "nan")) && src.is_end(src(e))) {
+      kind = kLexNaN;
+    }
+    if (r.kind != kLexInvalid) r.kind = kind;
+    return r;
+  }
+  const uint32_t first_digit = c;  // for the JSON leading-zero rule
   uint32_t nsig = 0;
   int64_t ndig = 0, nfrac = 0, dropped = 0;
   uint32_t nonzero_dropped = 0;
   uint64_t w = 0;
+  int64_t nint = 0;
   // integer part
   while (is_digit(c)) {
+    ++nint;
     const uint32_t d = c - '0';
     ++ndig;
     if (nsig < 19) {
@@ -310,8 +346,11 @@ FFP_HD Lexed lex_token(const Src& src, uint64_t pos, uint32_t flags) {
       c = src(++pos);
     }
     nfrac = ndig - before;
+    if ((flags & kFlagJson) && nfrac == 0) r.kind = kLexInvalid;  // "1." is not JSON
   }
   if (ndig == 0) r.kind = kLexInvalid;
+  if ((flags & kFlagJson) && (nint == 0 || (nint > 1 && first_digit == '0')))
+    r.kind = kLexInvalid;  // ".5" and leading zeros are not JSON
   int64_t e = 0;
   if ((c | 0x20u) == 'e') {
     c = src(++pos);
@@ -369,6 +408,12 @@ FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* tabl
     d.bits = qnan;
     d.status = kStInvalid;
     d.path = kCntInvalid;
+    return d;
+  }
+  if (L.kind == kLexInf || L.kind == kLexNaN) {
+    d.bits = (L.kind == kLexInf ? fmt.inf : qnan) | (L.neg ? sign : 0);
+    d.status = kStOk;
+    d.path = kCntEarly;
     return d;
   }
   if (L.w == 0) {

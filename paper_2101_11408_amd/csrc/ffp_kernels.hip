@@ -485,8 +485,15 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
   const int end = has_e ? e1 : f1;
   const int nint = b - a, nfrac = f1 - f0, nexp = e1 - e0;
   r.neg = c0 == '-';
-  const bool valid = end == L && nint + nfrac > 0 && (!has_e || nexp > 0) &&
-                     !(c0 == '+' && (flags & 1u));
+  bool valid = end == L && nint + nfrac > 0 && (!has_e || nexp > 0) &&
+               !(c0 == '+' && (flags & (kFlagRejectPlus | kFlagJson)));
+  if (flags & (kFlagJson | kFlagInfNan)) {  // the same for every lane
+    const uint32_t ca = tb[s + a];  // first byte after the sign
+    if (flags & kFlagJson)  // no ".5", no "1.", no leading zeros
+      valid = valid && nint > 0 && (!dot || nfrac > 0) && !(nint > 1 && ca == '0');
+    if (!valid && (flags & kFlagInfNan) && ((ca | 0x20u) == 'i' || (ca | 0x20u) == 'n'))
+      return r;  // inf / nan: the byte-by-byte lexer
+  }
   if (!valid) {
     r.code = kFastInvalid;
     return r;

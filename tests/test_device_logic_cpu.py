@@ -144,3 +144,23 @@ def test_half_formats(host_check):
     for fmt in ("f16", "bf16"):
         nfb = check(host_check, buf, fmt, "half")
         assert nfb > 0
+
+
+def _flag_tokens(seed):
+    rng = np.random.default_rng(seed)
+    parts = ["", "-", "+", "0", "00", "1", "01", "9", "12", ".", ".5", "5.", "e", "E",
+             "e+", "e-", "3", "0.", ".0", "inf", "Inf", "nan", "NaN", "infinity", "INFINITY",
+             "in", "na"]
+    toks = set()
+    for _ in range(6000):
+        k = int(rng.integers(1, 5))
+        toks.add("".join(parts[int(i)] for i in rng.integers(0, len(parts), k)))
+    return sorted(t for t in toks if t)
+
+
+@pytest.mark.parametrize("flags", [2, 4, 6, 5])
+def test_json_and_infnan_flags(host_check, flags):
+    """The byte-by-byte lexer under the JSON and inf/nan flags."""
+    buf = W.join_tokens(_flag_tokens(49))
+    for fmt in ("f64", "f32"):
+        check(host_check, buf, fmt, "flags-%d" % flags, flags=flags)

@@ -348,3 +348,74 @@ def test_bfloat16_values_and_midpoints(ctx):
     buf = W.join_tokens(toks)
     _log("bfloat16 tokens", len(toks))
     compare_full(ctx, buf, "bf16", "bfloat16-sampled")
+
+
+# ---------------------------------------------------------------------------
+# JSON grammar, inf/nan, JSON documents
+# ---------------------------------------------------------------------------
+
+def _flag_tokens(seed, n=8000):
+    rng = np.random.default_rng(seed)
+    parts = ["", "-", "+", "0", "00", "1", "01", "9", "12", ".", ".5", "5.", "e", "E",
+             "e+", "e-", "3", "0.", ".0", "inf", "Inf", "nan", "NaN", "infinity", "INFINITY",
+             "in", "na", "0.1234567890123456789", "123456789012345678901234"]
+    toks = []
+    for _ in range(n):
+        k = int(rng.integers(1, 5))
+        t = "".join(parts[int(i)] for i in rng.integers(0, len(parts), k))
+        if t:
+            toks.append(t)
+    return toks
+
+
+@pytest.mark.parametrize("flags", [2, 4, 6])
+def test_json_and_infnan_flags(ffpmod, flags):
+    rng = np.random.default_rng(62 + flags)
+    toks = _flag_tokens(70 + flags) + W.mixed_tokens(rng, 20_000)
+    rng.shuffle(toks)
+    buf = W.join_tokens(toks)
+    c = ffpmod.Context(0, flags=flags)
+    try:
+        for fmt in ("f64", "f32", "f16"):
+            _log("case flags", flags, fmt)
+            rc, n, bits, status = run_gpu(c, buf, fmt)
+            wb, ws = parse_buffer(buf, fmt, flags=flags)
+            assert rc == len(wb) and n == len(wb)
+            bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                 (status[:n] != np.array(ws, dtype=np.uint8)))
+            assert bad.size == 0, (flags, fmt, [toks[i] for i in bad[:5]])
+    finally:
+        c.close()
+
+
+def _geojson(rng, nfeat):
+    """A GeoJSON-like document: features with coordinate rings of numbers
+    printed with 6-15 fraction digits (the shape of the canada data)."""
+    out = ['{"type":"FeatureCollection","features":[']
+    for f in range(nfeat):
+        ring = ",".join("[%.*f,%.*f]" % (int(rng.integers(6, 16)), float(x),
+                                         int(rng.integers(6, 16)), float(y))
+                        for x, y in zip(rng.uniform(-180, 180, 40), rng.uniform(-90, 90, 40)))
+        out.append('{"type":"Feature","properties":{"name":"n%d"},"geometry":'
+                   '{"type":"Polygon","coordinates":[[%s]]}}%s' % (f, ring,
+                                                                   "," if f + 1 < nfeat else ""))
+    out.append("]}\n")
+    return "".join(out).encode()
+
+
+def test_json_document_numbers(ffpmod):
+    """Numbers of a JSON document with its structure bytes as delimiters:
+    every coordinate parses, keys and string values come back invalid."""
+    rng = np.random.default_rng(63)
+    doc = _geojson(rng, 400)
+    delims = b'[]{},:" \n'
+    c = ffpmod.Context(0, delims=delims, flags=ffpmod.FFP_JSON)
+    try:
+        rc, n, bits, status = run_gpu(c, doc, "f64")
+        wb, ws = parse_buffer(doc, "f64", delims=delims, flags=2)
+        assert rc == len(wb) == n
+        assert np.array_equal(bits[:n], np.array(wb, dtype=np.uint64))
+        assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8))
+        assert int((status[:n] == 0).sum()) == 400 * 40 * 2
+    finally:
+        c.close()
