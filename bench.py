@@ -28,6 +28,7 @@ the CPU oracle on a bounded sample of the same text (config2 only).
 
 import argparse
 import hashlib
+import re
 import json
 import multiprocessing as mp
 import os
@@ -45,6 +46,7 @@ WORKLOAD_NAMES = {
     "config4u": "config4u-4096-buffers-uniform-batched",
     "config5": "config5-served-poisson",
     "copycal": "copy-calibration",
+    "jsondoc": "jsondoc-10M-coordinates-binary64-plain",
 }
 OUT_NAMES = {"f64": "binary64", "f32": "binary32", "f16": "binary16", "bf16": "bfloat16"}
 METRIC = "GB/s input text + Mfloats/s parsed (bit-exact), batched/served vs plain; p50/p99"
@@ -184,7 +186,8 @@ def timed_steps(torch, fn, steps, warmup):
 # single-buffer workloads
 # ---------------------------------------------------------------------------
 
-def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False):
+def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False, delims=b"\n",
+              flags=0, expect_ok=None):
     import torch
     from paper_2101_11408_amd import ffp
     dev = torch.device("cuda", 0)
@@ -194,11 +197,17 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False):
     values = torch.empty(ntok, dtype=dt, device=dev)
     status = torch.empty(ntok, dtype=torch.uint8, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
-    ctx = ffp.Context(0)
+    ctx = ffp.Context(0, delims=delims, flags=flags)
     ctx.reserve(len(buf))
+    red = None
+    if args.reduce:
+        red = torch.zeros(3, dtype=torch.int64, device=dev)
+        ctx.set_reduce(red)
     stream = torch.cuda.current_stream()
     n = ctx.parse_into(text, values, status, count, stream=stream, sync=True)
     assert n == ntok, n
+    if expect_ok is not None:
+        assert int((status[:n] == 0).sum()) == expect_ok
     ms = timed_steps(torch, lambda: ctx.parse_into(text, values, status, count, stream=stream),
                      0, args.warmup)
     ctx.timing(True)
@@ -220,6 +229,9 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False):
     rec["mfloats_per_s"] = round(ntok / (ms / 1e3) / 1e6, 1)
     rec["roofline"] = roofline(alg, kavg, workload)
     rec["cpu_baseline"] = cpu_baseline(buf, min(args.cpu_sample, ntok)) if cpu else None
+    if red is not None:
+        mn, mx, cnt = [int(x) & 0xFFFFFFFFFFFFFFFF for x in red.cpu().tolist()]
+        rec["reduce"] = {"min_bits": hex(mn), "max_bits": hex(mx), "count": cnt}
     ctx.close()
     return rec
 
@@ -592,9 +604,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config4u",
-                             "config5", "copycal"])
+                             "config5", "copycal", "jsondoc"])
     ap.add_argument("--tokens", type=int, default=None)
     ap.add_argument("--nbuf", type=int, default=4096)
+    ap.add_argument("--reduce", action="store_true",
+                    help="plain workloads: also keep the min, max and count of the values")
     ap.add_argument("--out", default="f64", choices=["f64", "f32", "f16", "bf16"],
                     help="plain workloads: output format")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -670,6 +684,19 @@ def main():
                         out_dtype=args.out)
     elif wl == "config4":
         rec = run_batched(args, "mixed", WORKLOAD_NAMES[wl])
+    elif wl == "jsondoc":
+        t0 = time.time()
+        nfeat = (args.tokens or 10_000_000) // 2000
+        doc = W.geojson_document(7, nfeat, 1000)
+        ntok = len(re.findall(b"[^" + re.escape(W.JSON_DELIMS) + b"]+", doc))
+        log("generated %d bytes, %d tokens in %.1f s" % (len(doc), ntok, time.time() - t0))
+        rec = run_plain(args, doc, ntok, out_name(wl, args.out),
+                        "GeoJSON-like document (%.1f MB): %d features of 1000 coordinate pairs "
+                        "with 6-15 fraction digits; JSON number grammar, the document's "
+                        "structure bytes as delimiters (keys and strings come back invalid); "
+                        "%s" % (len(doc) / 1e6, nfeat, OUT_NAMES[args.out]),
+                        out_dtype=args.out, delims=W.JSON_DELIMS, flags=2,
+                        expect_ok=nfeat * 2000)
     elif wl == "config5":
         rec = run_served(args, WORKLOAD_NAMES[wl])
     elif wl == "copycal":

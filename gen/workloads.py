@@ -426,3 +426,27 @@ def config5_requests(seed: int, rate: float, count: int):
     is_f32 = rng.random(count) < 0.10
     is_hard = rng.random(count) < 0.01
     return t, sizes, is_f32, is_hard
+
+
+def geojson_document(seed: int, nfeat: int, npts: int) -> bytes:
+    """A GeoJSON-like document (the shape of the canada test file): nfeat
+    polygon features of npts [longitude, latitude] pairs printed with 6-15
+    fraction digits, keys and strings around them."""
+    rng = np.random.default_rng(seed)
+    out = ['{"type":"FeatureCollection","features":[']
+    for f in range(nfeat):
+        xs = rng.uniform(-180, 180, npts)
+        ys = rng.uniform(-90, 90, npts)
+        kx = rng.integers(6, 16, npts)
+        ky = rng.integers(6, 16, npts)
+        ring = ",".join("[%.*f,%.*f]" % (int(a), float(x), int(b), float(y))
+                        for a, x, b, y in zip(kx, xs, ky, ys))
+        out.append('{"type":"Feature","properties":{"name":"n%d"},"geometry":'
+                   '{"type":"Polygon","coordinates":[[%s]]}}%s'
+                   % (f, ring, "," if f + 1 < nfeat else ""))
+    out.append("]}\n")
+    return "".join(out).encode()
+
+
+# Delimiters that make the numbers of such a document its tokens.
+JSON_DELIMS = b'[]{},:" \n'

@@ -265,6 +265,18 @@ int ffp_timing_enable(ffp_ctx* ctx, int enable);
 int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches);
 
 /* ---------------------------------------------------------------------------
+ * In-kernel reduction (the paper's benchmark keeps the running minimum of
+ * the parsed values, Section 12).  With d_out set (a device array of three
+ * uint64_t), every later plain parse call on the context also writes, when
+ * its last kernel ends: d_out[0] the encoding of the smallest value and
+ * d_out[1] of the largest among the tokens with status FFP_OK that are not
+ * NaN (-0 orders before +0), zero-extended to 64 bits, and d_out[2] their
+ * number; with no such token both encodings are the canonical quiet NaN.
+ * NULL turns it off.  Batched calls ignore it.
+ * ------------------------------------------------------------------------- */
+int ffp_set_reduce(ffp_ctx* ctx, uint64_t* d_out);
+
+/* ---------------------------------------------------------------------------
  * Device path counters (Table 5 of the paper reports the same categories on
  * CPUs).  When enabled, the parse kernels count tokens per path; reading
  * synchronises.  counters[0..5]: tokens, invalid, early-exit (zero / out of

@@ -143,6 +143,7 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uin
   P.delim = ctx->delim;
   P.flags = ctx->flags;
   P.count_paths = ctx->counters ? 1u : 0u;
+  P.reduce_out = js.jobs ? nullptr : ctx->reduce_out;  // plain calls only
   uint64_t grid = (uint64_t)shape.grid;
   if (grid > nblocks) grid = nblocks;
 
@@ -170,6 +171,7 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uin
   F.queue_cap = ctx->queue_cap;
   F.st = ctx->d_state;
   F.delim = ctx->delim;
+  F.reduce_out = P.reduce_out;
   if (ffp::launch_fallback(F, ctx->fb_grid, s) != hipSuccess) return FFP_E_HIP;
   return FFP_SUCCESS;
 }
@@ -700,6 +702,12 @@ int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches) {
   *launches = ctx->timed_launches;
   ctx->timed_ms = 0.0;
   ctx->timed_launches = 0;
+  return FFP_SUCCESS;
+}
+
+int ffp_set_reduce(ffp_ctx* ctx, uint64_t* d_out) {
+  if (!ctx) return FFP_E_ARG;
+  ctx->reduce_out = d_out;
   return FFP_SUCCESS;
 }
 

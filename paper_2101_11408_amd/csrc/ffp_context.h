@@ -42,6 +42,7 @@ struct ffp_ctx {
   uint64_t timed_launches = 0;
 
   bool counters = false;
+  uint64_t* reduce_out = nullptr;  // plain calls: min, max, count of the values
 };
 
 struct ffp_graph {

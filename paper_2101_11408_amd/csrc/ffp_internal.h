@@ -73,9 +73,12 @@ struct QueueEntry {
 
 struct DeviceState {
   unsigned int error;
+  unsigned int done_wgs;            // fallback workgroups finished (reduction)
   unsigned long long queue_tail;
   unsigned long long total_blocks;  // batched calls: blocks of all jobs
   unsigned long long counters[8];
+  // min / max of the order keys of the values and their count (reduction)
+  unsigned long long red_min, red_max, red_count;
 };
 
 struct DelimSet {
@@ -138,6 +141,7 @@ struct ParseParams {
   DelimSet delim;
   uint32_t flags;           // FFP_REJECT_PLUS ...
   uint32_t count_paths;
+  uint64_t* reduce_out;     // plain calls: min, max, count of the values (or null)
 };
 
 struct FallbackParams {
@@ -146,6 +150,7 @@ struct FallbackParams {
   uint64_t queue_cap;
   DeviceState* st;
   DelimSet delim;
+  uint64_t* reduce_out;  // as in ParseParams
 };
 
 }  // namespace ffp

@@ -44,6 +44,52 @@ __device__ __forceinline__ void gstore(T* p, T v) {
   *(FFP_GLOBAL T*)p = v;  // address-space cast: a global store
 }
 
+// Reduction of parsed values: a key whose unsigned order is the numeric
+// order of the encodings of a `width`-bit format (-0 before +0).  NaN, and
+// tokens whose status is not FFP_OK, are left out: their key is kNoMin for
+// the minimum and kNoMax for the maximum.
+constexpr uint64_t kNoMin = ~0ull;
+constexpr uint64_t kNoMax = 0ull;
+
+__device__ __forceinline__ int dtype_width(uint32_t dtype) {
+  return dtype == kF64 ? 64 : dtype == kF32 ? 32 : 16;
+}
+
+__device__ __forceinline__ uint64_t dtype_inf(uint32_t dtype) {
+  return dtype == kF64 ? F64::kInf : dtype == kF32 ? F32::kInf : dtype == kF16 ? F16::kInf : BF16::kInf;
+}
+
+__device__ __forceinline__ bool order_key(uint64_t bits, uint32_t status, uint32_t dtype,
+                                          uint64_t& key) {
+  const int width = dtype_width(dtype);
+  const uint64_t mag = bits & ((1ull << (width - 1)) - 1);
+  if (status != kStOk || mag > dtype_inf(dtype)) return false;
+  const uint64_t x = bits << (64 - width);
+  key = (x >> 63) ? ~x : (x | (1ull << 63));
+  return true;
+}
+
+__device__ __forceinline__ uint64_t key_to_bits(uint64_t key, uint32_t dtype) {
+  const uint64_t x = (key >> 63) ? (key & ~(1ull << 63)) : ~key;
+  return x >> (64 - dtype_width(dtype));
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
   return v;
@@ -265,6 +311,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
     P.block_sum[n] = s_carry;
     P.st->queue_tail = 0;
     P.st->error = 0;
+    P.st->done_wgs = 0;
+    P.st->red_min = ~0ull;
+    P.st->red_max = 0;
+    P.st->red_count = 0;
   }
   __syncthreads();
   // token count of every job: prefix at its end minus prefix at its start
@@ -367,6 +417,7 @@ struct TileSmem {
   uint8_t delim_lut[256];
   Packed scan[kThreads / kWave];
   uint32_t prev_nd;
+  unsigned long long red_min, red_max, red_count;  // this workgroup's reduction
 };
 
 struct LdsSrc {
@@ -514,8 +565,11 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
 template <class F>
 __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, const JobDesc& job,
                                             uint64_t idx, const unsigned long long* table,
-                                            const ParseParams& P) {
+                                            const ParseParams& P, uint64_t& bits_out,
+                                            uint32_t& status_out) {
   Decision<F> d = decide_lexed<F>(L, table);
+  bits_out = d.bits;
+  status_out = d.fallback ? kPending : d.status;
   uint8_t st = (uint8_t)d.status;
   if (d.fallback) {
     const unsigned long long slot = atomicAdd(&P.st->queue_tail, 1ull);
@@ -535,8 +589,10 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
   return (int)d.path;
 }
 
-template <int K, bool kSingle>
-// Four workgroups per CU (the LDS allows four): keep registers within 128.
+// Four workgroups per CU (the LDS allows four): registers are kept within
+// 128.  kReduce: the call also keeps the minimum, maximum and count of the
+// values (a separate instance, so that the plain parse pays nothing for it).
+template <int K, bool kSingle, bool kReduce>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_parse(ParseParams P) {
   using S = TileSmem<K>;
   using Packed = typename S::Packed;
@@ -558,6 +614,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   if (tid < 8) {
     sm.nd[S::kChunks + tid] = 0;
     sm.dg[S::kChunks + tid] = 0;
+  }
+  if (tid == 0) {
+    sm.red_min = kNoMin;
+    sm.red_max = kNoMax;
+    sm.red_count = 0;
   }
   const uint32_t drep = P.delim.byte * 0x01010101u;
   const uint64_t nblk = total_blocks_of(P.js);
@@ -656,41 +717,61 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       const uint32_t nfit = next_idx >= job.capacity ? 0u
                             : (job.capacity - next_idx < ntok ? (uint32_t)(job.capacity - next_idx)
                                                               : ntok);
-      for (uint32_t j = tid; j < nfit; j += kThreads) {
-        const uint64_t idx = next_idx + j;
-        const uint32_t s = sm.starts[j];
-        const uint64_t vpos = tile_start + s;  // virtual
-        const uint64_t pos = vpos - align;     // offset in the text
-        const bool global = straddle && j == ntok - 1;
-        FastLex fl;
-        if (!global) {
-          fl = fast_lex<K>(sm, s, P.flags);
-        } else {
-          fl.code = kFastSlow;
+      // whole rounds of 256 tokens: lanes without a token in the last round
+      // stay in step, so the reduction below sees every lane
+      for (uint32_t round = 0; round < nfit; round += kThreads) {
+        const uint32_t j = round + tid;
+        const bool has_token = j < nfit;
+        uint64_t vbits = 0;
+        uint32_t vstatus = kStInvalid;
+        if (has_token) {
+          const uint64_t idx = next_idx + j;
+          const uint32_t s = sm.starts[j];
+          const uint64_t vpos = tile_start + s;  // virtual
+          const uint64_t pos = vpos - align;     // offset in the text
+          const bool global = straddle && j == ntok - 1;
+          FastLex fl;
+          if (!global) {
+            fl = fast_lex<K>(sm, s, P.flags);
+          } else {
+            fl.code = kFastSlow;
+          }
+          Lexed L;
+          if (fl.code == kFastSlow) {
+            L = global ? lex_token(gsrc, pos, P.flags) : lex_token(lsrc, vpos, P.flags);
+          } else {
+            L.w = fl.w;
+            L.q = fl.q;
+            L.neg = fl.neg;
+            L.kind = fl.code == kFastInvalid ? kLexInvalid : kLexExact;
+          }
+          int path;
+          switch (job.dtype) {
+            case kF64: path = finish_token<F64>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            case kF32: path = finish_token<F32>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            case kF16: path = finish_token<F16>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            default: path = finish_token<BF16>(L, pos, job, idx, table, P, vbits, vstatus); break;
+          }
+          if (P.count_paths) {
+            c_tok += 1;
+            c_inv += path == kCntInvalid;
+            c_early += path == kCntEarly;
+            c_one += path == kCntOne;
+            c_two += path == kCntTwo;
+            c_fb += path == kCntFallback;
+          }
         }
-        Lexed L;
-        if (fl.code == kFastSlow) {
-          L = global ? lex_token(gsrc, pos, P.flags) : lex_token(lsrc, vpos, P.flags);
-        } else {
-          L.w = fl.w;
-          L.q = fl.q;
-          L.neg = fl.neg;
-          L.kind = fl.code == kFastInvalid ? kLexInvalid : kLexExact;
-        }
-        int path;
-        switch (job.dtype) {
-          case kF64: path = finish_token<F64>(L, pos, job, idx, table, P); break;
-          case kF32: path = finish_token<F32>(L, pos, job, idx, table, P); break;
-          case kF16: path = finish_token<F16>(L, pos, job, idx, table, P); break;
-          default: path = finish_token<BF16>(L, pos, job, idx, table, P); break;
-        }
-        if (P.count_paths) {
-          c_tok += 1;
-          c_inv += path == kCntInvalid;
-          c_early += path == kCntEarly;
-          c_one += path == kCntOne;
-          c_two += path == kCntTwo;
-          c_fb += path == kCntFallback;
+        if (kReduce) {
+          uint64_t key = 0;
+          const bool in = has_token && order_key(vbits, vstatus, job.dtype, key);
+          const uint64_t kmin = wave_min_u64(in ? key : kNoMin);
+          const uint64_t kmax = wave_max_u64(in ? key : kNoMax);
+          const uint64_t cnt = wave_sum_u64(in ? 1u : 0u);
+          if (lane == 0 && cnt) {
+            atomicMin(&sm.red_min, (unsigned long long)kmin);
+            atomicMax(&sm.red_max, (unsigned long long)kmax);
+            atomicAdd(&sm.red_count, (unsigned long long)cnt);
+          }
         }
       }
       next_idx += ntok;
@@ -698,6 +779,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     }
   }
 
+  if (kReduce) {
+    __syncthreads();
+    if (tid == 0 && sm.red_count) {
+      atomicMin(&P.st->red_min, sm.red_min);
+      atomicMax(&P.st->red_max, sm.red_max);
+      atomicAdd(&P.st->red_count, sm.red_count);
+    }
+  }
   if (P.count_paths) {
     const uint32_t cnt[kNumCounters] = {c_tok, c_inv, c_early, c_one, c_two, c_fb};
 #pragma unroll
@@ -717,13 +806,19 @@ constexpr int kFbWaves = kFbThreads / kWave;
 
 template <class F>
 __device__ __forceinline__ void fallback_token(const JobDesc& job, uint64_t pos, uint64_t idx,
-                                               FbLds* lds) {
+                                               FbLds* lds, const FallbackParams& P) {
   typename F::bits_t bits;
   uint32_t status;
   fb_decide<F>(job.text, job.nbytes, pos, g_table, lds, bits, status);
   if (fb_lane() == 0) {
     gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, bits);
     gstore(job.status + idx, (uint8_t)status);
+    uint64_t key;
+    if (P.reduce_out && order_key(bits, status, job.dtype, key)) {
+      atomicMin(&P.st->red_min, (unsigned long long)key);
+      atomicMax(&P.st->red_max, (unsigned long long)key);
+      atomicAdd(&P.st->red_count, 1ull);
+    }
   }
 }
 
@@ -740,10 +835,27 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(FallbackParams P) {
     const JobDesc job = P.js.jobs ? P.js.jobs[job_id] : P.js.single;
     fb_wave_sync();  // the previous token's LDS reads are done
     switch (job.dtype) {
-      case kF64: fallback_token<F64>(job, e.offset, idx, &lds[wid]); break;
-      case kF32: fallback_token<F32>(job, e.offset, idx, &lds[wid]); break;
-      case kF16: fallback_token<F16>(job, e.offset, idx, &lds[wid]); break;
-      default: fallback_token<BF16>(job, e.offset, idx, &lds[wid]); break;
+      case kF64: fallback_token<F64>(job, e.offset, idx, &lds[wid], P); break;
+      case kF32: fallback_token<F32>(job, e.offset, idx, &lds[wid], P); break;
+      case kF16: fallback_token<F16>(job, e.offset, idx, &lds[wid], P); break;
+      default: fallback_token<BF16>(job, e.offset, idx, &lds[wid], P); break;
+    }
+  }
+  if (P.reduce_out) {  // the last workgroup to finish writes the result
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd(&P.st->done_wgs, 1u) == gridDim.x - 1) {
+        const unsigned long long kmin = atomicAdd(&P.st->red_min, 0ull);
+        const unsigned long long kmax = atomicAdd(&P.st->red_max, 0ull);
+        const unsigned long long cnt = atomicAdd(&P.st->red_count, 0ull);
+        const uint32_t dt = P.js.single.dtype;
+        const uint64_t nan = dt == kF64 ? F64::kQNaN : dt == kF32 ? F32::kQNaN
+                             : dt == kF16 ? F16::kQNaN : BF16::kQNaN;
+        gstore(P.reduce_out + 0, cnt ? key_to_bits(kmin, dt) : nan);
+        gstore(P.reduce_out + 1, cnt ? key_to_bits(kmax, dt) : nan);
+        gstore(P.reduce_out + 2, (uint64_t)cnt);
+      }
     }
   }
 }
@@ -755,8 +867,9 @@ int parse_tile_bytes(int k) { return kThreads * kChunk * k; }
 
 template <int K>
 static hipError_t occ_k(bool single, int* blocks) {
-  return single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_parse<K, true>, kThreads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_parse<K, false>, kThreads, 0);
+  return single
+             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_parse<K, true, false>, kThreads, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_parse<K, false, false>, kThreads, 0);
 }
 
 hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu) {
@@ -798,7 +911,10 @@ hipError_t launch_scan(const ScanParams& P, hipStream_t s) {
 
 template <int K, bool kSingle>
 static hipError_t launch_parse_k(const ParseParams& P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_parse<K, kSingle>), dim3(grid), dim3(kThreads), 0, s, P);
+  if (P.reduce_out)
+    hipLaunchKernelGGL((k_parse<K, kSingle, true>), dim3(grid), dim3(kThreads), 0, s, P);
+  else
+    hipLaunchKernelGGL((k_parse<K, kSingle, false>), dim3(grid), dim3(kThreads), 0, s, P);
   return hipGetLastError();
 }
 

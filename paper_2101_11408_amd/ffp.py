@@ -115,6 +115,7 @@ _SIGNATURES = {
     "ffp_timing_enable": (_INT, [_P, _INT]),
     "ffp_timing_read": (_INT, [_P, _c.POINTER(_c.c_double), _c.POINTER(_U64)]),
     "ffp_counters_enable": (_INT, [_P, _INT]),
+    "ffp_set_reduce": (_INT, [_P, _P]),
     "ffp_counters_read": (_INT, [_P, _U64 * 6]),
     "ffp_parse_batch": (_INT, [_P, _P, _c.c_uint32, _U64, _P]),
     "ffp_batch_graph_create": (_INT, [_P, _P, _c.c_uint32, _U64, _c.POINTER(_P)]),
@@ -261,6 +262,11 @@ class Context:
 
     def counters(self, enable: bool = True):
         check(load().ffp_counters_enable(self.handle, 1 if enable else 0))
+
+    def set_reduce(self, out=None):
+        """out: device int64 tensor of 3 elements (min bits, max bits, count)
+        written by every later plain call; None turns the reduction off."""
+        check(load().ffp_set_reduce(self.handle, out.data_ptr() if out is not None else None))
 
     def counters_read(self):
         arr = (ctypes.c_uint64 * 6)()

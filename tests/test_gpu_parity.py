@@ -1,6 +1,7 @@
 """Parity of the HIP path with the CPU oracle, bit for bit, on values, status
 codes and the token count.  Every call goes through the C-ABI (libffp.so)."""
 
+import math
 import os
 
 import numpy as np
@@ -388,27 +389,11 @@ def test_json_and_infnan_flags(ffpmod, flags):
         c.close()
 
 
-def _geojson(rng, nfeat):
-    """A GeoJSON-like document: features with coordinate rings of numbers
-    printed with 6-15 fraction digits (the shape of the canada data)."""
-    out = ['{"type":"FeatureCollection","features":[']
-    for f in range(nfeat):
-        ring = ",".join("[%.*f,%.*f]" % (int(rng.integers(6, 16)), float(x),
-                                         int(rng.integers(6, 16)), float(y))
-                        for x, y in zip(rng.uniform(-180, 180, 40), rng.uniform(-90, 90, 40)))
-        out.append('{"type":"Feature","properties":{"name":"n%d"},"geometry":'
-                   '{"type":"Polygon","coordinates":[[%s]]}}%s' % (f, ring,
-                                                                   "," if f + 1 < nfeat else ""))
-    out.append("]}\n")
-    return "".join(out).encode()
-
-
 def test_json_document_numbers(ffpmod):
     """Numbers of a JSON document with its structure bytes as delimiters:
     every coordinate parses, keys and string values come back invalid."""
-    rng = np.random.default_rng(63)
-    doc = _geojson(rng, 400)
-    delims = b'[]{},:" \n'
+    doc = W.geojson_document(63, 400, 40)
+    delims = W.JSON_DELIMS
     c = ffpmod.Context(0, delims=delims, flags=ffpmod.FFP_JSON)
     try:
         rc, n, bits, status = run_gpu(c, doc, "f64")
@@ -417,5 +402,56 @@ def test_json_document_numbers(ffpmod):
         assert np.array_equal(bits[:n], np.array(wb, dtype=np.uint64))
         assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8))
         assert int((status[:n] == 0).sum()) == 400 * 40 * 2
+    finally:
+        c.close()
+
+
+# ---------------------------------------------------------------------------
+# in-kernel reduction
+# ---------------------------------------------------------------------------
+
+def _expected_minmax(bits, status, fmt):
+    """(min bits, max bits, count) over OK, non-NaN values: numeric order,
+    -0 before +0; NaN encodings for an empty set."""
+    npdt = {"f64": np.float64, "f32": np.float32, "f16": np.float16}
+    vals = []
+    for b, s in zip(bits, status):
+        if s != 0:
+            continue
+        if fmt == "bf16":
+            v = float(np.array([b << 16], dtype=np.uint32).view(np.float32)[0])
+        else:
+            v = float(np.array([b], dtype=NP_DT[fmt]).view(npdt[fmt])[0])
+        if v != v:
+            continue
+        vals.append(((v, 1 if (v != 0 or not math.copysign(1, v) < 0) else 0), b))
+    if not vals:
+        qnan = {"f64": 0x7FF8000000000000, "f32": 0x7FC00000, "f16": 0x7E00, "bf16": 0x7FC0}
+        return qnan[fmt], qnan[fmt], 0
+    return min(vals)[1], max(vals)[1], len(vals)
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32", "f16", "bf16"])
+def test_min_max_reduction(ffpmod, fmt):
+    rng = np.random.default_rng(64)
+    toks = W.mixed_tokens(rng, 50_000) + W.hard_tokens(rng, 2000)
+    toks += ["-0", "0", "nan", "-nan", "inf", "-inf", "x1", "1e999", "-1e999", "1e-999"]
+    rng.shuffle(toks)
+    buf = W.join_tokens(toks)
+    c = ffpmod.Context(0, flags=ffpmod.FFP_INFNAN)
+    out = torch.full((3,), -1, dtype=torch.int64, device="cuda:0")
+    try:
+        c.set_reduce(out)
+        for rep in range(2):  # the second call starts from a clean state
+            rc, n, bits, status = run_gpu(c, buf, fmt)
+            got = [int(x) & 0xFFFFFFFFFFFFFFFF for x in out.cpu().tolist()]
+            wb, ws = parse_buffer(buf, fmt, flags=4)
+            want = _expected_minmax(wb, ws, fmt)
+            assert tuple(got) == want, (fmt, rep, [hex(x) for x in got], [hex(x) for x in want])
+        # nothing to reduce: NaN encodings and a zero count
+        rc, n, bits, status = run_gpu(c, b"x\ny\n-\n", fmt)
+        got = [int(x) & 0xFFFFFFFFFFFFFFFF for x in out.cpu().tolist()]
+        assert tuple(got) == _expected_minmax([], [], fmt)
+        c.set_reduce(None)
     finally:
         c.close()
