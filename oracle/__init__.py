@@ -24,6 +24,7 @@ from .exact import (
     round_decimal,
 )
 from .grammar import (
+    FLAG_HEX,
     FLAG_INFNAN,
     FLAG_JSON,
     FLAG_REJECT_PLUS,
@@ -38,6 +39,7 @@ __all__ = [
     "BINARY16",
     "BINARY32",
     "BINARY64",
+    "FLAG_HEX",
     "FLAG_INFNAN",
     "FLAG_JSON",
     "FLAG_REJECT_PLUS",

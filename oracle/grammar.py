@@ -34,6 +34,14 @@ FLAG_JSON = 2
 # inf, infinity and nan in any letter case, with an optional sign: +-infinity
 # and the quiet NaN (the sign bit follows the sign).
 FLAG_INFNAN = 4
+# Hexadecimal floating-point tokens (Appendix C): 0x, hexadecimal digits with
+# an optional point, an optional binary exponent p[+-]digits; the value is
+# the hexadecimal significand times 16^-(fraction nibbles) times 2^exponent.
+FLAG_HEX = 8
+
+_HEX_RE = re.compile(
+    rb"([+-]?)0[xX](?:([0-9a-fA-F]+)(?:\.([0-9a-fA-F]*))?|\.([0-9a-fA-F]+))(?:[pP]([+-]?[0-9]+))?"
+)
 
 _JSON_RE = re.compile(rb"-?(?:0|[1-9][0-9]*)(?:\.[0-9]+)?(?:[eE][+-]?[0-9]+)?")
 _INFNAN_RE = re.compile(rb"([+-]?)(?:inf|infinity|nan)", re.IGNORECASE)
@@ -59,10 +67,47 @@ def decompose(tok: bytes, flags: int = 0):
     return sign == b"-", D, E
 
 
+def decompose_hex(tok: bytes, flags: int = 0):
+    """(neg, M, B) with value (-1)^neg * M * 2^B for a hexadecimal token, or
+    None."""
+    m = _HEX_RE.fullmatch(tok)
+    if m is None:
+        return None
+    sign, int_digits, frac_digits, only_frac, exp = m.groups()
+    if sign == b"+" and (flags & (FLAG_REJECT_PLUS | FLAG_JSON)):
+        return None
+    if only_frac is not None:
+        int_digits, frac_digits = b"", only_frac
+    if frac_digits is None:
+        frac_digits = b""
+    M = int(int_digits + frac_digits, 16)
+    B = (int(exp) if exp is not None else 0) - 4 * len(frac_digits)
+    return sign == b"-", M, B
+
+
+def round_binary(neg: bool, M: int, B: int, fmt):
+    """Round (-1)^neg * M * 2^B to ``fmt`` (through the decimal rounding, as
+    M * 2^B = M * 5^-B * 10^B exactly)."""
+    if M == 0:
+        return round_decimal(neg, 0, 0, fmt)
+    top = M.bit_length() + B  # value in [2^(top-1), 2^top)
+    if top - 1 > fmt.emax + 1:  # at least 2^(emax+2): infinity
+        return round_decimal(neg, 1, 400, fmt)
+    if top < fmt.emin - fmt.p - 1:  # below 2^(emin-p-1): zero
+        return round_decimal(neg, 1, -400, fmt)
+    if B >= 0:
+        return round_decimal(neg, M << B, 0, fmt)
+    return round_decimal(neg, M * 5 ** (-B), B, fmt)
+
+
 def parse_token(tok: bytes, fmt=BINARY64, flags: int = 0):
     """(bits, status) for one token."""
     if isinstance(fmt, str):
         fmt = FORMATS[fmt]
+    if flags & FLAG_HEX:
+        parts = decompose_hex(tok, flags)
+        if parts is not None:
+            return round_binary(*parts, fmt)
     if flags & FLAG_INFNAN:
         m = _INFNAN_RE.fullmatch(tok)
         if m is not None and not (m.group(1) == b"+" and flags & (FLAG_REJECT_PLUS | FLAG_JSON)):
@@ -105,10 +150,12 @@ def parse_buffer(buf: bytes, fmt="f64", delims: bytes = b"\n", flags: int = 0):
 __all__ = [
     "BINARY32",
     "BINARY64",
+    "FLAG_HEX",
     "FLAG_INFNAN",
     "FLAG_JSON",
     "FLAG_REJECT_PLUS",
     "decompose",
+    "decompose_hex",
     "parse_buffer",
     "parse_token",
     "split_tokens",

@@ -593,3 +593,72 @@ def test_infnan_acceptance_matches_float():
                 assert bool(bits >> 63) == tok.startswith("-"), tok
             else:
                 assert bits == want, tok
+
+
+# ---------------------------------------------------------------------------
+# hexadecimal floating-point tokens (Appendix C)
+# ---------------------------------------------------------------------------
+
+def test_hexfloat_golden(golden_dir):
+    n = 0
+    with open(os.path.join(golden_dir, "hexfloat.tsv")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            tok, st, bits, _ = line.rstrip("\n").split("\t")
+            assert parse_token(tok.encode(), BINARY64, 8) == (int(bits, 16), int(st)), tok
+            n += 1
+    assert n >= 20
+
+
+def _hex_tokens(rng, n):
+    toks = []
+    for _ in range(n):
+        k = int(rng.integers(0, 4))
+        if k == 0:  # a random double's own hex form
+            x = float(rng.standard_normal() * 10.0 ** rng.integers(-300, 300))
+            toks.append(x.hex())
+        elif k == 1:  # long significands around the subnormal range and beyond
+            digits = "".join(rng.choice(list("0123456789abcdef"), int(rng.integers(1, 40))))
+            toks.append("0x%s.%sp%d" % (digits[:3] or "0", digits[3:], int(rng.integers(-1200, 1100))))
+        elif k == 2:  # exact ties: 53 bits and a trailing 1 bit
+            m = int(rng.integers(2 ** 52, 2 ** 53)) * 2 + 1
+            toks.append("0x%xp%d" % (m, int(rng.integers(-1130, 1000))))
+        else:
+            digits = "".join(rng.choice(list("0123456789ABCDEF"), int(rng.integers(1, 20))))
+            toks.append("%s0X.%sP%+d" % ("-" if rng.integers(0, 2) else "", digits,
+                                         int(rng.integers(-60, 60))))
+    return toks
+
+
+def test_hexfloat_matches_fromhex():
+    """float.fromhex rounds to nearest, ties to even (binary64)."""
+    rng = np.random.default_rng(8)
+    for tok in _hex_tokens(rng, 20_000):
+        mant = tok.lower().lstrip("+-")[2:].split("p")[0].replace(".", "")
+        nonzero = int(mant or "0", 16) != 0
+        try:
+            v = float.fromhex(tok)
+            want = struct.unpack("<Q", struct.pack("<d", v))[0]
+            want_st = 2 if math.isinf(v) or (v == 0 and nonzero) else 0
+        except OverflowError:
+            want = 0x7FF0000000000000 | (1 << 63 if tok.startswith("-") else 0)
+            want_st = 2
+        bits, st = parse_token(tok.encode(), BINARY64, 8)
+        assert bits == want, (tok, hex(bits), hex(want))
+        assert st == want_st, (tok, st, want_st)
+
+
+def test_hexfloat_narrow_formats_match_numpy():
+    """Hex values exact in binary64, rounded once to binary32 / binary16."""
+    rng = np.random.default_rng(9)
+    for _ in range(20_000):
+        m = int(rng.integers(1, 2 ** 40))
+        e = int(rng.integers(-180, 140))
+        tok = "0x%xp%d" % (m, e)
+        v = float.fromhex(tok)  # exact: 40 bits, in range
+        with np.errstate(over="ignore", under="ignore"):
+            w32 = int(np.array([v]).astype(np.float32).view(np.uint32)[0])
+            w16 = int(np.array([v]).astype(np.float16).view(np.uint16)[0])
+        assert parse_token(tok.encode(), BINARY32, 8)[0] == w32, tok
+        assert parse_token(tok.encode(), BINARY16, 8)[0] == w16, tok
