@@ -450,3 +450,36 @@ def geojson_document(seed: int, nfeat: int, npts: int) -> bytes:
 
 # Delimiters that make the numbers of such a document its tokens.
 JSON_DELIMS = b'[]{},:" \n'
+
+
+def hex_tokens(rng, n: int):
+    """Hexadecimal floating-point tokens: random doubles in their own hex
+    form, long significands across the whole exponent range, exact ties of
+    53-, 24-, 11- and 8-bit significands (and their neighbours), upper-case
+    and fraction-only forms."""
+    toks = []
+    hexd = list("0123456789abcdef")
+    for _ in range(n):
+        k = int(rng.integers(0, 5))
+        if k == 0:
+            x = float(rng.standard_normal() * 10.0 ** rng.integers(-300, 300))
+            toks.append(x.hex())
+        elif k == 1:
+            digits = "".join(rng.choice(hexd, int(rng.integers(1, 40))))
+            toks.append("0x%s.%sp%d" % (digits[:3] or "0", digits[3:],
+                                       int(rng.integers(-1200, 1100))))
+        elif k == 2:
+            p = int(rng.choice([53, 24, 11, 8]))
+            m = int(rng.integers(2 ** (p - 1), 2 ** p)) * 2 + 1 + int(rng.integers(-1, 2))
+            m <<= int(rng.integers(0, 12))
+            lo, hi = {53: (-1130, 1000), 24: (-180, 110), 11: (-40, 10), 8: (-150, 110)}[p]
+            toks.append("%s0x%xp%d" % ("-" if rng.integers(0, 2) else "", m,
+                                       int(rng.integers(lo, hi))))
+        elif k == 3:
+            digits = "".join(rng.choice(list("0123456789ABCDEF"), int(rng.integers(1, 20))))
+            toks.append("%s0X.%sP%+d" % ("-" if rng.integers(0, 2) else "", digits,
+                                         int(rng.integers(-60, 60))))
+        else:
+            toks.append("0x%x.%xp%d" % (int(rng.integers(0, 2 ** 16)), int(rng.integers(0, 2 ** 20)),
+                                        int(rng.integers(-30, 30))))
+    return toks

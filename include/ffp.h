@@ -73,6 +73,11 @@ enum ffp_error {
  * +-infinity (status FFP_OK) and the canonical quiet NaN with the token's
  * sign (status FFP_OK). */
 #define FFP_INFNAN 4u
+/* Also accept hexadecimal floating-point tokens (Appendix C):
+ * [+-]? 0[xX] ( H+ ('.' H*)? | '.' H+ ) ( [pP] [+-]? D+ )?   H = [0-9a-fA-F],
+ * value = hexadecimal significand * 16^-(nibbles after the point) * 2^exponent,
+ * rounded to nearest, ties to even (exact; no table, no fallback). */
+#define FFP_HEX 8u
 
 /* ---------------------------------------------------------------------------
  * Options.  delim_set is a 256-bit set of delimiter bytes: byte c is a

@@ -402,7 +402,7 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   } else {
     o.delim_set['\n' >> 6] |= 1ull << ('\n' & 63);
   }
-  if (o.flags & ~(FFP_REJECT_PLUS | FFP_JSON | FFP_INFNAN)) return FFP_E_ARG;
+  if (o.flags & ~(FFP_REJECT_PLUS | FFP_JSON | FFP_INFNAN | FFP_HEX)) return FFP_E_ARG;
   int members = 0, first = -1;
   for (int c = 0; c < 256; ++c) {
     if ((o.delim_set[c >> 6] >> (c & 63)) & 1) {

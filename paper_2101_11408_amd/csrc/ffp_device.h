@@ -249,14 +249,23 @@ enum LexKind : uint32_t {
   kLexExact = 0,
   kLexTruncated = 1,
   kLexInvalid = 2,
-  kLexInf = 3,  // inf / infinity (flag FFP_INFNAN)
-  kLexNaN = 4   // nan (flag FFP_INFNAN)
+  kLexInf = 3,        // inf / infinity (flag FFP_INFNAN)
+  kLexNaN = 4,        // nan (flag FFP_INFNAN)
+  kLexHex = 5,        // hexadecimal: value w * 2^q exactly (flag FFP_HEX)
+  kLexHexSticky = 6   // hexadecimal: w * 2^q plus nonzero nibbles below it
 };
 
 // Grammar flags (public values of include/ffp.h).
 constexpr uint32_t kFlagRejectPlus = 1;
 constexpr uint32_t kFlagJson = 2;    // JSON number grammar
 constexpr uint32_t kFlagInfNan = 4;  // inf, infinity, nan in any case
+constexpr uint32_t kFlagHex = 8;     // hexadecimal floating-point tokens
+
+FFP_HD int hex_value(uint32_t c) {
+  if (c - '0' < 10u) return (int)(c - '0');
+  const uint32_t l = c | 0x20u;
+  return (l - 'a' < 6u) ? (int)(l - 'a' + 10) : -1;
+}
 
 // Case-insensitive match of the letters of `word` at pos; returns the
 // position after them, or 0 if they do not match.
@@ -278,7 +287,62 @@ struct Lexed {
 // counts cannot bring a saturated exponent back into range.
 constexpr int64_t kExpCap = 1ll << 56;
 
+// Hexadecimal token after its sign (Appendix C): 0x, hexadecimal digits with
+// an optional point, an optional binary exponent.  The first 16 significant
+// nibbles go to w, the others only set the sticky kind; q = exponent -
+// 4 * (fraction nibbles - dropped nibbles).
 template <class Src>
+FFP_HD Lexed lex_hex(const Src& src, uint64_t pos, Lexed r) {
+  pos += 2;
+  uint32_t c = src(pos);
+  uint64_t w = 0;
+  int nsig = 0;
+  int64_t ndig = 0, nfrac = 0, dropped = 0;
+  bool sticky = false, point = false;
+  for (;; c = src(++pos)) {
+    const int h = hex_value(c);
+    if (h < 0) {
+      if (c == '.' && !point) {
+        point = true;
+        continue;
+      }
+      break;
+    }
+    ++ndig;
+    nfrac += point;
+    if (nsig < 16) {
+      if (nsig || h) {
+        w = (w << 4) | (uint64_t)h;
+        ++nsig;
+      }
+    } else {
+      ++dropped;
+      sticky |= h != 0;
+    }
+  }
+  int64_t e = 0;
+  bool ok = ndig > 0;
+  if ((c | 0x20u) == 'p') {
+    c = src(++pos);
+    const bool eneg = c == '-';
+    if (c == '-' || c == '+') c = src(++pos);
+    ok = ok && is_digit(c);
+    for (; is_digit(c); c = src(++pos))
+      if (e < kExpCap) e = e * 10 + (c - '0');
+    if (eneg) e = -e;
+  }
+  ok = ok && src.is_end(c);
+  int64_t q = e - 4 * (nfrac - dropped);
+  q = q < -100000 ? -100000 : (q > 100000 ? 100000 : q);
+  r.w = w;
+  r.q = (int32_t)q;
+  if (r.kind != kLexInvalid) r.kind = !ok ? kLexInvalid : (sticky ? kLexHexSticky : kLexHex);
+  return r;
+}
+
+// kHex: hexadecimal tokens are recognised (flag FFP_HEX); kernels built
+// without them keep their registers for the decimal path.
+template <bool kHex = true, class Src>
 FFP_HD Lexed lex_token(const Src& src, uint64_t pos, uint32_t flags) {
   Lexed r;
   r.w = 0;
@@ -306,6 +370,8 @@ FFP_HD Lexed lex_token(const Src& src, uint64_t pos, uint32_t flags) {
     if (r.kind != kLexInvalid) r.kind = kind;
     return r;
   }
+  if (kHex && (flags & kFlagHex) && c == '0' && (src(pos + 1) | 0x20u) == 'x')
+    return lex_hex(src, pos, r);
   const uint32_t first_digit = c;  // for the JSON leading-zero rule
   uint32_t nsig = 0;
   int64_t ndig = 0, nfrac = 0, dropped = 0;
@@ -392,6 +458,45 @@ struct GlobalSrc {
 // Decision for one lexed token: Algorithm 1 on w (and on w+1 when digits
 // beyond the 19th were dropped and not all zero, Section 11).
 // ---------------------------------------------------------------------------
+// Nearest value of w * 2^q (plus something below its last bit when
+// `sticky`), ties to even: the exact rounding of a hexadecimal token.
+FFP_HD uint64_t hex_round(uint64_t w, int q, bool sticky, const FormatRT& F, uint32_t& st) {
+  st = kStOk;
+  if (w == 0) return 0;
+  const int l = __builtin_clzll(w);
+  w <<= l;
+  int64_t e = (int64_t)q + 63 - l;  // exponent of the leading bit
+  if (e > F.max_exp) {
+    st = kStRange;
+    return F.inf;
+  }
+  const int64_t unit = (e < F.min_exp ? F.min_exp : e) - F.mant;  // exponent of the last kept bit
+  const int64_t s = 63 + unit - e;  // bits of w below it, >= 63 - mant
+  uint64_t m = 0;
+  bool up = false;
+  if (s == 64) {  // w is at least half a unit (w >= 2^63); exactly half is a tie to 0
+    up = w > (1ull << 63) || sticky;
+  } else if (s < 64) {
+    m = w >> s;
+    const uint64_t rem = w & ((1ull << s) - 1), half = 1ull << (s - 1);
+    up = rem > half || (rem == half && (sticky || (m & 1)));
+  }
+  if (up) ++m;
+  if (e < F.min_exp) {  // subnormal; m == 2^mant encodes the smallest normal
+    if (m == 0) st = kStRange;
+    return m;
+  }
+  if (m == (2ull << F.mant)) {
+    m >>= 1;
+    ++e;
+  }
+  if (e > F.max_exp) {
+    st = kStRange;
+    return F.inf;
+  }
+  return ((uint64_t)(e + F.bias) << F.mant) | (m & ((1ull << F.mant) - 1));
+}
+
 struct DecisionRT {
   uint64_t bits;      // sign applied (sign_bit = 1 << (format width - 1))
   uint32_t status;    // kStOk / kStInvalid / kStRange
@@ -400,6 +505,7 @@ struct DecisionRT {
 };
 
 // qnan / sign: the format's canonical quiet NaN and sign bit.
+template <bool kHex = true>
 FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* table,
                                   const FormatRT& fmt, uint64_t qnan, uint64_t sign) {
   DecisionRT d;
@@ -414,6 +520,11 @@ FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* tabl
     d.bits = (L.kind == kLexInf ? fmt.inf : qnan) | (L.neg ? sign : 0);
     d.status = kStOk;
     d.path = kCntEarly;
+    return d;
+  }
+  if (kHex && (L.kind == kLexHex || L.kind == kLexHexSticky)) {
+    d.bits = hex_round(L.w, L.q, L.kind == kLexHexSticky, fmt, d.status) | (L.neg ? sign : 0);
+    d.path = kCntOne;
     return d;
   }
   if (L.w == 0) {
@@ -449,10 +560,10 @@ struct Decision {
   bool fallback;            // undecided: needs the exact fallback
 };
 
-template <class F>
+template <class F, bool kHex = true>
 FFP_HD Decision<F> decide_lexed(const Lexed& L, const unsigned long long* table) {
   constexpr FormatRT fmt = format_of<F>();
-  const DecisionRT r = decide_lexed_rt(L, table, fmt, F::kQNaN, F::kSign);
+  const DecisionRT r = decide_lexed_rt<kHex>(L, table, fmt, F::kQNaN, F::kSign);
   Decision<F> d;
   d.bits = (typename F::bits_t)r.bits;
   d.status = r.status;

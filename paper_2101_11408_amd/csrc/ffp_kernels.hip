@@ -538,12 +538,14 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
   r.neg = c0 == '-';
   bool valid = end == L && nint + nfrac > 0 && (!has_e || nexp > 0) &&
                !(c0 == '+' && (flags & (kFlagRejectPlus | kFlagJson)));
-  if (flags & (kFlagJson | kFlagInfNan)) {  // the same for every lane
+  if (flags & (kFlagJson | kFlagInfNan | kFlagHex)) {  // the same for every lane
     const uint32_t ca = tb[s + a];  // first byte after the sign
     if (flags & kFlagJson)  // no ".5", no "1.", no leading zeros
       valid = valid && nint > 0 && (!dot || nfrac > 0) && !(nint > 1 && ca == '0');
     if (!valid && (flags & kFlagInfNan) && ((ca | 0x20u) == 'i' || (ca | 0x20u) == 'n'))
       return r;  // inf / nan: the byte-by-byte lexer
+    if ((flags & kFlagHex) && ca == '0' && (tb[s + a + 1] | 0x20u) == 'x')
+      return r;  // hexadecimal: the byte-by-byte lexer
   }
   if (!valid) {
     r.code = kFastInvalid;
@@ -562,12 +564,12 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
 
 // Algorithm 1 (and w+1 for long significands) on a lexed token, the queue
 // append for undecided tokens, and the stores.  Returns the path counter.
-template <class F>
+template <class F, bool kHex>
 __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, const JobDesc& job,
                                             uint64_t idx, const unsigned long long* table,
                                             const ParseParams& P, uint64_t& bits_out,
                                             uint32_t& status_out) {
-  Decision<F> d = decide_lexed<F>(L, table);
+  Decision<F> d = decide_lexed<F, kHex>(L, table);
   bits_out = d.bits;
   status_out = d.fallback ? kPending : d.status;
   uint8_t st = (uint8_t)d.status;
@@ -591,8 +593,9 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
 
 // Four workgroups per CU (the LDS allows four): registers are kept within
 // 128.  kReduce: the call also keeps the minimum, maximum and count of the
-// values (a separate instance, so that the plain parse pays nothing for it).
-template <int K, bool kSingle, bool kReduce>
+// values; kHex: hexadecimal tokens are accepted (flag FFP_HEX).  Separate
+// instances, so that the plain parse pays nothing for either.
+template <int K, bool kSingle, bool kReduce, bool kHex>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_parse(ParseParams P) {
   using S = TileSmem<K>;
   using Packed = typename S::Packed;
@@ -738,7 +741,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           }
           Lexed L;
           if (fl.code == kFastSlow) {
-            L = global ? lex_token(gsrc, pos, P.flags) : lex_token(lsrc, vpos, P.flags);
+            L = global ? lex_token<kHex>(gsrc, pos, P.flags) : lex_token<kHex>(lsrc, vpos, P.flags);
           } else {
             L.w = fl.w;
             L.q = fl.q;
@@ -747,10 +750,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           }
           int path;
           switch (job.dtype) {
-            case kF64: path = finish_token<F64>(L, pos, job, idx, table, P, vbits, vstatus); break;
-            case kF32: path = finish_token<F32>(L, pos, job, idx, table, P, vbits, vstatus); break;
-            case kF16: path = finish_token<F16>(L, pos, job, idx, table, P, vbits, vstatus); break;
-            default: path = finish_token<BF16>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            case kF64: path = finish_token<F64, kHex>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            case kF32: path = finish_token<F32, kHex>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            case kF16: path = finish_token<F16, kHex>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            default: path = finish_token<BF16, kHex>(L, pos, job, idx, table, P, vbits, vstatus); break;
           }
           if (P.count_paths) {
             c_tok += 1;
@@ -867,9 +870,10 @@ int parse_tile_bytes(int k) { return kThreads * kChunk * k; }
 
 template <int K>
 static hipError_t occ_k(bool single, int* blocks) {
-  return single
-             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_parse<K, true, false>, kThreads, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_parse<K, false, false>, kThreads, 0);
+  return single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      blocks, k_parse<K, true, false, false>, kThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      blocks, k_parse<K, false, false, false>, kThreads, 0);
 }
 
 hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu) {
@@ -911,10 +915,18 @@ hipError_t launch_scan(const ScanParams& P, hipStream_t s) {
 
 template <int K, bool kSingle>
 static hipError_t launch_parse_k(const ParseParams& P, int grid, hipStream_t s) {
-  if (P.reduce_out)
-    hipLaunchKernelGGL((k_parse<K, kSingle, true>), dim3(grid), dim3(kThreads), 0, s, P);
-  else
-    hipLaunchKernelGGL((k_parse<K, kSingle, false>), dim3(grid), dim3(kThreads), 0, s, P);
+  const bool hex = (P.flags & kFlagHex) != 0;
+  if (P.reduce_out) {
+    if (hex)
+      hipLaunchKernelGGL((k_parse<K, kSingle, true, true>), dim3(grid), dim3(kThreads), 0, s, P);
+    else
+      hipLaunchKernelGGL((k_parse<K, kSingle, true, false>), dim3(grid), dim3(kThreads), 0, s, P);
+  } else {
+    if (hex)
+      hipLaunchKernelGGL((k_parse<K, kSingle, false, true>), dim3(grid), dim3(kThreads), 0, s, P);
+    else
+      hipLaunchKernelGGL((k_parse<K, kSingle, false, false>), dim3(grid), dim3(kThreads), 0, s, P);
+  }
   return hipGetLastError();
 }
 

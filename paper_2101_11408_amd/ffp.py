@@ -30,6 +30,7 @@ FFP_E_INTERNAL = -8
 FFP_REJECT_PLUS = 1
 FFP_JSON = 2
 FFP_INFNAN = 4
+FFP_HEX = 8
 
 DTYPE_F64 = 0
 DTYPE_F32 = 1

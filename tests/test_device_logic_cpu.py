@@ -164,3 +164,24 @@ def test_json_and_infnan_flags(host_check, flags):
     buf = W.join_tokens(_flag_tokens(49))
     for fmt in ("f64", "f32"):
         check(host_check, buf, fmt, "flags-%d" % flags, flags=flags)
+
+
+def _hex_buffer(seed):
+    rng = np.random.default_rng(seed)
+    toks = W.hex_tokens(rng, 8000)
+    with open(os.path.join(ROOT, "tests", "golden", "hexfloat.tsv")) as f:
+        toks += [ln.split("\t")[0] for ln in f if ln.strip() and not ln.startswith("#")]
+    # decimal tokens and near-misses of the hexadecimal form in the same text
+    toks += W.mixed_tokens(rng, 2000) + ["0", "0x", "x1", "00x1", "0x1p+", "0x1.p-", "+0x1",
+                                         "0x1e", "0xg", "0x.", "0x1.2.3", "0x1p1p1"]
+    rng.shuffle(toks)
+    return W.join_tokens(toks)
+
+
+@pytest.mark.parametrize("flags", [8, 12, 9, 10])
+def test_hex_flag(host_check, flags):
+    """Hexadecimal tokens (Appendix C) through the byte-by-byte lexer and
+    their rounding, in every format."""
+    buf = _hex_buffer(50)
+    for fmt in ("f64", "f32", "f16", "bf16"):
+        check(host_check, buf, fmt, "hex-%d" % flags, flags=flags)

@@ -69,13 +69,13 @@ def build_jobs(ffpmod, pool, sizes, f32_mask, seed, dtypes=None):
     return table, values, statuses, spans
 
 
-def check_jobs(pool, table, values, statuses, spans, label):
+def check_jobs(pool, table, values, statuses, spans, label, flags=0):
     host, _ = pool
     res = table.download()
     for i, ((st, ln), (count, err)) in enumerate(zip(spans, res)):
         buf = host[st:st + ln]
         fmt = FMT_OF[values[i].dtype]
-        wb, ws = parse_buffer(buf, fmt)
+        wb, ws = parse_buffer(buf, fmt, flags=flags)
         assert count == len(wb), (label, i, count, len(wb))
         assert err == 0, (label, i, err)
         n = len(wb)
@@ -219,3 +219,26 @@ def test_batch_all_output_types(ctx, ffpmod, pool):
     ctx.parse_batch(table.dev, table.n, table.total_bytes)
     torch.cuda.synchronize()
     check_jobs(pool, table, values, statuses, spans, "four-types")
+
+
+def test_batch_hex_tokens(ffpmod):
+    """Hexadecimal and decimal tokens (flag FFP_HEX) in jobs of the four
+    output types."""
+    rng = np.random.default_rng(17)
+    toks = W.hex_tokens(rng, 40_000) + W.mixed_tokens(rng, 40_000) + W.hard_tokens(rng, 1000)
+    rng.shuffle(toks)
+    host = W.join_tokens(toks)
+    hp = (host, torch.frombuffer(bytearray(host), dtype=torch.uint8).to("cuda:0"))
+    n = 120
+    sizes = W.lognormal_sizes(rng, n, 8000, 1.5, 1, 100_000)
+    kinds = [torch.float64, torch.float32, torch.float16, torch.bfloat16]
+    dtypes = [kinds[int(k)] for k in rng.integers(0, 4, n)]
+    c = ffpmod.Context(0, flags=ffpmod.FFP_HEX)
+    try:
+        table, values, statuses, spans = build_jobs(ffpmod, hp, sizes, None, 18, dtypes)
+        c.parse_batch(table.dev, table.n, table.total_bytes)
+        torch.cuda.synchronize()
+        assert c.last_device_error() == 0
+        check_jobs(hp, table, values, statuses, spans, "hex", flags=8)
+    finally:
+        c.close()

@@ -406,6 +406,56 @@ def test_json_document_numbers(ffpmod):
         c.close()
 
 
+@pytest.fixture(scope="module")
+def hex_case():
+    rng = np.random.default_rng(65)
+    toks = W.hex_tokens(rng, 30_000) + W.mixed_tokens(rng, 30_000) + W.hard_tokens(rng, 500)
+    toks += ["0x", "0x.p1", "0x1p", "+0x1", "-0x0p0", "0X1P-1074", "0x1.fffffffffffff8p1023",
+             "inf", "-nan", "0x1.8e3", "0x1p99999999999999999999"]
+    rng.shuffle(toks)
+    return toks, W.join_tokens(toks)
+
+
+@pytest.mark.parametrize("flags", [8, 12])
+@pytest.mark.parametrize("tile_k", [1, 2, 4])
+def test_hex_tokens(ffpmod, hex_case, flags, tile_k):
+    """Hexadecimal tokens (Appendix C) beside decimal ones, every tile size,
+    every output type."""
+    toks, buf = hex_case
+    c = ffpmod.Context(0, flags=flags)
+    try:
+        c.set_tuning(tile_k, 0, 16)
+        for fmt in ("f64", "f32", "f16", "bf16"):
+            _log("case hex flags", flags, "tile_k", tile_k, fmt)
+            rc, n, bits, status = run_gpu(c, buf, fmt, offset=3)
+            wb, ws = parse_buffer(buf, fmt, flags=flags)
+            assert rc == len(wb) and n == len(wb)
+            bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                 (status[:n] != np.array(ws, dtype=np.uint8)))
+            assert bad.size == 0, (flags, tile_k, fmt, [toks[i] for i in bad[:5]])
+    finally:
+        c.close()
+
+
+def test_hex_tokens_with_reduction(ffpmod, hex_case):
+    toks, buf = hex_case
+    c = ffpmod.Context(0, flags=ffpmod.FFP_HEX | ffpmod.FFP_INFNAN)
+    out = torch.full((3,), -1, dtype=torch.int64, device="cuda:0")
+    try:
+        c.set_reduce(out)
+        for fmt in ("f64", "f32"):
+            _log("case hex reduce", fmt)
+            rc, n, bits, status = run_gpu(c, buf, fmt)
+            wb, ws = parse_buffer(buf, fmt, flags=12)
+            assert np.array_equal(bits[:n], np.array(wb, dtype=NP_DT[fmt]))
+            got = [int(x) & 0xFFFFFFFFFFFFFFFF for x in out.cpu().tolist()]
+            want = _expected_minmax(wb, ws, fmt)
+            assert tuple(got) == want, (fmt, [hex(x) for x in got], [hex(x) for x in want])
+        c.set_reduce(None)
+    finally:
+        c.close()
+
+
 # ---------------------------------------------------------------------------
 # in-kernel reduction
 # ---------------------------------------------------------------------------

@@ -611,30 +611,10 @@ def test_hexfloat_golden(golden_dir):
     assert n >= 20
 
 
-def _hex_tokens(rng, n):
-    toks = []
-    for _ in range(n):
-        k = int(rng.integers(0, 4))
-        if k == 0:  # a random double's own hex form
-            x = float(rng.standard_normal() * 10.0 ** rng.integers(-300, 300))
-            toks.append(x.hex())
-        elif k == 1:  # long significands around the subnormal range and beyond
-            digits = "".join(rng.choice(list("0123456789abcdef"), int(rng.integers(1, 40))))
-            toks.append("0x%s.%sp%d" % (digits[:3] or "0", digits[3:], int(rng.integers(-1200, 1100))))
-        elif k == 2:  # exact ties: 53 bits and a trailing 1 bit
-            m = int(rng.integers(2 ** 52, 2 ** 53)) * 2 + 1
-            toks.append("0x%xp%d" % (m, int(rng.integers(-1130, 1000))))
-        else:
-            digits = "".join(rng.choice(list("0123456789ABCDEF"), int(rng.integers(1, 20))))
-            toks.append("%s0X.%sP%+d" % ("-" if rng.integers(0, 2) else "", digits,
-                                         int(rng.integers(-60, 60))))
-    return toks
-
-
 def test_hexfloat_matches_fromhex():
     """float.fromhex rounds to nearest, ties to even (binary64)."""
     rng = np.random.default_rng(8)
-    for tok in _hex_tokens(rng, 20_000):
+    for tok in W.hex_tokens(rng, 20_000):
         mant = tok.lower().lstrip("+-")[2:].split("p")[0].replace(".", "")
         nonzero = int(mant or "0", 16) != 0
         try:
