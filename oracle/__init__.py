@@ -20,6 +20,11 @@ from .exact import (
     STATUS_INVALID,
     STATUS_OK,
     STATUS_OUT_OF_RANGE,
+    ROUND_DOWN,
+    ROUND_NEAREST,
+    ROUND_TOWARD_ZERO,
+    ROUND_UP,
+    ROUNDING_MODES,
     Format,
     round_decimal,
 )
@@ -28,9 +33,14 @@ from .grammar import (
     FLAG_INFNAN,
     FLAG_JSON,
     FLAG_REJECT_PLUS,
+    FLAG_ROUND_DOWN,
+    FLAG_ROUND_MASK,
+    FLAG_ROUND_TOWARD_ZERO,
+    FLAG_ROUND_UP,
     decompose,
     parse_buffer,
     parse_token,
+    rounding_mode,
     split_tokens,
 )
 
@@ -43,6 +53,16 @@ __all__ = [
     "FLAG_INFNAN",
     "FLAG_JSON",
     "FLAG_REJECT_PLUS",
+    "FLAG_ROUND_DOWN",
+    "FLAG_ROUND_MASK",
+    "FLAG_ROUND_TOWARD_ZERO",
+    "FLAG_ROUND_UP",
+    "ROUND_DOWN",
+    "ROUND_NEAREST",
+    "ROUND_TOWARD_ZERO",
+    "ROUND_UP",
+    "ROUNDING_MODES",
+    "rounding_mode",
     "FORMATS",
     "Format",
     "STATUS_INVALID",

@@ -41,6 +41,32 @@ STATUS_OK = 0
 STATUS_INVALID = 1
 STATUS_OUT_OF_RANGE = 2
 
+# Rounding-direction attributes of IEEE 754.  The paper works with
+# round-to-nearest, ties to even, and notes (the footnote of Section 6) that
+# the approach extends to the other modes; these are the three directed
+# ones.
+ROUND_NEAREST = "nearest"
+ROUND_TOWARD_ZERO = "zero"
+ROUND_UP = "up"        # toward +infinity
+ROUND_DOWN = "down"    # toward -infinity
+ROUNDING_MODES = (ROUND_NEAREST, ROUND_TOWARD_ZERO, ROUND_UP, ROUND_DOWN)
+
+
+def _away_from_zero(mode: str, neg: bool) -> bool:
+    """For a directed mode: does the magnitude round up (away from zero)?
+
+    Toward zero truncates the magnitude for either sign; toward +infinity
+    raises the magnitude of positive values and truncates negative ones;
+    toward -infinity the reverse.
+    """
+    if mode == ROUND_TOWARD_ZERO:
+        return False
+    if mode == ROUND_UP:
+        return not neg
+    if mode == ROUND_DOWN:
+        return neg
+    raise ValueError("not a directed rounding mode: %r" % (mode,))
+
 
 @dataclass(frozen=True)
 class Format:
@@ -133,24 +159,39 @@ def _decades(fmt: Format):
     return _DECADE_CACHE[key]
 
 
-def round_decimal(neg: bool, D: int, E: int, fmt: Format):
+def round_decimal(neg: bool, D: int, E: int, fmt: Format, mode: str = ROUND_NEAREST):
     """Round the exact value (-1)^neg * D * 10^E to ``fmt``.
 
     D >= 0 and E are arbitrary integers.  Returns (bits, status) where bits is
     the IEEE encoding as an unsigned integer.
+
+    ``mode`` is the rounding direction.  Directed modes follow IEEE 754: the
+    result is the representable value next to v on the mode's side (v itself
+    when it is representable); past the largest finite value a mode that
+    truncates the magnitude delivers that largest value and the others
+    infinity, both with status OUT_OF_RANGE (the IEEE overflow condition);
+    a nonzero value below the smallest subnormal becomes zero (status
+    OUT_OF_RANGE) or, rounding away from zero, the smallest subnormal.
     """
     sign = fmt.sign_bit if neg else 0
     if D == 0:
         # zero significand: signed zero, exact
         return sign, STATUS_OK
+    nearest = mode == ROUND_NEAREST
+    away = False if nearest else _away_from_zero(mode, neg)
+    largest = fmt.inf_bits - 1  # largest finite encoding
+    overflow = (sign | (fmt.inf_bits if nearest or away else largest), STATUS_OUT_OF_RANGE)
 
     # Magnitude pre-checks keep 10^|E| finite for absurd exponents.  The value
     # lies in [10^(n-1+E), 10^(n+E)).
     n = _decimal_digits(D)
     over_k, under_k = _decades(fmt)
     if n - 1 + E >= over_k:
-        return sign | fmt.inf_bits, STATUS_OUT_OF_RANGE
+        return overflow
     if n + E <= under_k:
+        # strictly between 0 and half the smallest subnormal
+        if away:
+            return sign | 1, STATUS_OK
         return sign, STATUS_OUT_OF_RANGE
 
     # v = N / Dn exactly, both positive integers.
@@ -178,9 +219,13 @@ def round_decimal(neg: bool, D: int, E: int, fmt: Format):
         num, den = N << (-k), Dn
     m, r = divmod(num, den)
 
-    # Round half to even.
-    twice_r = 2 * r
-    if twice_r > den or (twice_r == den and (m & 1)):
+    if nearest:
+        # Round half to even.
+        twice_r = 2 * r
+        if twice_r > den or (twice_r == den and (m & 1)):
+            m += 1
+    elif away and r != 0:
+        # Directed: the magnitude is m (exact or truncated) or the next one up.
         m += 1
 
     # Rounding may carry into a new binade.
@@ -199,6 +244,6 @@ def round_decimal(neg: bool, D: int, E: int, fmt: Format):
 
     unbiased = k + fmt.p - 1
     if unbiased > fmt.emax:
-        return sign | fmt.inf_bits, STATUS_OUT_OF_RANGE
+        return overflow
     field = unbiased + fmt.bias
     return sign | (field << (fmt.p - 1)) | (m - hidden), STATUS_OK

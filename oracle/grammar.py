@@ -19,7 +19,8 @@ library contract; the paper does not fix them.
 
 import re
 
-from .exact import BINARY32, BINARY64, FORMATS, STATUS_INVALID, STATUS_OK, round_decimal
+from .exact import (BINARY32, BINARY64, FORMATS, ROUND_DOWN, ROUND_NEAREST,
+                    ROUND_TOWARD_ZERO, ROUND_UP, STATUS_INVALID, STATUS_OK, round_decimal)
 
 # [+-]? ( D+ ('.' D*)? | '.' D+ ) ( [eE] [+-]? D+ )?   -- whole token
 _TOKEN_RE = re.compile(
@@ -38,6 +39,18 @@ FLAG_INFNAN = 4
 # an optional point, an optional binary exponent p[+-]digits; the value is
 # the hexadecimal significand times 16^-(fraction nibbles) times 2^exponent.
 FLAG_HEX = 8
+# Rounding direction, a two-bit field: 0 nearest (ties to even), then toward
+# zero, toward +infinity and toward -infinity.
+FLAG_ROUND_MASK = 0x30
+FLAG_ROUND_TOWARD_ZERO = 0x10
+FLAG_ROUND_UP = 0x20
+FLAG_ROUND_DOWN = 0x30
+_MODE_OF_FLAGS = {0: ROUND_NEAREST, FLAG_ROUND_TOWARD_ZERO: ROUND_TOWARD_ZERO,
+                  FLAG_ROUND_UP: ROUND_UP, FLAG_ROUND_DOWN: ROUND_DOWN}
+
+
+def rounding_mode(flags: int) -> str:
+    return _MODE_OF_FLAGS[flags & FLAG_ROUND_MASK]
 
 _HEX_RE = re.compile(
     rb"([+-]?)0[xX](?:([0-9a-fA-F]+)(?:\.([0-9a-fA-F]*))?|\.([0-9a-fA-F]+))(?:[pP]([+-]?[0-9]+))?"
@@ -85,29 +98,30 @@ def decompose_hex(tok: bytes, flags: int = 0):
     return sign == b"-", M, B
 
 
-def round_binary(neg: bool, M: int, B: int, fmt):
+def round_binary(neg: bool, M: int, B: int, fmt, mode: str = ROUND_NEAREST):
     """Round (-1)^neg * M * 2^B to ``fmt`` (through the decimal rounding, as
     M * 2^B = M * 5^-B * 10^B exactly)."""
     if M == 0:
-        return round_decimal(neg, 0, 0, fmt)
+        return round_decimal(neg, 0, 0, fmt, mode)
     top = M.bit_length() + B  # value in [2^(top-1), 2^top)
-    if top - 1 > fmt.emax + 1:  # at least 2^(emax+2): infinity
-        return round_decimal(neg, 1, 400, fmt)
-    if top < fmt.emin - fmt.p - 1:  # below 2^(emin-p-1): zero
-        return round_decimal(neg, 1, -400, fmt)
+    if top - 1 > fmt.emax + 1:  # at least 2^(emax+2): overflows in every mode
+        return round_decimal(neg, 1, 400, fmt, mode)
+    if top < fmt.emin - fmt.p - 1:  # below 2^(emin-p-1): as any such tiny value
+        return round_decimal(neg, 1, -400, fmt, mode)
     if B >= 0:
-        return round_decimal(neg, M << B, 0, fmt)
-    return round_decimal(neg, M * 5 ** (-B), B, fmt)
+        return round_decimal(neg, M << B, 0, fmt, mode)
+    return round_decimal(neg, M * 5 ** (-B), B, fmt, mode)
 
 
 def parse_token(tok: bytes, fmt=BINARY64, flags: int = 0):
     """(bits, status) for one token."""
     if isinstance(fmt, str):
         fmt = FORMATS[fmt]
+    mode = rounding_mode(flags)
     if flags & FLAG_HEX:
         parts = decompose_hex(tok, flags)
         if parts is not None:
-            return round_binary(*parts, fmt)
+            return round_binary(*parts, fmt, mode)
     if flags & FLAG_INFNAN:
         m = _INFNAN_RE.fullmatch(tok)
         if m is not None and not (m.group(1) == b"+" and flags & (FLAG_REJECT_PLUS | FLAG_JSON)):
@@ -118,7 +132,7 @@ def parse_token(tok: bytes, fmt=BINARY64, flags: int = 0):
     if parts is None:
         return fmt.qnan_bits, STATUS_INVALID
     neg, D, E = parts
-    return round_decimal(neg, D, E, fmt)
+    return round_decimal(neg, D, E, fmt, mode)
 
 
 def _delim_class(delims: bytes) -> bytes:
