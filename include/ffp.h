@@ -356,6 +356,7 @@ typedef struct ffp_server_stats {
     uint64_t arena_peak_bytes;  /* most arena bytes held at once */
     uint64_t scratch_bytes;     /* scratch of all streams */
     uint64_t max_batch_seen;    /* largest batch launched (requests) */
+    uint64_t cancelled;         /* released while still queued, never run */
 } ffp_server_stats;
 
 /* Current CLOCK_MONOTONIC time in nanoseconds. */
@@ -392,8 +393,10 @@ int ffp_server_wait(ffp_server* srv, uint64_t ticket, ffp_result* out);
 int ffp_server_copy_result(ffp_server* srv, uint64_t ticket, void* dst_values,
                            uint8_t* dst_status, uint64_t max_count, void* stream);
 
-/* Frees the request's memory.  A request that is not done yet is detached:
- * its memory is freed when it completes and its ticket is forgotten now. */
+/* Frees the request's memory.  A request still waiting in the queue is
+ * cancelled (never launched, counted in `cancelled`); one that is running is
+ * detached: its memory is freed when it completes.  Either way its ticket is
+ * forgotten now. */
 int ffp_server_release(ffp_server* srv, uint64_t ticket);
 
 int ffp_server_stats_read(ffp_server* srv, ffp_server_stats* out);

@@ -112,7 +112,8 @@ struct ffp_server {
   uint64_t next_ticket = 1;
   uint64_t epoch = 0;  // bumped by every event that can unblock admission
   bool stopping = false;
-  uint64_t n_submitted = 0, n_completed = 0, n_batches = 0, n_bytes = 0, max_batch_seen = 0;
+  uint64_t n_submitted = 0, n_completed = 0, n_batches = 0, n_bytes = 0, max_batch_seen = 0,
+           n_cancelled = 0;
   std::thread dispatcher;
 
   uint64_t need_of(uint64_t nbytes, bool on_device, int dtype, uint64_t* cap) const {
@@ -484,6 +485,7 @@ int ffp_server_release(ffp_server* srv, uint64_t ticket) {
     } else if (r->state == kQueued) {
       srv->queue.erase(std::find(srv->queue.begin(), srv->queue.end(), r));
       delete r;
+      ++srv->n_cancelled;
     } else {
       r->detached = true;  // freed when its batch completes
     }
@@ -505,6 +507,7 @@ int ffp_server_stats_read(ffp_server* srv, ffp_server_stats* out) {
   out->arena_peak_bytes = srv->arena.peak();
   out->scratch_bytes = srv->scratch_bytes;
   out->max_batch_seen = srv->max_batch_seen;
+  out->cancelled = srv->n_cancelled;
   return FFP_SUCCESS;
 }
 

@@ -89,7 +89,7 @@ class ffp_replay_result(ctypes.Structure):
 class ffp_server_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in
                 ("submitted", "completed", "batches", "bytes", "arena_bytes",
-                 "arena_peak_bytes", "scratch_bytes", "max_batch_seen")]
+                 "arena_peak_bytes", "scratch_bytes", "max_batch_seen", "cancelled")]
 
 
 _c = ctypes

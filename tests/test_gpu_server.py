@@ -216,6 +216,12 @@ def test_admission_by_budget(ctx, ffpmod, pool):
         b = submit(srv, pool, (n, n, False, 0))
         time.sleep(0.05)
         assert srv.poll(b) is None  # blocked by the held result of a
+        # queued behind b (admission is first come, first served): cancelled
+        d = submit(srv, pool, (0, 1000, False, 0))
+        time.sleep(0.01)
+        assert srv.poll(d) is None
+        srv.release(d)
+        assert srv.stats()["cancelled"] == 1
         srv.release(a)
         rb = srv.wait(b)
         assert rb.err == 0 and rb.t_launch_ns >= ra.t_done_ns
@@ -243,17 +249,22 @@ def test_inflight_limit_and_detach(ctx, ffpmod, pool):
         with pytest.raises(ffpmod.FFPError) as e:
             submit(srv, pool, (20_000, 10_000, True, 0))
         assert e.value.code == ffpmod.FFP_E_BUSY
-        srv.release(a)  # possibly still running: detached
+        srv.release(a)  # queued: cancelled; running: detached; done: freed
         c = submit(srv, pool, (20_000, 10_000, True, 0))
         assert srv.wait(b).err == 0 and srv.wait(c).err == 0
         srv.release(b)
         srv.release(c)
         with pytest.raises(ffpmod.FFPError):
             srv.poll(a)
+        # a either ran to completion or was cancelled before its launch
         deadline = time.time() + 10
-        while srv.stats()["completed"] < 3 and time.time() < deadline:
+        while time.time() < deadline:
+            st = srv.stats()
+            if st["completed"] + st["cancelled"] == 3:
+                break
             time.sleep(0.001)
-        assert srv.stats()["completed"] == 3
+        assert st["completed"] + st["cancelled"] == 3 and st["cancelled"] <= 1
+        assert st["arena_peak_bytes"] <= st["arena_bytes"]
     finally:
         srv.close()
 
