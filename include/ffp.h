@@ -76,8 +76,26 @@ enum ffp_error {
 /* Also accept hexadecimal floating-point tokens (Appendix C):
  * [+-]? 0[xX] ( H+ ('.' H*)? | '.' H+ ) ( [pP] [+-]? D+ )?   H = [0-9a-fA-F],
  * value = hexadecimal significand * 16^-(nibbles after the point) * 2^exponent,
- * rounded to nearest, ties to even (exact; no table, no fallback). */
+ * rounded in the context's rounding direction (exact; no table, no
+ * fallback). */
 #define FFP_HEX 8u
+/* Rounding direction, a two-bit field of the flags (IEEE 754 rounding-
+ * direction attributes; the paper rounds to nearest and notes that its
+ * method extends to the other modes, footnote of Section 6).  0 selects
+ * round to nearest, ties to even.  Under a directed mode the result is the
+ * representable value next to the token's exact value on the mode's side
+ * (the value itself when representable).  Overflow (the magnitude, rounded
+ * with an unbounded exponent, exceeds the largest finite value) gives the
+ * largest finite value when the mode truncates the magnitude (toward zero;
+ * toward -inf for positive values; toward +inf for negative ones) and
+ * infinity otherwise, status FFP_OUT_OF_RANGE either way.  A nonzero value
+ * below the smallest subnormal gives a signed zero (FFP_OUT_OF_RANGE) when
+ * truncating and the smallest subnormal (FFP_OK) otherwise. */
+#define FFP_ROUND_MASK 0x30u
+#define FFP_ROUND_NEAREST 0x00u
+#define FFP_ROUND_TOWARD_ZERO 0x10u
+#define FFP_ROUND_UP 0x20u   /* toward +infinity */
+#define FFP_ROUND_DOWN 0x30u /* toward -infinity */
 
 /* ---------------------------------------------------------------------------
  * Options.  delim_set is a 256-bit set of delimiter bytes: byte c is a

@@ -172,6 +172,7 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uin
   F.st = ctx->d_state;
   F.delim = ctx->delim;
   F.reduce_out = P.reduce_out;
+  F.flags = P.flags;
   if (ffp::launch_fallback(F, ctx->fb_grid, s) != hipSuccess) return FFP_E_HIP;
   return FFP_SUCCESS;
 }
@@ -402,7 +403,8 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   } else {
     o.delim_set['\n' >> 6] |= 1ull << ('\n' & 63);
   }
-  if (o.flags & ~(FFP_REJECT_PLUS | FFP_JSON | FFP_INFNAN | FFP_HEX)) return FFP_E_ARG;
+  if (o.flags & ~(FFP_REJECT_PLUS | FFP_JSON | FFP_INFNAN | FFP_HEX | FFP_ROUND_MASK))
+    return FFP_E_ARG;
   int members = 0, first = -1;
   for (int c = 0; c < 256; ++c) {
     if ((o.delim_set[c >> 6] >> (c & 63)) & 1) {

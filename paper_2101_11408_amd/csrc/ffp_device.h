@@ -224,6 +224,123 @@ FFP_HD typename F::bits_t alg1(uint64_t w, int q, uint64_t thi, uint64_t tlo, bo
 }
 
 // ---------------------------------------------------------------------------
+// Directed rounding.  The paper rounds to nearest, ties to even, and notes
+// that its approach extends to the other IEEE modes (footnote of Section 6).
+// Toward zero, toward +infinity and toward -infinity reduce, once the sign is
+// known, to two rules on the magnitude: truncate it, or raise it to the next
+// representable value when anything is lost.  Overflow (the IEEE condition:
+// the magnitude, rounded with an unbounded exponent, exceeds the largest
+// finite value) gives the largest finite value when truncating and infinity
+// otherwise; a nonzero value below the smallest subnormal gives zero when
+// truncating and the smallest subnormal otherwise.
+// ---------------------------------------------------------------------------
+enum RoundDir : uint32_t { kDirNearest = 0, kDirTruncate = 1, kDirAway = 2 };
+
+// Rounding-direction field of the flags (public values of include/ffp.h).
+constexpr uint32_t kFlagRoundMask = 0x30;
+constexpr uint32_t kRoundTowardZero = 0x10;
+constexpr uint32_t kRoundUp = 0x20;    // toward +infinity
+constexpr uint32_t kRoundDown = 0x30;  // toward -infinity
+
+FFP_HD uint32_t round_dir(uint32_t flags, uint32_t neg) {
+  const uint32_t m = flags & kFlagRoundMask;
+  if (m == 0) return kDirNearest;
+  if (m == kRoundTowardZero) return kDirTruncate;
+  return (m == kRoundUp) == (neg == 0) ? kDirAway : kDirTruncate;
+}
+
+// Directed rounding of w * 10^q (0 < w < 2^64) with the table entry of q
+// (Algorithm 1's product, both halves always).  The value is v = w * 10^q;
+// the 128-bit product z approximates it scaled to [2^126, 2^128).  Let Z be
+// the exact scaled value.  From the table's construction:
+//   q in [0, 27]   the entry is 5^q itself in the high word: z = Z exactly;
+//   q in [28, 55]  the entry is exact, the product is truncated: Z in [z, z+1);
+//   q > 55         the entry is truncated too: Z in [z, z+2);
+//   q < 0          the entry is a rounded-up reciprocal (or the truncation of
+//                  one): Z in (z-1, z+2).
+// v is exactly representable only if its odd part, a multiple of 5^q for
+// q > 0, has at most 53 bits, so never for q >= 23; for q < 0 only if 5^-q
+// divides w.  Let R be the bits of z below the last kept significand bit.
+// Outside the exact region the truncation is m (the kept bits) and v is
+// inexact unless R sits within the error of 0 or of the next unit (R = 0,
+// or R >= 2^r - 2): those products set `abort` (the exact fallback decides),
+// except that for q in [-27, -1] a w divisible by 5^-q gives the exact
+// value (w / 5^-q) * 2^q, rounded directly.
+FFP_HD uint64_t round_exact(uint64_t w, int q, bool sticky, const FormatRT& F, uint32_t dir,
+                            uint32_t& st);
+
+FFP_HD uint64_t alg1_dir_rt(uint64_t w, int q, uint64_t thi, uint64_t tlo, const FormatRT& F,
+                            bool away, bool& abort, uint32_t& st) {
+  abort = false;
+  st = kStOk;
+  const uint64_t largest = F.inf - 1;
+  if (q < kQMin) {  // strictly between 0 and half the smallest subnormal
+    if (!away) st = kStRange;
+    return away ? 1 : 0;
+  }
+  if (q > kQMax) {
+    st = kStRange;
+    return away ? F.inf : largest;
+  }
+  const uint64_t w0 = w;
+  const int l = __builtin_clzll(w);
+  w <<= l;
+  uint64_t zh, zl, ph, pl;
+  mul_64x64(w, thi, zh, zl);
+  mul_64x64(w, tlo, ph, pl);
+  zl += ph;
+  zh += (zl < ph);
+  const int u = (int)(zh >> 63);
+  int p = ((217706 * q) >> 16) + 63 - l + u;  // exponent of the leading bit
+  if (p <= F.min_exp - 64) {
+    if (!away) st = kStRange;
+    return away ? 1 : 0;
+  }
+  // rb: bits of zh below the last kept bit (all of zl lies below it too)
+  int rb = u + F.shift + 1;
+  if (p < F.min_exp) rb += F.min_exp - p;
+  const uint64_t mask = rb < 64 ? (1ull << rb) - 1 : ~0ull;
+  uint64_t m = rb < 64 ? zh >> rb : 0;
+  const uint64_t rh = zh & mask;
+  const bool rzero = rh == 0 && zl == 0;
+  const bool rtop = rh == mask && zl >= ~1ull;  // R >= 2^r - 2
+  bool inexact = true;
+  if (q >= 0 && q <= 27) {
+    inexact = !rzero;
+  } else if (q > 55) {
+    abort = rtop;
+  } else if (q < 0) {
+    if ((rzero || rtop) && q >= -27) {
+      // divisible by 5^-q?  n = w * (5^-q)^-1 mod 2^64 is the quotient if so
+      uint64_t p5 = 1, inv = 1;
+      for (int k = 0; k < -q; ++k) {
+        p5 *= 5;
+        inv *= 0xCCCCCCCCCCCCCCCDull;  // 5^-1 mod 2^64
+      }
+      const uint64_t n = w0 * inv;
+      uint64_t hi, lo;
+      mul_64x64(n, p5, hi, lo);
+      if (hi == 0 && lo == w0) return round_exact(n, q, false, F, away ? kDirAway : kDirTruncate, st);
+    }
+    abort = rzero || rtop;
+  }
+  if (away && inexact) ++m;
+  if (p < F.min_exp) {  // subnormal; m == 2^mant encodes the smallest normal
+    if (m == 0) st = kStRange;
+    return m;
+  }
+  if (m == (2ull << F.mant)) {
+    m >>= 1;
+    p += 1;
+  }
+  if (p > F.max_exp) {
+    st = kStRange;
+    return away ? F.inf : largest;
+  }
+  return ((uint64_t)(p + F.bias) << F.mant) | (m & ((1ull << F.mant) - 1));
+}
+
+// ---------------------------------------------------------------------------
 // Delimiter classification.
 // ---------------------------------------------------------------------------
 FFP_HD bool is_delim(const DelimSet& d, uint32_t c) {
@@ -340,9 +457,10 @@ FFP_HD Lexed lex_hex(const Src& src, uint64_t pos, Lexed r) {
   return r;
 }
 
-// kHex: hexadecimal tokens are recognised (flag FFP_HEX); kernels built
-// without them keep their registers for the decimal path.
-template <bool kHex = true, class Src>
+// kExt: the extensions (hexadecimal tokens, flag FFP_HEX, and directed
+// rounding) are compiled in; kernels built without them keep their registers
+// for the decimal path.
+template <bool kExt = true, class Src>
 FFP_HD Lexed lex_token(const Src& src, uint64_t pos, uint32_t flags) {
   Lexed r;
   r.w = 0;
@@ -370,7 +488,7 @@ FFP_HD Lexed lex_token(const Src& src, uint64_t pos, uint32_t flags) {
     if (r.kind != kLexInvalid) r.kind = kind;
     return r;
   }
-  if (kHex && (flags & kFlagHex) && c == '0' && (src(pos + 1) | 0x20u) == 'x')
+  if (kExt && (flags & kFlagHex) && c == '0' && (src(pos + 1) | 0x20u) == 'x')
     return lex_hex(src, pos, r);
   const uint32_t first_digit = c;  // for the JSON leading-zero rule
   uint32_t nsig = 0;
@@ -458,28 +576,40 @@ struct GlobalSrc {
 // Decision for one lexed token: Algorithm 1 on w (and on w+1 when digits
 // beyond the 19th were dropped and not all zero, Section 11).
 // ---------------------------------------------------------------------------
-// Nearest value of w * 2^q (plus something below its last bit when
-// `sticky`), ties to even: the exact rounding of a hexadecimal token.
-FFP_HD uint64_t hex_round(uint64_t w, int q, bool sticky, const FormatRT& F, uint32_t& st) {
+// Rounding of w * 2^q (plus something below its last bit when `sticky`)
+// in direction `dir`: the exact rounding of a hexadecimal token, and of a
+// decimal that reduces to an integer times a power of two.
+FFP_HD uint64_t round_exact(uint64_t w, int q, bool sticky, const FormatRT& F, uint32_t dir,
+                            uint32_t& st) {
   st = kStOk;
   if (w == 0) return 0;
+  const uint64_t largest = F.inf - 1;
   const int l = __builtin_clzll(w);
   w <<= l;
   int64_t e = (int64_t)q + 63 - l;  // exponent of the leading bit
   if (e > F.max_exp) {
     st = kStRange;
-    return F.inf;
+    return dir == kDirTruncate ? largest : F.inf;
   }
   const int64_t unit = (e < F.min_exp ? F.min_exp : e) - F.mant;  // exponent of the last kept bit
   const int64_t s = 63 + unit - e;  // bits of w below it, >= 63 - mant
-  uint64_t m = 0;
-  bool up = false;
-  if (s == 64) {  // w is at least half a unit (w >= 2^63); exactly half is a tie to 0
-    up = w > (1ull << 63) || sticky;
-  } else if (s < 64) {
+  uint64_t m = 0, rem = w;          // rem: the bits below the last kept one
+  if (s < 64) {
     m = w >> s;
-    const uint64_t rem = w & ((1ull << s) - 1), half = 1ull << (s - 1);
-    up = rem > half || (rem == half && (sticky || (m & 1)));
+    rem = w & ((1ull << s) - 1);
+  }
+  bool up;
+  if (dir == kDirNearest) {
+    if (s == 64) {  // w is at least half a unit (w >= 2^63); exactly half is a tie to 0
+      up = w > (1ull << 63) || sticky;
+    } else if (s < 64) {
+      const uint64_t half = 1ull << (s - 1);
+      up = rem > half || (rem == half && (sticky || (m & 1)));
+    } else {
+      up = false;  // below half a unit
+    }
+  } else {
+    up = dir == kDirAway && (rem != 0 || sticky);
   }
   if (up) ++m;
   if (e < F.min_exp) {  // subnormal; m == 2^mant encodes the smallest normal
@@ -492,7 +622,7 @@ FFP_HD uint64_t hex_round(uint64_t w, int q, bool sticky, const FormatRT& F, uin
   }
   if (e > F.max_exp) {
     st = kStRange;
-    return F.inf;
+    return dir == kDirTruncate ? largest : F.inf;
   }
   return ((uint64_t)(e + F.bias) << F.mant) | (m & ((1ull << F.mant) - 1));
 }
@@ -504,10 +634,12 @@ struct DecisionRT {
   bool fallback;      // undecided: needs the exact fallback
 };
 
-// qnan / sign: the format's canonical quiet NaN and sign bit.
-template <bool kHex = true>
+// qnan / sign: the format's canonical quiet NaN and sign bit; flags: the
+// rounding direction (with kExt).
+template <bool kExt = true>
 FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* table,
-                                  const FormatRT& fmt, uint64_t qnan, uint64_t sign) {
+                                  const FormatRT& fmt, uint64_t qnan, uint64_t sign,
+                                  uint32_t flags) {
   DecisionRT d;
   d.fallback = false;
   if (L.kind == kLexInvalid) {
@@ -522,8 +654,10 @@ FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* tabl
     d.path = kCntEarly;
     return d;
   }
-  if (kHex && (L.kind == kLexHex || L.kind == kLexHexSticky)) {
-    d.bits = hex_round(L.w, L.q, L.kind == kLexHexSticky, fmt, d.status) | (L.neg ? sign : 0);
+  const uint32_t dir = kExt ? round_dir(flags, L.neg) : (uint32_t)kDirNearest;
+  if (kExt && (L.kind == kLexHex || L.kind == kLexHexSticky)) {
+    d.bits = round_exact(L.w, L.q, L.kind == kLexHexSticky, fmt, dir, d.status) |
+             (L.neg ? sign : 0);
     d.path = kCntOne;
     return d;
   }
@@ -537,15 +671,30 @@ FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* tabl
   const uint64_t thi = table[2 * (qi - kQMin)];
   const uint64_t tlo = table[2 * (qi - kQMin) + 1];
   bool ab;
-  d.bits = alg1_rt(L.w, L.q, thi, tlo, fmt, ab, d.status);
-  d.fallback = ab;
   d.path = (L.q < kQMin || L.q > kQMax) ? kCntEarly : kCntOne;
-  if (L.kind == kLexTruncated) {
-    bool ab2;
-    uint32_t st2;
-    const uint64_t b2 = alg1_rt(L.w + 1, L.q, thi, tlo, fmt, ab2, st2);
-    d.fallback = d.fallback || ab2 || b2 != d.bits;
-    d.path = kCntTwo;
+  if (kExt && dir != kDirNearest) {
+    // w and w+1 bracket a truncated token's value; a monotone rounding that
+    // maps both ends to the same result and status maps the value there too
+    const bool away = dir == kDirAway;
+    d.bits = alg1_dir_rt(L.w, L.q, thi, tlo, fmt, away, ab, d.status);
+    d.fallback = ab;
+    if (L.kind == kLexTruncated) {
+      bool ab2;
+      uint32_t st2;
+      const uint64_t b2 = alg1_dir_rt(L.w + 1, L.q, thi, tlo, fmt, away, ab2, st2);
+      d.fallback = d.fallback || ab2 || b2 != d.bits || st2 != d.status;
+      d.path = kCntTwo;
+    }
+  } else {
+    d.bits = alg1_rt(L.w, L.q, thi, tlo, fmt, ab, d.status);
+    d.fallback = ab;
+    if (L.kind == kLexTruncated) {
+      bool ab2;
+      uint32_t st2;
+      const uint64_t b2 = alg1_rt(L.w + 1, L.q, thi, tlo, fmt, ab2, st2);
+      d.fallback = d.fallback || ab2 || b2 != d.bits;
+      d.path = kCntTwo;
+    }
   }
   if (L.neg) d.bits |= sign;
   if (d.fallback) d.path = kCntFallback;
@@ -560,10 +709,10 @@ struct Decision {
   bool fallback;            // undecided: needs the exact fallback
 };
 
-template <class F, bool kHex = true>
-FFP_HD Decision<F> decide_lexed(const Lexed& L, const unsigned long long* table) {
+template <class F, bool kExt = true>
+FFP_HD Decision<F> decide_lexed(const Lexed& L, const unsigned long long* table, uint32_t flags) {
   constexpr FormatRT fmt = format_of<F>();
-  const DecisionRT r = decide_lexed_rt<kHex>(L, table, fmt, F::kQNaN, F::kSign);
+  const DecisionRT r = decide_lexed_rt<kExt>(L, table, fmt, F::kQNaN, F::kSign, flags);
   Decision<F> d;
   d.bits = (typename F::bits_t)r.bits;
   d.status = r.status;

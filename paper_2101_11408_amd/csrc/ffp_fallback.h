@@ -19,7 +19,10 @@
 //     nearest encoding by comparing v with the halfway points
 //     (2m+1) * 2^(e-1) between neighbouring values, ties to even; encodings
 //     are used as integers, so "next value up" crosses binades and reaches
-//     infinity.
+//     infinity (whose encoding reads as the value 2^(emax+1));
+//   - under a directed rounding mode the comparisons are with the values
+//     m * 2^e themselves: the truncation is the largest encoding not above
+//     v, the rounding away from zero the smallest not below it.
 // Every branch below depends only on wave-uniform values, so the lanes stay
 // converged for the cross-lane operations.
 #pragma once
@@ -316,11 +319,12 @@ __device__ FbToken fb_lex(const uint8_t* text, uint64_t nbytes, uint64_t pos, Fb
 // ---------------------------------------------------------------------------
 template <class F>
 __device__ void fb_decide(const uint8_t* text, uint64_t nbytes, uint64_t pos,
-                          const unsigned long long* table, FbLds* lds,
+                          const unsigned long long* table, FbLds* lds, uint32_t flags,
                           typename F::bits_t& out_bits, uint32_t& out_status) {
   using Bits = typename F::bits_t;
   const int l = fb_lane();
   const FbToken t = fb_lex(text, nbytes, pos, lds);
+  const uint32_t dir = round_dir(flags, t.neg);
 
   Bits bits = 0;
   uint32_t status = kStOk;
@@ -331,10 +335,14 @@ __device__ void fb_decide(const uint8_t* text, uint64_t nbytes, uint64_t pos,
     int kept = t.nsig < kFallbackDigits ? (int)t.nsig : kFallbackDigits;
     const int64_t q64 = t.e10 - t.nfrac + (t.nsig - nw);
     int64_t f64v = t.e10 - t.nfrac + (t.nsig - kept);
-    if (q64 < kQMin) {
-      status = kStRange;
+    if (q64 < kQMin) {  // below half the smallest subnormal
+      if (dir == kDirAway) {
+        bits = 1;
+      } else {
+        status = kStRange;
+      }
     } else if (q64 > kQMax) {
-      bits = F::kInf;
+      bits = dir == kDirTruncate ? F::kInf - 1 : F::kInf;
       status = kStRange;
     } else {
       if (t.sticky) {  // P = 10 * P + 1: strictly between the truncation and the next digit
@@ -380,16 +388,43 @@ __device__ void fb_decide(const uint8_t* text, uint64_t nbytes, uint64_t pos,
       uint32_t st1;
       bits = alg1<F>(w, q, table[2 * (q - kQMin)], table[2 * (q - kQMin) + 1], ab, st1);
       if (bits == F::kInf) bits = F::kInf - 1;
-      // sign(v - (2m+1) * 2^(e-1)) for the midpoint above encoding b
-      auto vs_mid = [&](Bits b) {
+      // sign(v - (2m+half) * 2^(e-1)): half = 1 for the midpoint above
+      // encoding b, 0 for b itself
+      auto vs_at = [&](Bits b, uint64_t half) {
         uint64_t m;
         int e;
         decode_bits<F>(b, m, e);
-        const uint64_t h = 2 * m + 1;
+        const uint64_t h = 2 * m + half;
         const uint64_t T = f >= 0 ? (l == 0 ? h : 0) : fbig_mul_add(Y, h, 0);
         return fbig_cmp_pow2(X, f, T, e - 1);
       };
-      for (int iter = 0; iter < 8; ++iter) {
+      auto vs_mid = [&](Bits b) { return vs_at(b, 1); };
+      if (dir == kDirTruncate) {  // largest b with value(b) <= v
+        for (int iter = 0; iter < 8; ++iter) {
+          if (bits < F::kInf && vs_at((Bits)(bits + 1), 0) >= 0) {
+            bits += 1;
+            continue;
+          }
+          if (bits > 0 && vs_at(bits, 0) < 0) {
+            bits -= 1;
+            continue;
+          }
+          break;
+        }
+      } else if (dir == kDirAway) {  // smallest b with value(b) >= v
+        for (int iter = 0; iter < 8; ++iter) {
+          if (bits < F::kInf && vs_at(bits, 0) > 0) {
+            bits += 1;
+            continue;
+          }
+          if (bits > 0 && vs_at((Bits)(bits - 1), 0) <= 0) {
+            bits -= 1;
+            continue;
+          }
+          break;
+        }
+      }
+      for (int iter = 0; iter < 8 && dir == kDirNearest; ++iter) {
         if (bits < F::kInf) {
           const int up = vs_mid(bits);
           if (up > 0 || (up == 0 && (bits & 1))) {
@@ -408,6 +443,7 @@ __device__ void fb_decide(const uint8_t* text, uint64_t nbytes, uint64_t pos,
         break;
       }
       if (bits == F::kInf || bits == 0) status = kStRange;
+      if (bits == F::kInf && dir == kDirTruncate) bits = F::kInf - 1;  // overflow: largest finite
     }
   }
   if (t.neg) bits |= F::kSign;

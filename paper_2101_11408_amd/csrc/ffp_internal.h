@@ -151,6 +151,7 @@ struct FallbackParams {
   DeviceState* st;
   DelimSet delim;
   uint64_t* reduce_out;  // as in ParseParams
+  uint32_t flags;        // as in ParseParams (the rounding direction)
 };
 
 }  // namespace ffp

@@ -564,12 +564,12 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
 
 // Algorithm 1 (and w+1 for long significands) on a lexed token, the queue
 // append for undecided tokens, and the stores.  Returns the path counter.
-template <class F, bool kHex>
+template <class F, bool kExt>
 __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, const JobDesc& job,
                                             uint64_t idx, const unsigned long long* table,
                                             const ParseParams& P, uint64_t& bits_out,
                                             uint32_t& status_out) {
-  Decision<F> d = decide_lexed<F, kHex>(L, table);
+  Decision<F> d = decide_lexed<F, kExt>(L, table, P.flags);
   bits_out = d.bits;
   status_out = d.fallback ? kPending : d.status;
   uint8_t st = (uint8_t)d.status;
@@ -593,9 +593,10 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
 
 // Four workgroups per CU (the LDS allows four): registers are kept within
 // 128.  kReduce: the call also keeps the minimum, maximum and count of the
-// values; kHex: hexadecimal tokens are accepted (flag FFP_HEX).  Separate
-// instances, so that the plain parse pays nothing for either.
-template <int K, bool kSingle, bool kReduce, bool kHex>
+// values; kExt: hexadecimal tokens (flag FFP_HEX) and directed rounding are
+// compiled in.  Separate instances, so that the plain parse pays nothing for
+// either.
+template <int K, bool kSingle, bool kReduce, bool kExt>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_parse(ParseParams P) {
   using S = TileSmem<K>;
   using Packed = typename S::Packed;
@@ -741,7 +742,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           }
           Lexed L;
           if (fl.code == kFastSlow) {
-            L = global ? lex_token<kHex>(gsrc, pos, P.flags) : lex_token<kHex>(lsrc, vpos, P.flags);
+            L = global ? lex_token<kExt>(gsrc, pos, P.flags) : lex_token<kExt>(lsrc, vpos, P.flags);
           } else {
             L.w = fl.w;
             L.q = fl.q;
@@ -750,10 +751,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           }
           int path;
           switch (job.dtype) {
-            case kF64: path = finish_token<F64, kHex>(L, pos, job, idx, table, P, vbits, vstatus); break;
-            case kF32: path = finish_token<F32, kHex>(L, pos, job, idx, table, P, vbits, vstatus); break;
-            case kF16: path = finish_token<F16, kHex>(L, pos, job, idx, table, P, vbits, vstatus); break;
-            default: path = finish_token<BF16, kHex>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            case kF64: path = finish_token<F64, kExt>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            case kF32: path = finish_token<F32, kExt>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            case kF16: path = finish_token<F16, kExt>(L, pos, job, idx, table, P, vbits, vstatus); break;
+            default: path = finish_token<BF16, kExt>(L, pos, job, idx, table, P, vbits, vstatus); break;
           }
           if (P.count_paths) {
             c_tok += 1;
@@ -812,7 +813,7 @@ __device__ __forceinline__ void fallback_token(const JobDesc& job, uint64_t pos,
                                                FbLds* lds, const FallbackParams& P) {
   typename F::bits_t bits;
   uint32_t status;
-  fb_decide<F>(job.text, job.nbytes, pos, g_table, lds, bits, status);
+  fb_decide<F>(job.text, job.nbytes, pos, g_table, lds, P.flags, bits, status);
   if (fb_lane() == 0) {
     gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, bits);
     gstore(job.status + idx, (uint8_t)status);
@@ -915,14 +916,14 @@ hipError_t launch_scan(const ScanParams& P, hipStream_t s) {
 
 template <int K, bool kSingle>
 static hipError_t launch_parse_k(const ParseParams& P, int grid, hipStream_t s) {
-  const bool hex = (P.flags & kFlagHex) != 0;
+  const bool ext = (P.flags & (kFlagHex | kFlagRoundMask)) != 0;
   if (P.reduce_out) {
-    if (hex)
+    if (ext)
       hipLaunchKernelGGL((k_parse<K, kSingle, true, true>), dim3(grid), dim3(kThreads), 0, s, P);
     else
       hipLaunchKernelGGL((k_parse<K, kSingle, true, false>), dim3(grid), dim3(kThreads), 0, s, P);
   } else {
-    if (hex)
+    if (ext)
       hipLaunchKernelGGL((k_parse<K, kSingle, false, true>), dim3(grid), dim3(kThreads), 0, s, P);
     else
       hipLaunchKernelGGL((k_parse<K, kSingle, false, false>), dim3(grid), dim3(kThreads), 0, s, P);

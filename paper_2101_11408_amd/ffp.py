@@ -31,6 +31,11 @@ FFP_REJECT_PLUS = 1
 FFP_JSON = 2
 FFP_INFNAN = 4
 FFP_HEX = 8
+FFP_ROUND_MASK = 0x30
+FFP_ROUND_NEAREST = 0x00
+FFP_ROUND_TOWARD_ZERO = 0x10
+FFP_ROUND_UP = 0x20
+FFP_ROUND_DOWN = 0x30
 
 DTYPE_F64 = 0
 DTYPE_F32 = 1

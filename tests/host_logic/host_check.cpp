@@ -34,7 +34,7 @@ static void run(const std::vector<uint8_t>& buf, const ffp::DelimSet& ds, uint32
     const uint64_t start = i;
     while (i < n && !ffp::is_delim(ds, buf[i])) ++i;
     const ffp::Lexed L = ffp::lex_token(src, start, flags);
-    ffp::Decision<F> d = ffp::decide_lexed<F>(L, kTable);
+    ffp::Decision<F> d = ffp::decide_lexed<F>(L, kTable, flags);
     uint64_t bits = d.bits;
     uint8_t st = (uint8_t)d.status;
     if (d.fallback) {

@@ -185,3 +185,53 @@ def test_hex_flag(host_check, flags):
     buf = _hex_buffer(50)
     for fmt in ("f64", "f32", "f16", "bf16"):
         check(host_check, buf, fmt, "hex-%d" % flags, flags=flags)
+
+
+def _directed_tokens(seed):
+    """Tokens for the directed rounding modes: the usual mixes, decimals that
+    are exactly representable (dyadic fractions written out, integers), their
+    neighbours one unit of a far digit away, and the ends of every format's
+    range."""
+    rng = np.random.default_rng(seed)
+    toks = W.mixed_tokens(rng, 6000) + W.hard_tokens(rng, 800)
+    for _ in range(3000):
+        j = int(rng.integers(1, 28))
+        num = int(rng.integers(1, 2 ** 20))
+        digits, e10 = W._exact_decimal(num, -j)  # num * 2^-j = digits * 10^e10 exactly
+        d = int(digits)
+        toks += ["%de%d" % (d, e10), "%de%d" % (d * 10 ** 7 + 1, e10 - 7),
+                 "%de%d" % (d * 10 ** 7 - 1, e10 - 7)]
+    for _ in range(1000):
+        toks.append(str(int(rng.integers(1, 2 ** 62)) << int(rng.integers(0, 40))))
+    toks += ["7450580596923828125e-27", "0.5", "0.25", "1.5", "0.1", "-0.1", "1e23", "9007199254740993",
+             "18446744073709551616", "1e309", "-1e309", "1.7976931348623157e308",
+             "1.7976931348623158e308", "1.7976931348623159e308", "4.9e-324", "2e-324", "1e-400",
+             "-1e-400", "3.4028235e38", "3.4028236e38", "1.4e-45", "1e-46", "-1e-46", "65504",
+             "65519", "65520", "6e-8", "5.96e-8", "2.9e-8", "3.3895313892515355e38", "1e39", "9.2e-41"]
+    return toks
+
+
+@pytest.mark.parametrize("flags", [16, 32, 48, 56])
+def test_directed_rounding_modes(host_check, flags):
+    """Directed rounding (toward zero, +inf, -inf; 56 = -inf with hex tokens)
+    through the byte-by-byte lexer and Algorithm 1's directed form."""
+    toks = _directed_tokens(51)
+    if flags & 8:
+        toks += W.hex_tokens(np.random.default_rng(52), 2000)
+    buf = W.join_tokens(toks)
+
+    def significant(tok):
+        s = tok.lstrip("+-")
+        if s[:2].lower() == "0x":
+            return 0  # hexadecimal: always exact in-line
+        mant = s.split("e")[0].split("E")[0].replace(".", "")
+        return len(mant.strip("0"))
+
+    short = np.array([significant(tk) <= 19 for tk in toks])
+    for fmt in ("f64", "f32", "f16", "bf16"):
+        check(host_check, buf, fmt, "round-%d" % flags, flags=flags)
+        _, st, _ = run_host(host_check, buf, fmt, flags=flags)
+        # up to 19 significant digits Algorithm 1's directed form decides
+        # in-line; longer tokens whose value is within their dropped digits
+        # of a representable value need the exact fallback
+        assert not (short & (st == 255)).any(), [toks[i] for i in np.flatnonzero(short & (st == 255))[:5]]

@@ -242,3 +242,21 @@ def test_batch_hex_tokens(ffpmod):
         check_jobs(hp, table, values, statuses, spans, "hex", flags=8)
     finally:
         c.close()
+
+
+def test_batch_directed_rounding(ffpmod, pool):
+    """Rounding toward -infinity in a batch of the four output types."""
+    rng = np.random.default_rng(19)
+    n = 100
+    sizes = W.lognormal_sizes(rng, n, 8000, 1.5, 1, 100_000)
+    kinds = [torch.float64, torch.float32, torch.float16, torch.bfloat16]
+    dtypes = [kinds[int(k)] for k in rng.integers(0, 4, n)]
+    c = ffpmod.Context(0, flags=ffpmod.FFP_ROUND_DOWN)
+    try:
+        table, values, statuses, spans = build_jobs(ffpmod, pool, sizes, None, 20, dtypes)
+        c.parse_batch(table.dev, table.n, table.total_bytes)
+        torch.cuda.synchronize()
+        assert c.last_device_error() == 0
+        check_jobs(pool, table, values, statuses, spans, "round-down", flags=0x30)
+    finally:
+        c.close()

@@ -456,6 +456,49 @@ def test_hex_tokens_with_reduction(ffpmod, hex_case):
         c.close()
 
 
+@pytest.fixture(scope="module")
+def directed_case():
+    """Mixed and hard tokens, exactly representable decimals (dyadic
+    fractions written out, large integers) with neighbours one unit of a far
+    digit away, hexadecimal tokens, and the ends of every format's range."""
+    rng = np.random.default_rng(66)
+    toks = W.mixed_tokens(rng, 20_000) + W.hard_tokens(rng, 1500) + W.hex_tokens(rng, 3000)
+    for _ in range(4000):
+        digits, e10 = W._exact_decimal(int(rng.integers(1, 2 ** 20)), -int(rng.integers(1, 28)))
+        d = int(digits)
+        toks += ["%de%d" % (d, e10), "%de%d" % (d * 10 ** 7 + 1, e10 - 7),
+                 "%de%d" % (d * 10 ** 7 - 1, e10 - 7)]
+    toks += [str(int(rng.integers(1, 2 ** 62)) << int(rng.integers(0, 40))) for _ in range(1000)]
+    toks += ["1e309", "-1e309", "1.7976931348623158e308", "1.7976931348623159e308", "4.9e-324",
+             "2e-324", "1e-400", "-1e-400", "3.4028235e38", "3.4028236e38", "1e-46", "-1e-46",
+             "65504", "65520", "6e-8", "2.9e-8", "1e39", "-0", "0", "inf", "-nan", "x"]
+    rng.shuffle(toks)
+    return toks, W.join_tokens(toks)
+
+
+@pytest.mark.parametrize("mode", [0x10, 0x20, 0x30])
+@pytest.mark.parametrize("tile_k", [1, 4])
+def test_directed_rounding(ffpmod, directed_case, mode, tile_k):
+    """Rounding toward zero, +inf and -inf (with hexadecimal and inf/nan
+    tokens), every output type; long tokens near representable values go
+    through the exact fallback."""
+    toks, buf = directed_case
+    flags = mode | ffpmod.FFP_HEX | ffpmod.FFP_INFNAN
+    c = ffpmod.Context(0, flags=flags)
+    try:
+        c.set_tuning(tile_k, 0, 16)
+        for fmt in ("f64", "f32", "f16", "bf16"):
+            _log("case directed", hex(mode), "tile_k", tile_k, fmt)
+            rc, n, bits, status = run_gpu(c, buf, fmt, offset=1)
+            wb, ws = parse_buffer(buf, fmt, flags=flags)
+            assert rc == len(wb) and n == len(wb)
+            bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                 (status[:n] != np.array(ws, dtype=np.uint8)))
+            assert bad.size == 0, (hex(mode), tile_k, fmt, [toks[i] for i in bad[:5]])
+    finally:
+        c.close()
+
+
 # ---------------------------------------------------------------------------
 # in-kernel reduction
 # ---------------------------------------------------------------------------
