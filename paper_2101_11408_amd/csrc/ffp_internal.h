@@ -73,7 +73,7 @@ struct QueueEntry {
 
 struct DeviceState {
   unsigned int error;
-  unsigned int done_wgs;            // fallback workgroups finished (reduction)
+  unsigned int pad;
   unsigned long long queue_tail;
   unsigned long long total_blocks;  // batched calls: blocks of all jobs
   unsigned long long counters[8];

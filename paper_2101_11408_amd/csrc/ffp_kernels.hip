@@ -311,7 +311,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
     P.block_sum[n] = s_carry;
     P.st->queue_tail = 0;
     P.st->error = 0;
-    P.st->done_wgs = 0;
     P.st->red_min = ~0ull;
     P.st->red_max = 0;
     P.st->red_count = 0;
@@ -845,23 +844,27 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(FallbackParams P) {
       default: fallback_token<BF16>(job, e.offset, idx, &lds[wid], P); break;
     }
   }
-  if (P.reduce_out) {  // the last workgroup to finish writes the result
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      if (atomicAdd(&P.st->done_wgs, 1u) == gridDim.x - 1) {
-        const unsigned long long kmin = atomicAdd(&P.st->red_min, 0ull);
-        const unsigned long long kmax = atomicAdd(&P.st->red_max, 0ull);
-        const unsigned long long cnt = atomicAdd(&P.st->red_count, 0ull);
-        const uint32_t dt = P.js.single.dtype;
-        const uint64_t nan = dt == kF64 ? F64::kQNaN : dt == kF32 ? F32::kQNaN
-                             : dt == kF16 ? F16::kQNaN : BF16::kQNaN;
-        gstore(P.reduce_out + 0, cnt ? key_to_bits(kmin, dt) : nan);
-        gstore(P.reduce_out + 1, cnt ? key_to_bits(kmax, dt) : nan);
-        gstore(P.reduce_out + 2, (uint64_t)cnt);
-      }
-    }
-  }
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce_final (plain calls with a reduction): one thread turns the
+// call's minimum / maximum keys and count into the caller's three words.
+// A kernel of its own: the kernel boundary orders it after every update of
+// the parse and fallback kernels (a last-workgroup test inside the fallback
+// kernel would need a device-scope fence in every workgroup, which writes
+// back the XCD's L2 each time).
+// ---------------------------------------------------------------------------
+__global__ void k_reduce_final(FallbackParams P) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long kmin = P.st->red_min;
+  const unsigned long long kmax = P.st->red_max;
+  const unsigned long long cnt = P.st->red_count;
+  const uint32_t dt = P.js.single.dtype;
+  const uint64_t nan = dt == kF64 ? F64::kQNaN : dt == kF32 ? F32::kQNaN
+                       : dt == kF16 ? F16::kQNaN : BF16::kQNaN;
+  gstore(P.reduce_out + 0, cnt ? key_to_bits(kmin, dt) : nan);
+  gstore(P.reduce_out + 1, cnt ? key_to_bits(kmax, dt) : nan);
+  gstore(P.reduce_out + 2, (uint64_t)cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -942,6 +945,7 @@ hipError_t launch_parse(int k, bool single_delim, const ParseParams& P, int grid
 
 hipError_t launch_fallback(const FallbackParams& P, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(kFbThreads), 0, s, P);
+  if (P.reduce_out) hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kWave), 0, s, P);
   return hipGetLastError();
 }
 
