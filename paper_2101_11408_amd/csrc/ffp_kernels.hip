@@ -403,19 +403,27 @@ struct TileSmem {
   // masked off).
   static constexpr int kPadFront = 32;
   static constexpr int kPadBack = 96;
+  // The 1 KiB of text after the tile (the first chunks of the next tile, or
+  // delimiters past the job's end) is added before the round that decides a
+  // token running past the tile's end, so that such a token is lexed from
+  // LDS like the others; only a token reaching beyond it reads global memory.
+  static constexpr int kExtChunks = kWave;
+  static constexpr int kExtBytes = kExtChunks * kChunk;
   // block scan of the per-thread start counts: one 16-bit field per row of
   // 256 chunks (a row holds at most 2048 starts)
   using Packed = typename std::conditional<(K <= 2), uint32_t, uint64_t>::type;
   unsigned long long pow10[20];
-  alignas(16) uint8_t text[kPadFront + kBytes + kPadBack];
+  alignas(16) uint8_t text[kPadFront + kBytes + kExtBytes + kPadBack];
   uint16_t starts[kBytes / 2];
   // bit i of these bitmaps describes byte i of the tile (16 bits per chunk),
-  // followed by 128 zero bits so that 32-bit windows stay in range
-  alignas(8) uint16_t nd[kChunks + 8];  // not a delimiter
-  alignas(8) uint16_t dg[kChunks + 8];  // ASCII digit
+  // then the extension, then 128 zero bits so that 32-bit windows stay in
+  // range
+  alignas(8) uint16_t nd[kChunks + kExtChunks + 8];  // not a delimiter
+  alignas(8) uint16_t dg[kChunks + kExtChunks + 8];  // ASCII digit
   uint8_t delim_lut[256];
   Packed scan[kThreads / kWave];
   uint32_t prev_nd;
+  uint32_t ext_end;  // the extension holds a delimiter
   unsigned long long red_min, red_max, red_count;  // this workgroup's reduction
 };
 
@@ -614,7 +622,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     for (int i = 0; i < tid; ++i) p *= 10;
     sm.pow10[tid] = p;
   }
-  if (tid < 8) {
+  if (tid < S::kExtChunks + 8) {
     sm.nd[S::kChunks + tid] = 0;
     sm.dg[S::kChunks + tid] = 0;
   }
@@ -667,11 +675,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                                                 digit_word(v.z), digit_word(v.w));
       }
       const uint64_t next_start = tile_start + S::kBytes;
-      if (t + 1 < ntiles && next_start < vend) {
+      // pre[] takes the next tile of the block; at the block's end wave 0
+      // loads the extension (the 1 KiB after the tile) instead
+      const bool next_loaded = t + 1 < ntiles && next_start < vend;
+      uint4 ext_v = make_uint4(0, 0, 0, 0);
+      if (next_loaded) {
 #pragma unroll
         for (int c = 0; c < K; ++c)
           pre[c] = load_chunk(vbase, next_start + (uint64_t)(c * kThreads + tid) * kChunk, align,
                               vend, P.delim.byte);
+      } else if (tid < S::kExtChunks) {
+        ext_v = load_chunk(vbase, next_start + (uint64_t)tid * kChunk, align, vend, P.delim.byte);
       }
       if (tid == 0 && t == 0) sm.prev_nd = prev_nondelim(vbase, tile_start, align, P.delim);
       __syncthreads();
@@ -712,14 +726,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 
       // -- one lane per token -------------------------------------------
       // When the tile's last byte belongs to a token, that token (the last
-      // one starting here) may continue past the tile: it is read from
-      // global memory, which returns a delimiter past the end of the text.
+      // one starting here) continues past the tile: the extension is filled
+      // before its round; if the token also runs past the extension it is
+      // read from global memory, which returns a delimiter past the text.
       const bool straddle = (sm.nd[S::kChunks - 1] >> 15) & 1u;
       const LdsSrc lsrc{sm.text + S::kPadFront, tile_start, sm.delim_lut};
       // tokens of this tile that fit the caller's capacity
       const uint32_t nfit = next_idx >= job.capacity ? 0u
                             : (job.capacity - next_idx < ntok ? (uint32_t)(job.capacity - next_idx)
                                                               : ntok);
+      if (straddle && nfit == ntok) {  // the last token is decided here: fill the extension
+        if (tid < S::kExtChunks) {  // wave 0: chunk tid of the next tile
+          const uint4 v = next_loaded ? pre[0] : ext_v;
+          *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + S::kBytes + tid * kChunk]) = v;
+          const uint32_t m = nondelim_mask16<kSingle>(v, drep, sm.delim_lut);
+          sm.nd[S::kChunks + tid] = (uint16_t)m;
+          sm.dg[S::kChunks + tid] = (uint16_t)pack_high_bits(digit_word(v.x), digit_word(v.y),
+                                                             digit_word(v.z), digit_word(v.w));
+          const uint64_t has_delim = (uint64_t)__ballot(m != 0xFFFFu);
+          if (tid == 0) sm.ext_end = has_delim != 0;
+        }
+        __syncthreads();
+      }
+      // the token read from global memory, if any (index; ~0: none)
+      const uint32_t global_j = straddle && nfit == ntok && !sm.ext_end ? ntok - 1 : ~0u;
       // whole rounds of 256 tokens: lanes without a token in the last round
       // stay in step, so the reduction below sees every lane
       for (uint32_t round = 0; round < nfit; round += kThreads) {
@@ -732,7 +762,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           const uint32_t s = sm.starts[j];
           const uint64_t vpos = tile_start + s;  // virtual
           const uint64_t pos = vpos - align;     // offset in the text
-          const bool global = straddle && j == ntok - 1;
+          const bool global = j == global_j;
           FastLex fl;
           if (!global) {
             fl = fast_lex<K>(sm, s, P.flags);
