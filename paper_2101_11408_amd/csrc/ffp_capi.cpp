@@ -179,7 +179,7 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uin
 
 int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t nbytes,
                  void* d_values, uint8_t* d_status, uint64_t capacity, uint64_t* d_count,
-                 void* stream) {
+                 void* stream, int32_t* d_err = nullptr) {
   if (!ctx || !d_count) return FFP_E_ARG;
   if (nbytes >= ffp::kMaxBytes) return FFP_E_ARG;
   if (nbytes > 0 && !d_text) return FFP_E_ARG;
@@ -195,7 +195,7 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   job.status = d_status;
   job.capacity = capacity;
   job.count_out = d_count;
-  job.err_out = nullptr;
+  job.err_out = d_err;
   job.block_begin = 0;
   job.dtype = dtype;
   job.job_id = 0;
@@ -319,8 +319,9 @@ int ctx_grow(ffp_ctx* ctx, uint64_t bytes, uint64_t njobs) {
 
 int ctx_parse(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t nbytes,
               void* d_values, uint8_t* d_status, uint64_t capacity, uint64_t* d_count,
-              hipStream_t s) {
-  return parse_common(ctx, dtype, d_text, nbytes, d_values, d_status, capacity, d_count, s);
+              hipStream_t s, int32_t* d_err) {
+  return parse_common(ctx, dtype, d_text, nbytes, d_values, d_status, capacity, d_count, s,
+                      d_err);
 }
 
 int ctx_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,

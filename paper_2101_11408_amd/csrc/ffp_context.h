@@ -57,9 +57,11 @@ namespace ffp {
 int ctx_grow(ffp_ctx* ctx, uint64_t bytes, uint64_t njobs);
 
 // Stream-ordered plain parse of one buffer (the body of ffp_parse_f64/f32).
+// d_err (or null) receives the error codes a batched job record would get
+// (capacity exceeded, fallback queue overflow).
 int ctx_parse(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t nbytes,
               void* d_values, uint8_t* d_status, uint64_t capacity, uint64_t* d_count,
-              hipStream_t s);
+              hipStream_t s, int32_t* d_err = nullptr);
 
 // Stream-ordered batched parse (the body of ffp_parse_batch).
 int ctx_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,

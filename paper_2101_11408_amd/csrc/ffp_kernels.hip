@@ -658,6 +658,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     for (int c = 0; c < K; ++c)
       pre[c] = load_chunk(vbase, bstart + (uint64_t)(c * kThreads + tid) * kChunk, align, vend,
                           P.delim.byte);
+    // the byte before the block, loaded with the block's first chunks
+    const uint32_t block_prev = tid == 0 ? prev_nondelim(vbase, bstart, align, P.delim) : 0u;
     for (int t = 0; t < ntiles; ++t) {
       const uint64_t tile_start = bstart + (uint64_t)t * S::kBytes;  // virtual
       if (tile_start >= vend) break;
@@ -687,7 +689,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       } else if (tid < S::kExtChunks) {
         ext_v = load_chunk(vbase, next_start + (uint64_t)tid * kChunk, align, vend, P.delim.byte);
       }
-      if (tid == 0 && t == 0) sm.prev_nd = prev_nondelim(vbase, tile_start, align, P.delim);
+      if (tid == 0 && t == 0) sm.prev_nd = block_prev;
       __syncthreads();
 
       // -- token starts: non-delimiter byte after a delimiter -----------

@@ -179,13 +179,16 @@ struct ffp_server {
       j.dtype = r->dtype;
       j.err = 0;
     }
-    if (mode == FFP_SERVE_PLAIN) {
+    // one request without a captured graph: the plain kernel sequence (no
+    // job-table kernel); count and error codes still land in its record
+    if (mode == FFP_SERVE_PLAIN || (n == 1 && !use_graph)) {
       std::atomic_thread_fence(std::memory_order_release);
       Req* r = s.reqs[0];
       const uint8_t* text = r->on_device ? r->text : r->d_text;
       const int rc = ffp::ctx_parse(s.ctx, (uint32_t)r->dtype,
                                     r->nbytes ? text : nullptr, r->nbytes, r->d_values,
-                                    r->d_status, r->capacity, &s.d_jobs[0].count, s.stream);
+                                    r->d_status, r->capacity, &s.d_jobs[0].count, s.stream,
+                                    &s.d_jobs[0].err);
       if (rc != FFP_SUCCESS) return rc;
     } else {
       // records past this batch must be empty jobs when the graph replays a
