@@ -239,6 +239,70 @@ def test_long_tokens(ctx):
     compare_full(ctx, buf, "f32", "long")
 
 
+@pytest.fixture(scope="module")
+def straddle_case():
+    """Tokens that start just before a 4 KiB boundary and run past it by
+    1..2000 bytes (around the 16-byte chunk, the 32-byte bitmap window and the
+    1 KiB of text the parse kernel keeps after each tile), short filler in
+    between, and a last token that reaches the end of the text."""
+    rng = np.random.default_rng(67)
+    overhangs = [1, 2, 15, 16, 17, 31, 32, 33, 100, 1007, 1008, 1023, 1024, 1025, 1040, 2000]
+    digits = "".join(map(str, rng.integers(0, 10, 4000).tolist()))
+    out, toks = bytearray(), []
+    for i in range(48):
+        # the next 4 KiB boundary at least 200 bytes ahead (sometimes one more)
+        boundary = ((len(out) + 200) // 4096 + 1 + (i % 3 == 2)) * 4096
+        while len(out) < boundary - 40:  # filler up to just before the boundary
+            tok = W.mixed_tokens(rng, 1)[0]
+            if len(out) + len(tok) + 1 > boundary - 40:
+                tok = "7" * max(1, boundary - 41 - len(out))
+            out += tok.encode() + b"\n"
+            toks.append(tok)
+        start = boundary - int(rng.integers(1, 40))
+        while len(out) < start:
+            out += b"\n"
+        start = len(out)
+        over = overhangs[i % len(overhangs)]
+        n = boundary + over - start
+        kind = i % 4
+        if kind == 0:
+            tok = "1" + digits[: max(0, n - 1)]
+        elif kind == 1:
+            tok = ("0." + digits)[:n]
+        elif kind == 2:
+            tok = (digits[: max(1, n - 5)] + "e-" + "123")[:n] if n > 6 else "5" * n
+        else:
+            tok = ("-" + "0" * (n - 3) + "25")[:n] if n > 3 else "9" * n
+        out += tok.encode() + b"\n"
+        toks.append(tok)
+    tail = "3." + digits[:1500]  # ends exactly at the end of the text (no delimiter)
+    out += tail.encode()
+    toks.append(tail)
+    buf = bytes(out)
+    return toks, buf, {fmt: parse_buffer(buf, fmt) for fmt in ("f64", "f32")}
+
+
+@pytest.mark.parametrize("tile_k,block_kib", [(4, 16), (4, 64), (2, 16), (1, 16), (1, 4)])
+def test_tokens_across_tile_ends(ffpmod, straddle_case, tile_k, block_kib):
+    """A token running past its tile is lexed from the text kept after the
+    tile (the next tile's chunks inside a block, loaded ones at a block's
+    end) or, beyond that, from global memory; all must match the oracle."""
+    toks, buf, want = straddle_case
+    c = ffpmod.Context(0)
+    try:
+        c.set_tuning(tile_k, 0, block_kib)
+        for fmt in ("f64", "f32"):
+            _log("case straddle", tile_k, block_kib, fmt, len(buf))
+            rc, n, bits, status = run_gpu(c, buf, fmt)
+            wb, ws = want[fmt]
+            assert rc == len(wb) and n == len(wb)
+            bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                 (status[:n] != np.array(ws, dtype=np.uint8)))
+            assert bad.size == 0, (tile_k, block_kib, fmt, [toks[i][:60] for i in bad[:3]])
+    finally:
+        c.close()
+
+
 def test_delimiter_set_and_flags(ffpmod):
     c = ffpmod.Context(0, delims=b",; \t\r\n", flags=ffpmod.FFP_REJECT_PLUS)
     try:
