@@ -569,6 +569,123 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
   return r;
 }
 
+// First position >= p (a tile offset) whose bit in a tile bitmap is clear;
+// the bitmaps end in zero bits, so the scan always stops.
+__device__ __forceinline__ uint32_t run_end(const uint16_t* bm, uint32_t p) {
+  for (;;) {
+    const uint32_t w = bit_window(bm, p);
+    if (w != ~0u) return p + (uint32_t)__builtin_ctz(~w);
+    p += 32;
+  }
+}
+
+// First position in [p, end) of the tile text whose byte is not '0' (all
+// bytes there are digits), or end; 16 bytes per LDS read.
+template <int K>
+__device__ __forceinline__ uint32_t first_nonzero_digit(const TileSmem<K>& sm, uint32_t p,
+                                                        uint32_t end) {
+  const uint8_t* tb = sm.text + TileSmem<K>::kPadFront;
+  while (p < end) {
+    const uint32_t a = p & ~15u;
+    const uint4 v = *reinterpret_cast<const uint4*>(tb + a);
+    const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t base = a + 4 * i;
+      uint32_t x = wd[i] ^ 0x30303030u;  // zero bytes are '0'
+      if (base + 4 <= p) x = 0;
+      else if (base < p) x &= ~0u << (8 * (p - base));
+      if (base >= end) x = 0;
+      else if (end - base < 4) x &= (1u << (8 * (end - base))) - 1u;
+      if (x) return base + ((uint32_t)__builtin_ctz(x) >> 3);
+    }
+    p = a + 16;
+  }
+  return end;
+}
+
+// Lexer for a token the bitmap lexer leaves to the byte-by-byte one (32
+// bytes or longer, more than 19 significant digits, more than 8 exponent
+// digits), when the token lies in the tile (or the text kept after it) and
+// no grammar flag other than FFP_REJECT_PLUS is set.  Digit runs are found
+// 32 bytes at a time on the bitmaps, leading zeros and nonzero dropped
+// digits 16 bytes at a time; the first 19 significant digits are converted
+// with the SWAR helpers.  The result equals lex_token's (Section 4's grammar;
+// Section 11's w, q and the dropped-digit flag).
+template <int K>
+__device__ Lexed long_lex(const TileSmem<K>& sm, uint32_t s, uint32_t flags) {
+  const uint8_t* tb = sm.text + TileSmem<K>::kPadFront;
+  Lexed r;
+  r.w = 0;
+  r.q = 0;
+  r.neg = 0;
+  r.kind = kLexInvalid;
+  const uint32_t end = run_end(sm.nd, s);
+  const uint32_t c0 = tb[s];
+  uint32_t i0 = s;
+  if (c0 == '-' || c0 == '+') {
+    r.neg = c0 == '-';
+    if (c0 == '+' && (flags & kFlagRejectPlus)) return r;
+    ++i0;
+  }
+  const uint32_t b = run_end(sm.dg, i0);  // end of the integer digits
+  uint32_t f0 = b, f1 = b;
+  if (tb[b] == '.') {
+    f0 = b + 1;
+    f1 = run_end(sm.dg, f0);
+  }
+  const uint32_t nint = b - i0, nfrac = f1 - f0;
+  if (nint + nfrac == 0) return r;
+  uint32_t p = f1;
+  int64_t e = 0;
+  if ((tb[p] | 0x20u) == 'e') {
+    uint32_t e0 = p + 1;
+    const bool eneg = tb[e0] == '-';
+    if (tb[e0] == '-' || tb[e0] == '+') ++e0;
+    const uint32_t e1 = run_end(sm.dg, e0);
+    if (e1 == e0) return r;
+    // leading zeros do not count; beyond 17 significant digits the value
+    // saturates (lex_token stops growing it past 2^56, and q is clamped)
+    const uint32_t z = first_nonzero_digit<K>(sm, e0, e1);
+    e = e1 - z > 17 ? kExpCap : (int64_t)digits_before<K>(sm, (int)e1, (int)(e1 - z));
+    if (eneg) e = -e;
+    p = e1;
+  }
+  if (p != end) return r;
+  // significant digits: from the first nonzero one, the dot skipped
+  uint32_t nz = first_nonzero_digit<K>(sm, i0, b);
+  const bool in_int = nz < b;
+  if (!in_int) nz = first_nonzero_digit<K>(sm, f0, f1);
+  uint64_t w = 0;
+  int64_t dropped = 0;
+  bool nonzero_dropped = false;
+  if (in_int || nz < f1) {
+    const uint32_t n_int = in_int ? b - nz : 0;               // significant integer digits
+    const uint32_t n_frac = in_int ? nfrac : f1 - nz;         // significant fraction digits
+    const uint32_t nsig = n_int + n_frac;
+    const uint32_t take_int = n_int < 19 ? n_int : 19;
+    const uint32_t take_frac = nsig <= 19 ? n_frac : 19 - take_int;
+    const uint32_t fs = in_int ? f0 : nz;                     // first significant fraction digit
+    if (take_int) w = digits_before<K>(sm, (int)(nz + take_int), (int)take_int);
+    if (take_frac)
+      w = w * sm.pow10[take_frac] + digits_before<K>(sm, (int)(fs + take_frac), (int)take_frac);
+    if (nsig > 19) {
+      dropped = nsig - 19;
+      // dropped digits: the rest of the integer run, then the fraction run
+      if (take_int < n_int)
+        nonzero_dropped = first_nonzero_digit<K>(sm, nz + take_int, b) < b;
+      if (!nonzero_dropped)
+        nonzero_dropped = first_nonzero_digit<K>(sm, fs + take_frac, f1) < f1;
+    }
+  }
+  int64_t q = e - (int64_t)nfrac + dropped;
+  q = q < -100000 ? -100000 : (q > 100000 ? 100000 : q);
+  r.q = (int32_t)q;
+  r.w = w;
+  r.kind = nonzero_dropped ? kLexTruncated : kLexExact;
+  return r;
+}
+
 // Algorithm 1 (and w+1 for long significands) on a lexed token, the queue
 // append for undecided tokens, and the stores.  Returns the path counter.
 template <class F, bool kExt>
@@ -773,7 +890,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           }
           Lexed L;
           if (fl.code == kFastSlow) {
-            L = global ? lex_token<kExt>(gsrc, pos, P.flags) : lex_token<kExt>(lsrc, vpos, P.flags);
+            if (global)
+              L = lex_token<kExt>(gsrc, pos, P.flags);
+            else if (P.flags & (kFlagJson | kFlagInfNan | kFlagHex))
+              L = lex_token<kExt>(lsrc, vpos, P.flags);
+            else
+              L = long_lex<K>(sm, s, P.flags);
           } else {
             L.w = fl.w;
             L.q = fl.q;
