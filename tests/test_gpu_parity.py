@@ -303,6 +303,68 @@ def test_tokens_across_tile_ends(ffpmod, straddle_case, tile_k, block_kib):
         c.close()
 
 
+def _long_grammar_tokens(seed, n=3000):
+    """Tokens of 20-600 characters: digit strings with a dot anywhere (or
+    none), leading and trailing zeros, signs, exponents with leading zeros or
+    more than 17 significant digits, all-zero mantissas, and broken forms."""
+    rng = np.random.default_rng(seed)
+    toks = []
+    for _ in range(n):
+        nd = int(rng.integers(20, 500))
+        d = "".join(map(str, rng.integers(0, 10, nd).tolist()))
+        k = int(rng.integers(0, 8))
+        if k == 1:
+            d = "0" * int(rng.integers(1, 300)) + d
+        elif k == 2:
+            d = d + "0" * int(rng.integers(1, 300))
+        elif k == 3:
+            d = "0" * nd
+        dot = int(rng.integers(-1, len(d) + 1))
+        m = d if dot < 0 else d[:dot] + "." + d[dot:]
+        sign = ["", "-", "+"][int(rng.integers(0, 3))]
+        ek = int(rng.integers(0, 6))
+        if ek == 0:
+            ex = ""
+        elif ek == 1:
+            ex = "e%+d" % int(rng.integers(-400, 400))
+        elif ek == 2:
+            ex = "E" + "0" * int(rng.integers(1, 40)) + str(int(rng.integers(0, 400)))
+        elif ek == 3:
+            ex = "e-" + "".join(map(str, rng.integers(0, 10, int(rng.integers(17, 30))).tolist()))
+        elif ek == 4:
+            ex = "e" + str(int(rng.integers(0, 10))) * int(rng.integers(15, 19))
+        else:
+            ex = ["e", "e+", "e-", "ee5", "e5.", "x"][int(rng.integers(0, 6))]
+        tok = sign + m + ex
+        if rng.integers(0, 20) == 0:  # a stray byte somewhere
+            i = int(rng.integers(0, len(tok)))
+            tok = tok[:i] + "ab.-+"[int(rng.integers(0, 5))] + tok[i:]
+        toks.append(tok)
+    return toks
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_long_token_grammar(ffpmod, flags):
+    """The long-token lexer against the oracle on long valid and invalid
+    tokens, with and without FFP_REJECT_PLUS, mixed with short tokens."""
+    rng = np.random.default_rng(68 + flags)
+    toks = _long_grammar_tokens(69 + flags) + W.mixed_tokens(rng, 5000)
+    rng.shuffle(toks)
+    buf = W.join_tokens(toks)
+    c = ffpmod.Context(0, flags=flags)
+    try:
+        for fmt in ("f64", "f32"):
+            _log("case long grammar", flags, fmt, len(buf))
+            rc, n, bits, status = run_gpu(c, buf, fmt, offset=7)
+            wb, ws = parse_buffer(buf, fmt, flags=flags)
+            assert rc == len(wb) and n == len(wb)
+            bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                 (status[:n] != np.array(ws, dtype=np.uint8)))
+            assert bad.size == 0, (flags, fmt, [toks[i][:80] for i in bad[:3]])
+    finally:
+        c.close()
+
+
 def test_delimiter_set_and_flags(ffpmod):
     c = ffpmod.Context(0, delims=b",; \t\r\n", flags=ffpmod.FFP_REJECT_PLUS)
     try:
