@@ -39,10 +39,46 @@ constexpr int kFbWindow = kWave * 16;  // text bytes per wavefront step
 constexpr int kExpKeep = 18;           // significant exponent digits kept
 
 // Per-wavefront LDS of the fallback.
+// digits[] is 4-byte aligned with 8 bytes before it, so that the 8-digit
+// conversions below may read aligned words on either side of a run.
 struct FbLds {
-  uint8_t digits[kFallbackDigits + 8];  // significant digits, values 0..9
-  uint8_t edigits[kExpKeep + 6];        // significant exponent digits
+  alignas(4) uint8_t pad[8];
+  uint8_t digits[kFallbackDigits + 12];  // significant digits, values 0..9
+  uint8_t edigits[kExpKeep + 6];         // significant exponent digits
 };
+
+// Value of the n (0..8) digit values d[end - n .. end): two aligned words
+// around them, the unwanted leading bytes masked off, then four digits at a
+// time by byte dot products (weights 10/1, then 100), the first digit in the
+// low byte.
+__device__ __forceinline__ uint32_t fb_val4(uint32_t x) {
+  return __umul24(__builtin_amdgcn_udot4(x, 0x0000010Au, 0u, false), 100u) +
+         __builtin_amdgcn_udot4(x, 0x010A0000u, 0u, false);
+}
+
+__device__ __forceinline__ uint32_t fb_val8(const uint8_t* d, int end, int n) {
+  if (n <= 0) end = 8;        // nothing kept: any in-range words will do
+  const int A = end - 8 + 8;  // byte offset of d[end - 8] from d - 8 (>= 1 for n >= 1)
+  const uint32_t* W = reinterpret_cast<const uint32_t*>(d - 8);
+  const uint32_t w0 = W[A >> 2], w1 = W[(A >> 2) + 1], w2 = W[(A >> 2) + 2];
+  uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)A & 3u);
+  uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, (uint32_t)A & 3u);
+  const int drop = 8 - n;
+  const uint64_t keep = drop >= 8 ? 0ull : (~0ull << (8 * drop));
+  lo &= (uint32_t)keep;
+  hi &= (uint32_t)(keep >> 32);
+  return __umul24(fb_val4(lo), 10000u) + fb_val4(hi);
+}
+
+// Value of the digit values d[lo .. hi), hi - lo <= 19.
+__device__ __forceinline__ uint64_t fb_digits_value(const uint8_t* d, int lo, int hi) {
+  const int n = hi - lo;
+  const int n0 = n < 8 ? n : 8;
+  const int n1 = n < 16 ? (n > 8 ? n - 8 : 0) : 8;
+  const int n2 = n > 16 ? n - 16 : 0;
+  return (uint64_t)fb_val8(d, hi, n0) + (uint64_t)fb_val8(d, hi - 8, n1) * 100000000ull +
+         (uint64_t)fb_val8(d, hi - 16, n2) * 10000000000000000ull;
+}
 
 __device__ __forceinline__ int fb_lane() { return (int)(threadIdx.x & (kWave - 1)); }
 
@@ -331,7 +367,7 @@ __device__ void fb_decide(const uint8_t* text, uint64_t nbytes, uint64_t pos,
   if (t.nsig > 0) {
     const int nw = t.nsig < 19 ? (int)t.nsig : 19;
     uint64_t w = 0;
-    for (int i = 0; i < nw; ++i) w = w * 10 + lds->digits[i];
+    w = fb_digits_value(lds->digits, 0, nw);
     int kept = t.nsig < kFallbackDigits ? (int)t.nsig : kFallbackDigits;
     const int64_t q64 = t.e10 - t.nfrac + (t.nsig - nw);
     int64_t f64v = t.e10 - t.nfrac + (t.nsig - kept);
@@ -359,7 +395,7 @@ __device__ void fb_decide(const uint8_t* text, uint64_t nbytes, uint64_t pos,
       if (l < ng) {
         const int hi = kept - 19 * l;
         const int lo = hi - 19 > 0 ? hi - 19 : 0;
-        for (int i = lo; i < hi; ++i) grp = grp * 10 + lds->digits[i];
+        grp = fb_digits_value(lds->digits, lo, hi);
       }
       uint64_t X = l == 0 ? fb_read64(grp, ng - 1) : 0;
       for (int j = ng - 2; j >= 0; --j) X = fbig_mul_add(X, 10000000000000000000ull, fb_read64(grp, j));
