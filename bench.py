@@ -47,7 +47,9 @@ WORKLOAD_NAMES = {
     "config5": "config5-served-poisson",
     "copycal": "copy-calibration",
     "jsondoc": "jsondoc-10M-coordinates-binary64-plain",
+    "hexfloat": "hexfloat-10M-binary64-plain",
 }
+ROUND_FLAGS = {"nearest": 0x00, "zero": 0x10, "up": 0x20, "down": 0x30}
 OUT_NAMES = {"f64": "binary64", "f32": "binary32", "f16": "binary16", "bf16": "bfloat16"}
 METRIC = "GB/s input text + Mfloats/s parsed (bit-exact), batched/served vs plain; p50/p99"
 HBM_PEAK_GBS = 8000.0
@@ -56,9 +58,11 @@ KERNEL_SOURCES = ["paper_2101_11408_amd/csrc/ffp_kernels.hip",
                   "paper_2101_11408_amd/csrc/ffp_internal.h"]
 
 
-def out_name(wl, out):
-    """Workload name with the output format of a plain run."""
-    return WORKLOAD_NAMES[wl].replace("binary64", OUT_NAMES[out])
+def out_name(wl, out, rnd="nearest"):
+    """Workload name with the output format (and a directed rounding mode) of
+    a plain run."""
+    name = WORKLOAD_NAMES[wl].replace("binary64", OUT_NAMES[out])
+    return name if rnd == "nearest" else name + "-round-" + rnd
 
 
 def log(*a):
@@ -604,7 +608,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config4u",
-                             "config5", "copycal", "jsondoc"])
+                             "config5", "copycal", "jsondoc", "hexfloat"])
+    ap.add_argument("--round", default="nearest", choices=sorted(ROUND_FLAGS),
+                    help="plain workloads: rounding direction (FFP_ROUND_*)")
     ap.add_argument("--tokens", type=int, default=None)
     ap.add_argument("--nbuf", type=int, default=4096)
     ap.add_argument("--reduce", action="store_true",
@@ -659,29 +665,30 @@ def main():
         t0 = time.time()
         buf = W.config2(n=n)
         log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
-        rec = run_plain(args, buf, n, out_name(wl, args.out),
+        rec = run_plain(args, buf, n, out_name(wl, args.out, args.round),
                         "10M numbers in one %.1f MB buffer: 50%% uniform [0,1) shortest "
                         "digits, 25%% coordinates (6-15 fraction digits), 25%% random finite "
                         "bit patterns as %%.17e; %s output; one parse call per step"
                         % (len(buf) / 1e6, OUT_NAMES[args.out]), out_dtype=args.out,
-                        cpu=not args.no_cpu_baseline and args.out == "f64")
+                        cpu=not args.no_cpu_baseline and args.out == "f64" and args.round == "nearest",
+                        flags=ROUND_FLAGS[args.round])
     elif wl == "config1":
         n = args.tokens or 100_000
         buf = W.config1(n=n)
-        rec = run_plain(args, buf, n, out_name(wl, args.out),
+        rec = run_plain(args, buf, n, out_name(wl, args.out, args.round),
                         "100k uniform [0,1) doubles, shortest digits, positional, one "
                         "%.2f MB buffer; %s" % (len(buf) / 1e6, OUT_NAMES[args.out]),
-                        out_dtype=args.out)
+                        out_dtype=args.out, flags=ROUND_FLAGS[args.round])
     elif wl == "config3":
         n = args.tokens or 2_000_000
         t0 = time.time()
         buf = W.config3(n=n)
         log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
-        rec = run_plain(args, buf, n, out_name(wl, args.out),
+        rec = run_plain(args, buf, n, out_name(wl, args.out, args.round),
                         "2M hard cases (midpoints +-1 in the last of 20-800 digits, "
                         "subnormals, overflow, integers to 2^64, sign/zero variants) in one "
                         "%.1f MB buffer; %s" % (len(buf) / 1e6, OUT_NAMES[args.out]),
-                        out_dtype=args.out)
+                        out_dtype=args.out, flags=ROUND_FLAGS[args.round])
     elif wl == "config4":
         rec = run_batched(args, "mixed", WORKLOAD_NAMES[wl])
     elif wl == "jsondoc":
@@ -697,6 +704,19 @@ def main():
                         "%s" % (len(doc) / 1e6, nfeat, OUT_NAMES[args.out]),
                         out_dtype=args.out, delims=W.JSON_DELIMS, flags=2,
                         expect_ok=nfeat * 2000)
+    elif wl == "hexfloat":
+        import numpy as np
+        n = args.tokens or 10_000_000
+        t0 = time.time()
+        rng = np.random.default_rng(9)
+        x = rng.standard_normal(n) * np.power(10.0, rng.integers(-300, 300, n).astype(np.float64))
+        buf = ("\n".join(float(v).hex() for v in x.tolist()) + "\n").encode()
+        log("generated %d bytes in %.1f s" % (len(buf), time.time() - t0))
+        rec = run_plain(args, buf, n, out_name(wl, args.out, args.round),
+                        "10M random doubles (normal * 10^U[-300,300)) in their own hexadecimal "
+                        "form (Appendix C), one %.1f MB buffer; FFP_HEX; %s"
+                        % (len(buf) / 1e6, OUT_NAMES[args.out]), out_dtype=args.out,
+                        flags=8 | ROUND_FLAGS[args.round], expect_ok=n)
     elif wl == "config5":
         rec = run_served(args, WORKLOAD_NAMES[wl])
     elif wl == "copycal":
