@@ -558,10 +558,29 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
     r.code = kFastInvalid;
     return r;
   }
-  if (nint + nfrac > 19 || nexp > 8) return r;
-  const uint64_t iv = digits_before<K>(sm, (int)s + b, nint);
-  const uint64_t fv = digits_before<K>(sm, (int)s + f1, nfrac);
-  r.w = iv * sm.pow10[nfrac] + fv;
+  // Digits converted: all of them, except that when the integer part is
+  // empty or a single '0', up to 8 leading zeros of the fraction are skipped
+  // (values below 0.01 printed with 17 significant digits have 20 or more
+  // digits, but no more than 19 significant ones).
+  int ni = nint, nf = nfrac;
+  if (__any(nint + nfrac > 19)) {
+    if (nint + nfrac > 19 && (nint == 0 || (nint == 1 && tb[s + a] == '0'))) {
+      const int A = (int)s + f0 + TileSmem<K>::kPadFront;
+      const uint32_t* W = reinterpret_cast<const uint32_t*>(sm.text);
+      const uint32_t w0 = W[A >> 2], w1 = W[(A >> 2) + 1], w2 = W[(A >> 2) + 2];
+      // the 8 bytes from f0, first byte lowest; a zero byte is a '0'
+      const uint64_t x =
+          ((uint64_t)__builtin_amdgcn_alignbyte(w2, w1, (uint32_t)A & 3u) << 32 |
+           __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)A & 3u)) ^ 0x3030303030303030ull;
+      const int zf = x == 0 ? 8 : (int)(__builtin_ctzll(x) >> 3);  // < nfrac: nfrac > 18
+      ni = 0;
+      nf = nfrac - zf;
+    }
+  }
+  if (ni + nf > 19 || nexp > 8) return r;
+  const uint64_t iv = digits_before<K>(sm, (int)s + b, ni);
+  const uint64_t fv = digits_before<K>(sm, (int)s + f1, nf);
+  r.w = iv * sm.pow10[nf] + fv;
   int ev = 0;
   if (__any(has_e)) ev = (int)digits8_before<K>(sm, (int)s + e1, has_e ? nexp : 0);
   r.q = (es && cx1 == '-' ? -ev : ev) - nfrac;

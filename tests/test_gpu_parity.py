@@ -365,6 +365,47 @@ def test_long_token_grammar(ffpmod, flags):
         c.close()
 
 
+def _leading_zero_fraction_tokens(seed, n=6000):
+    """Short tokens (under 32 bytes) whose fraction starts with zeros and
+    whose digit count exceeds 19 while the significant digits may not: an
+    integer part that is empty, '0', '-0', '+0' or '00', 0-12 leading zeros,
+    then 1-20 digits, with or without an exponent."""
+    rng = np.random.default_rng(seed)
+    toks = []
+    while len(toks) < n:
+        ip = ["", "0", "-0", "+0", "00", "-", "1"][int(rng.integers(0, 7))]
+        z = int(rng.integers(0, 13))
+        d = "".join(map(str, rng.integers(0, 10, int(rng.integers(1, 21))).tolist()))
+        ex = ["", "e%d" % int(rng.integers(-30, 30)), "E+5", "e-300"][int(rng.integers(0, 4))]
+        tok = ip + "." + "0" * z + d + ex
+        if len(tok) < 32 and (ip not in ("", "-") or rng.integers(0, 4) == 0):
+            toks.append(tok)
+    return toks
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_leading_zero_fractions(ffpmod, flags):
+    """Fractions with leading zeros beyond 19 digits stay on the bitmap
+    lexer when their significant digits fit; parity with the oracle either
+    way, with and without FFP_JSON."""
+    rng = np.random.default_rng(90 + flags)
+    toks = _leading_zero_fraction_tokens(91 + flags) + W.mixed_tokens(rng, 4000)
+    rng.shuffle(toks)
+    buf = W.join_tokens(toks)
+    c = ffpmod.Context(0, flags=flags)
+    try:
+        for fmt in ("f64", "f32", "f16"):
+            _log("case leading zeros", flags, fmt, len(buf))
+            rc, n, bits, status = run_gpu(c, buf, fmt, offset=3)
+            wb, ws = parse_buffer(buf, fmt, flags=flags)
+            assert rc == len(wb) and n == len(wb)
+            bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                 (status[:n] != np.array(ws, dtype=np.uint8)))
+            assert bad.size == 0, (flags, fmt, [toks[i] for i in bad[:3]])
+    finally:
+        c.close()
+
+
 def test_delimiter_set_and_flags(ffpmod):
     c = ffpmod.Context(0, delims=b",; \t\r\n", flags=ffpmod.FFP_REJECT_PLUS)
     try:
