@@ -668,8 +668,12 @@ FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* tabl
     return d;
   }
   const int qi = L.q < kQMin ? kQMin : (L.q > kQMax ? kQMax : L.q);
-  const uint64_t thi = table[2 * (qi - kQMin)];
-  const uint64_t tlo = table[2 * (qi - kQMin) + 1];
+  // one 16-byte read of the entry (the table is 16-byte aligned)
+  struct alignas(16) Entry {
+    unsigned long long hi, lo;
+  };
+  const Entry ent = reinterpret_cast<const Entry*>(table)[qi - kQMin];
+  const uint64_t thi = ent.hi, tlo = ent.lo;
   bool ab;
   d.path = (L.q < kQMin || L.q > kQMax) ? kCntEarly : kCntOne;
   if (kExt && dir != kDirNearest) {

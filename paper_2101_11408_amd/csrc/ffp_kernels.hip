@@ -26,7 +26,7 @@
 
 namespace ffp {
 
-__device__ const unsigned long long g_table[FFP_TABLE_SIZE * 2] = {FFP_TABLE_ENTRIES};
+alignas(16) __device__ const unsigned long long g_table[FFP_TABLE_SIZE * 2] = {FFP_TABLE_ENTRIES};
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -498,6 +498,9 @@ __device__ __forceinline__ uint64_t digits_before(const TileSmem<K>& sm, int end
 
 constexpr uint32_t kFastOk = 0, kFastInvalid = 1, kFastSlow = 2;
 
+// Lexing modes of the parse kernel's instances (see k_parse).
+constexpr int kModePlain = 0, kModeGrammar = 1, kModeExt = 2;
+
 struct FastLex {
   uint64_t w;
   int32_t q;
@@ -511,8 +514,9 @@ struct FastLex {
 // converted up to eight at a time.  Tokens of 32 bytes or more, with more than
 // 19 mantissa digits or more than 8 exponent digits are left to the
 // byte-by-byte lexer (kFastSlow); for all others the result equals
-// lex_token's.
-template <int K>
+// lex_token's.  kGrammar: the grammar flags (FFP_JSON, FFP_INFNAN, FFP_HEX)
+// are honoured; without it they must be clear.
+template <int K, bool kGrammar>
 __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, uint32_t flags) {
   FastLex r;
   r.w = 0;
@@ -545,7 +549,7 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
   r.neg = c0 == '-';
   bool valid = end == L && nint + nfrac > 0 && (!has_e || nexp > 0) &&
                !(c0 == '+' && (flags & (kFlagRejectPlus | kFlagJson)));
-  if (flags & (kFlagJson | kFlagInfNan | kFlagHex)) {  // the same for every lane
+  if (kGrammar && (flags & (kFlagJson | kFlagInfNan | kFlagHex))) {  // the same for every lane
     const uint32_t ca = tb[s + a];  // first byte after the sign
     if (flags & kFlagJson)  // no ".5", no "1.", no leading zeros
       valid = valid && nint > 0 && (!dot || nfrac > 0) && !(nint > 1 && ca == '0');
@@ -736,11 +740,15 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
 
 // Four workgroups per CU (the LDS allows four): registers are kept within
 // 128.  kReduce: the call also keeps the minimum, maximum and count of the
-// values; kExt: hexadecimal tokens (flag FFP_HEX) and directed rounding are
-// compiled in.  Separate instances, so that the plain parse pays nothing for
-// either.
-template <int K, bool kSingle, bool kReduce, bool kExt>
+// values.  kMode: kModePlain lexes Section 4's grammar (FFP_REJECT_PLUS
+// aside, no grammar flag); kModeGrammar adds the JSON grammar and inf / nan
+// (FFP_JSON, FFP_INFNAN); kModeExt adds hexadecimal tokens (FFP_HEX) and the
+// directed rounding modes.  Separate instances, so that the plain parse pays
+// nothing for either: its register and branch budget is the tightest.
+template <int K, bool kSingle, bool kReduce, int kMode>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_parse(ParseParams P) {
+  constexpr bool kExt = kMode == kModeExt;
+  constexpr bool kGrammar = kMode != kModePlain;
   using S = TileSmem<K>;
   using Packed = typename S::Packed;
   __shared__ S sm;
@@ -903,7 +911,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           const bool global = j == global_j;
           FastLex fl;
           if (!global) {
-            fl = fast_lex<K>(sm, s, P.flags);
+            fl = fast_lex<K, kGrammar>(sm, s, P.flags);
           } else {
             fl.code = kFastSlow;
           }
@@ -911,7 +919,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           if (fl.code == kFastSlow) {
             if (global)
               L = lex_token<kExt>(gsrc, pos, P.flags);
-            else if (P.flags & (kFlagJson | kFlagInfNan | kFlagHex))
+            else if (kGrammar && (P.flags & (kFlagJson | kFlagInfNan | kFlagHex)))
               L = lex_token<kExt>(lsrc, vpos, P.flags);
             else
               L = long_lex<K>(sm, s, P.flags);
@@ -1048,9 +1056,9 @@ int parse_tile_bytes(int k) { return kThreads * kChunk * k; }
 template <int K>
 static hipError_t occ_k(bool single, int* blocks) {
   return single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      blocks, k_parse<K, true, false, false>, kThreads, 0)
+                      blocks, k_parse<K, true, false, kModePlain>, kThreads, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      blocks, k_parse<K, false, false, false>, kThreads, 0);
+                      blocks, k_parse<K, false, false, kModePlain>, kThreads, 0);
 }
 
 hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu) {
@@ -1090,20 +1098,24 @@ hipError_t launch_scan(const ScanParams& P, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int K, bool kSingle, bool kReduce>
+static void launch_parse_mode(const ParseParams& P, int grid, hipStream_t s) {
+  if (P.flags & (kFlagHex | kFlagRoundMask))
+    hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModeExt>), dim3(grid), dim3(kThreads), 0, s, P);
+  else if (P.flags & (kFlagJson | kFlagInfNan))
+    hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModeGrammar>), dim3(grid), dim3(kThreads), 0, s,
+                       P);
+  else
+    hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModePlain>), dim3(grid), dim3(kThreads), 0, s,
+                       P);
+}
+
 template <int K, bool kSingle>
 static hipError_t launch_parse_k(const ParseParams& P, int grid, hipStream_t s) {
-  const bool ext = (P.flags & (kFlagHex | kFlagRoundMask)) != 0;
-  if (P.reduce_out) {
-    if (ext)
-      hipLaunchKernelGGL((k_parse<K, kSingle, true, true>), dim3(grid), dim3(kThreads), 0, s, P);
-    else
-      hipLaunchKernelGGL((k_parse<K, kSingle, true, false>), dim3(grid), dim3(kThreads), 0, s, P);
-  } else {
-    if (ext)
-      hipLaunchKernelGGL((k_parse<K, kSingle, false, true>), dim3(grid), dim3(kThreads), 0, s, P);
-    else
-      hipLaunchKernelGGL((k_parse<K, kSingle, false, false>), dim3(grid), dim3(kThreads), 0, s, P);
-  }
+  if (P.reduce_out)
+    launch_parse_mode<K, kSingle, true>(P, grid, s);
+  else
+    launch_parse_mode<K, kSingle, false>(P, grid, s);
   return hipGetLastError();
 }
 

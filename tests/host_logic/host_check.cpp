@@ -19,7 +19,7 @@
 #include "ffp_device.h"
 #include "ffp_table.inc"
 
-static const unsigned long long kTable[FFP_TABLE_SIZE * 2] = {FFP_TABLE_ENTRIES};
+alignas(16) static const unsigned long long kTable[FFP_TABLE_SIZE * 2] = {FFP_TABLE_ENTRIES};
 
 template <class F>
 static void run(const std::vector<uint8_t>& buf, const ffp::DelimSet& ds, uint32_t flags,
