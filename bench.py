@@ -165,6 +165,7 @@ def base_record(args, value, ms, workload, config, dtype="u64"):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "spinup_ms": args.spinup_ms,
         "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
@@ -175,7 +176,21 @@ def base_record(args, value, ms, workload, config, dtype="u64"):
     }
 
 
-def timed_steps(torch, fn, steps, warmup):
+def spin_up(torch, fn, ms):
+    """Untimed calls for at least `ms` milliseconds of wall time, so that the
+    timed steps run at the GPU's steady clocks rather than during the clock
+    ramp after a process starts (a few warmup steps of this size take only
+    a millisecond or two)."""
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
+def timed_steps(torch, fn, steps, warmup, spinup_ms=0.0):
+    if spinup_ms > 0:
+        spin_up(torch, fn, spinup_ms)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -213,7 +228,7 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False, delim
     if expect_ok is not None:
         assert int((status[:n] == 0).sum()) == expect_ok
     ms = timed_steps(torch, lambda: ctx.parse_into(text, values, status, count, stream=stream),
-                     0, args.warmup)
+                     0, args.warmup, args.spinup_ms)
     ctx.timing(True)
     ctx.timing_read()
     ms = timed_steps(torch, lambda: ctx.parse_into(text, values, status, count, stream=stream),
@@ -293,7 +308,7 @@ def run_batched(args, kind, workload):
 
     # batched (one call) with the parse kernel timed
     ms_batch = timed_steps(torch, lambda: ctx.parse_batch(table.dev, table.n, total, stream),
-                           0, args.warmup)
+                           0, args.warmup, args.spinup_ms)
     ctx.timing(True)
     ctx.timing_read()
     ms_batch = timed_steps(torch, lambda: ctx.parse_batch(table.dev, table.n, total, stream),
@@ -310,7 +325,8 @@ def run_batched(args, kind, workload):
         ms_plain = ms_graph = ms_batch
     else:
         graph = ffp.BatchGraph(ctx, table, total)
-        ms_graph = timed_steps(torch, lambda: graph.launch(stream), args.steps, args.warmup)
+        ms_graph = timed_steps(torch, lambda: graph.launch(stream), args.steps, args.warmup,
+                               args.spinup_ms)
         res2 = table.download()
         assert [c for c, e in res2] == [c for c, e in res] and all(e == 0 for c, e in res2)
         graph.close()
@@ -606,6 +622,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--spinup-ms", type=float, default=200.0,
+                    help="untimed calls for this long before the warmup steps (GPU clock ramp)")
     ap.add_argument("--workload", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config4u",
                              "config5", "copycal", "jsondoc", "hexfloat"])

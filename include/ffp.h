@@ -282,7 +282,11 @@ int ffp_autotune_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t m
  * Timing of the dominant kernel.  When enabled, each parse call records HIP
  * events on its stream around the parse kernel (K-parse) only; the totals
  * accumulate until read.  ffp_timing_read synchronises on the last event and
- * returns the summed milliseconds and the number of timed launches.
+ * returns the summed milliseconds and the number of timed launches.  The
+ * events are created without the system-scope fence (timing only, so that
+ * recording them does not write back and invalidate the caches between the
+ * kernels): waiting on them does not make the call's results visible to the
+ * host; synchronise the stream for that.
  * ------------------------------------------------------------------------- */
 int ffp_timing_enable(ffp_ctx* ctx, int enable);
 int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches);

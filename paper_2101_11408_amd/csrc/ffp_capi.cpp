@@ -153,7 +153,11 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uin
       ev = ctx->ev_free.back();
       ctx->ev_free.pop_back();
     } else {
-      if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess)
+      // timing-only events: no system-scope fence (cache write-back and
+      // invalidation) at the record, which would otherwise slow down the
+      // kernels around it
+      if (hipEventCreateWithFlags(&ev.first, hipEventDisableSystemFence) != hipSuccess ||
+          hipEventCreateWithFlags(&ev.second, hipEventDisableSystemFence) != hipSuccess)
         return FFP_E_HIP;
     }
     if (hipEventRecord(ev.first, s) != hipSuccess) return FFP_E_HIP;
