@@ -258,7 +258,11 @@ void ffp_batch_graph_destroy(ffp_graph* g);
  * (1 .. the occupancy limit; 0 = the limit) and the block size in KiB
  * (4, 16 or 64; 0 = chosen per call: the largest block that still gives
  * every parse workgroup two blocks, so that small inputs spread over many
- * workgroups).  A call never uses tiles larger than its blocks. */
+ * workgroups).  A call never uses tiles larger than its blocks.  Until a
+ * schedule is set (ffp_set_tuning, ffp_autotune_batch or the FFP_TILE_K
+ * environment variable) the tile is chosen per call: 8 KiB for contexts
+ * without grammar or rounding flags and calls without a reduction, 16 KiB
+ * otherwise; ffp_get_tuning then reports the first choice. */
 typedef struct ffp_tuning {
     int32_t tile_k;
     int32_t blocks_per_cu;

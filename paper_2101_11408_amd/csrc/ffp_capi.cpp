@@ -80,13 +80,22 @@ struct CallShape {
   int grid;  // parse workgroups before clipping to the block count
 };
 
+// Tile of a call when the context has no fixed schedule: 8 KiB for the
+// plain instance without a reduction (compiled for five waves per SIMD),
+// 16 KiB for the others (four waves per SIMD either way, where the larger
+// tile halves the per-tile work).
+int auto_tile_k(const ffp_ctx* ctx, bool reduce) {
+  const bool plain = (ctx->flags & (FFP_JSON | FFP_INFNAN | FFP_HEX | FFP_ROUND_MASK)) == 0;
+  return plain && !reduce ? 2 : 4;
+}
+
 // The largest block (64, 16 or 4 KiB) that still gives every parse
 // workgroup two blocks; small inputs get small blocks (and tiles no larger
 // than a block) so that they spread over many workgroups.
-CallShape call_shape(const ffp_ctx* ctx, uint64_t bytes) {
+CallShape call_shape(const ffp_ctx* ctx, uint64_t bytes, bool reduce) {
   CallShape cs{};
-  int k = ctx->tile_k;
-  int bpc = ctx->blocks_per_cu;
+  int k = ctx->tile_auto ? auto_tile_k(ctx, reduce) : ctx->tile_k;
+  int bpc = ctx->tile_auto ? 0 : ctx->blocks_per_cu;
   auto grid_for = [&](int kk, int b) {
     const int lim = ctx->max_bpc[kk];
     if (b < 1 || b > lim) b = lim;
@@ -203,7 +212,7 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   job.block_begin = 0;
   job.dtype = dtype;
   job.job_id = 0;
-  const CallShape shape = call_shape(ctx, nbytes);
+  const CallShape shape = call_shape(ctx, nbytes, ctx->reduce_out != nullptr);
   // blocks start at the 16-byte boundary at or below d_text
   const uint64_t vbytes = nbytes ? nbytes + ((uintptr_t)d_text & 15u) : 0;
   const uint64_t nblocks = (vbytes + (1ull << shape.block_shift) - 1) >> shape.block_shift;
@@ -226,7 +235,7 @@ int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_tot
   // at least two jobs' worth of job table, so that grow() sizes it
   int rc = grow(ctx, max_total_bytes, njobs < 2 ? 2 : njobs);
   if (rc != FFP_SUCCESS) return rc;
-  const CallShape shape = call_shape(ctx, max_total_bytes);
+  const CallShape shape = call_shape(ctx, max_total_bytes, false);
   ffp::PrepParams pp{};
   pp.user = reinterpret_cast<ffp::UserJob*>(d_jobs);
   pp.njobs = njobs;
@@ -443,7 +452,10 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   }
   if (const char* k = getenv("FFP_TILE_K")) {
     const int v = atoi(k);
-    if (v == 1 || v == 2 || v == 4) ctx->tile_k = v;
+    if (v == 1 || v == 2 || v == 4) {
+      ctx->tile_k = v;
+      ctx->tile_auto = false;
+    }
   }
   ctx->blocks_per_cu = ctx->max_bpc[ctx->tile_k];
   ctx->fb_grid = ctx->num_cus * 4;
@@ -595,8 +607,8 @@ void ffp_batch_graph_destroy(ffp_graph* gr) {
 int ffp_get_tuning(ffp_ctx* ctx, ffp_tuning* out) {
   if (!ctx || !out) return FFP_E_ARG;
   memset(out, 0, sizeof *out);
-  out->tile_k = ctx->tile_k;
-  out->blocks_per_cu = ctx->blocks_per_cu;
+  out->tile_k = ctx->tile_auto ? auto_tile_k(ctx, false) : ctx->tile_k;
+  out->blocks_per_cu = ctx->tile_auto ? ctx->max_bpc[out->tile_k] : ctx->blocks_per_cu;
   out->block_kib = ctx->block_kib;
   return FFP_SUCCESS;
 }
@@ -608,6 +620,7 @@ int ffp_set_tuning(ffp_ctx* ctx, const ffp_tuning* t) {
   if (t->block_kib != 0 && t->block_kib != 4 && t->block_kib != 16 && t->block_kib != 64)
     return FFP_E_ARG;
   ctx->block_kib = t->block_kib;
+  ctx->tile_auto = false;
   ctx->tile_k = t->tile_k;
   ctx->blocks_per_cu = t->blocks_per_cu == 0 ? ctx->max_bpc[t->tile_k] : t->blocks_per_cu;
   return FFP_SUCCESS;
@@ -638,7 +651,10 @@ int ffp_autotune_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t m
   if (was_timing && ffp_timing_read(ctx, &ms0, &n0) != FFP_SUCCESS) return FFP_E_HIP;
   ctx->timing = true;
   double best = 1e30;
+  const bool was_auto = ctx->tile_auto;
+  const int was_k = ctx->tile_k, was_b = ctx->blocks_per_cu;
   int best_k = ctx->tile_k, best_b = ctx->blocks_per_cu;
+  ctx->tile_auto = false;  // the candidates below are fixed schedules
   for (int k : {1, 2, 4}) {
     std::vector<int> cands;
     for (int b = ctx->max_bpc[k]; b >= 1; b = (b > 2 ? b - 1 : b - 1)) cands.push_back(b);
@@ -657,6 +673,9 @@ int ffp_autotune_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t m
       }
       if (rc != FFP_SUCCESS) {
         ctx->timing = was_timing;
+        ctx->tile_auto = was_auto;
+        ctx->tile_k = was_k;
+        ctx->blocks_per_cu = was_b;
         return rc;
       }
       if (t_best < best) {
@@ -667,6 +686,7 @@ int ffp_autotune_batch(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t m
     }
   }
   ctx->timing = was_timing;
+  ctx->tile_auto = false;
   ctx->tile_k = best_k;
   ctx->blocks_per_cu = best_b;
   if (cache_path) {

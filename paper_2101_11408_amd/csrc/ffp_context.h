@@ -23,6 +23,7 @@ struct ffp_ctx {
   int num_cus = 0;
   std::string arch;
   int tile_k = 4;
+  bool tile_auto = true;         // tile_k chosen per call (see call_shape)
   int blocks_per_cu = 1;        // chosen schedule
   int block_kib = 0;            // 0: chosen per call from its size
   int max_bpc[5] = {0, 0, 0, 0, 0};  // occupancy limit per tile_k

@@ -738,15 +738,18 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
   return (int)d.path;
 }
 
-// Four workgroups per CU (the LDS allows four): registers are kept within
-// 128.  kReduce: the call also keeps the minimum, maximum and count of the
+// Registers: within 128 (four waves per SIMD; the LDS of a 16 KiB tile
+// allows four workgroups per CU), and within 96 for the plain and grammar
+// instances of 8 KiB and smaller tiles (five waves per SIMD; the extended
+// instances would spill).  kReduce: the call also keeps the minimum, maximum and count of the
 // values.  kMode: kModePlain lexes Section 4's grammar (FFP_REJECT_PLUS
 // aside, no grammar flag); kModeGrammar adds the JSON grammar and inf / nan
 // (FFP_JSON, FFP_INFNAN); kModeExt adds hexadecimal tokens (FFP_HEX) and the
 // directed rounding modes.  Separate instances, so that the plain parse pays
 // nothing for either: its register and branch budget is the tightest.
 template <int K, bool kSingle, bool kReduce, int kMode>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_parse(ParseParams P) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(K <= 2 && kMode != kModeExt ? 5 : 4))) void k_parse(ParseParams P) {
   constexpr bool kExt = kMode == kModeExt;
   constexpr bool kGrammar = kMode != kModePlain;
   using S = TileSmem<K>;
@@ -795,18 +798,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     uint64_t next_idx = P.block_prefix[blk] - P.block_prefix[job.block_begin];
     const GlobalSrc gsrc{job.text, nbytes, P.delim};
 
-    // The chunks of the next tile of the block are loaded into registers
-    // while the current tile's tokens are decided (software pipelining).
+    // A tile's chunks are loaded at the top of its iteration; the other
+    // workgroups on the CU hide the latency.  (Loading the next tile into
+    // registers during the token rounds held 4K registers through them and
+    // measured no faster.)
     uint4 pre[K];
-#pragma unroll
-    for (int c = 0; c < K; ++c)
-      pre[c] = load_chunk(vbase, bstart + (uint64_t)(c * kThreads + tid) * kChunk, align, vend,
-                          P.delim.byte);
     // the byte before the block, loaded with the block's first chunks
     const uint32_t block_prev = tid == 0 ? prev_nondelim(vbase, bstart, align, P.delim) : 0u;
     for (int t = 0; t < ntiles; ++t) {
       const uint64_t tile_start = bstart + (uint64_t)t * S::kBytes;  // virtual
       if (tile_start >= vend) break;
+#pragma unroll
+      for (int c = 0; c < K; ++c)
+        pre[c] = load_chunk(vbase, tile_start + (uint64_t)(c * kThreads + tid) * kChunk, align,
+                            vend, P.delim.byte);
       __syncthreads();  // LDS of the previous tile is consumed
       // -- store the tile to LDS and classify bytes ---------------------
       uint32_t ndm[K];
@@ -821,18 +826,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                                                 digit_word(v.z), digit_word(v.w));
       }
       const uint64_t next_start = tile_start + S::kBytes;
-      // pre[] takes the next tile of the block; at the block's end wave 0
-      // loads the extension (the 1 KiB after the tile) instead
-      const bool next_loaded = t + 1 < ntiles && next_start < vend;
+      // wave 0 loads the extension (the 1 KiB after the tile: the next
+      // tile's first chunks, or delimiters past the text), used if a token
+      // runs past the tile
       uint4 ext_v = make_uint4(0, 0, 0, 0);
-      if (next_loaded) {
-#pragma unroll
-        for (int c = 0; c < K; ++c)
-          pre[c] = load_chunk(vbase, next_start + (uint64_t)(c * kThreads + tid) * kChunk, align,
-                              vend, P.delim.byte);
-      } else if (tid < S::kExtChunks) {
+      if (tid < S::kExtChunks)
         ext_v = load_chunk(vbase, next_start + (uint64_t)tid * kChunk, align, vend, P.delim.byte);
-      }
       if (tid == 0 && t == 0) sm.prev_nd = block_prev;
       __syncthreads();
 
@@ -883,7 +882,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                                                               : ntok);
       if (straddle && nfit == ntok) {  // the last token is decided here: fill the extension
         if (tid < S::kExtChunks) {  // wave 0: chunk tid of the next tile
-          const uint4 v = next_loaded ? pre[0] : ext_v;
+          const uint4 v = ext_v;
           *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + S::kBytes + tid * kChunk]) = v;
           const uint32_t m = nondelim_mask16<kSingle>(v, drep, sm.delim_lut);
           sm.nd[S::kChunks + tid] = (uint16_t)m;
