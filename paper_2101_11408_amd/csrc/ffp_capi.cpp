@@ -80,14 +80,17 @@ struct CallShape {
   int grid;  // parse workgroups before clipping to the block count
 };
 
+// Whether a call launches the plain instance of the parse kernel without a
+// reduction (no grammar or rounding flag).
+bool plain_instance(const ffp_ctx* ctx, bool reduce) {
+  return (ctx->flags & (FFP_JSON | FFP_INFNAN | FFP_HEX | FFP_ROUND_MASK)) == 0 && !reduce;
+}
+
 // Tile of a call when the context has no fixed schedule: 8 KiB for the
 // plain instance without a reduction (compiled for five waves per SIMD),
 // 16 KiB for the others (four waves per SIMD either way, where the larger
 // tile halves the per-tile work).
-int auto_tile_k(const ffp_ctx* ctx, bool reduce) {
-  const bool plain = (ctx->flags & (FFP_JSON | FFP_INFNAN | FFP_HEX | FFP_ROUND_MASK)) == 0;
-  return plain && !reduce ? 2 : 4;
-}
+int auto_tile_k(const ffp_ctx* ctx, bool reduce) { return plain_instance(ctx, reduce) ? 2 : 4; }
 
 // The largest block (64, 16 or 4 KiB) that still gives every parse
 // workgroup two blocks; small inputs get small blocks (and tiles no larger
@@ -96,8 +99,10 @@ CallShape call_shape(const ffp_ctx* ctx, uint64_t bytes, bool reduce) {
   CallShape cs{};
   int k = ctx->tile_auto ? auto_tile_k(ctx, reduce) : ctx->tile_k;
   int bpc = ctx->tile_auto ? 0 : ctx->blocks_per_cu;
+  const bool plain = plain_instance(ctx, reduce);
   auto grid_for = [&](int kk, int b) {
-    const int lim = ctx->max_bpc[kk];
+    // resident workgroups of the instance this call launches
+    const int lim = plain ? ctx->max_bpc[kk] : ctx->max_bpc_wide[kk];
     if (b < 1 || b > lim) b = lim;
     return ctx->num_cus * (b < 1 ? 1 : b);
   };
@@ -447,8 +452,11 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   ctx->arch = prop.gcnArchName;
   for (int k : {1, 2, 4}) {
     int b = 0;
-    if (ffp::parse_occupancy(k, ctx->delim.single != 0, &b) != hipSuccess || b < 1) b = 1;
+    if (ffp::parse_occupancy(k, ctx->delim.single != 0, false, &b) != hipSuccess || b < 1) b = 1;
     ctx->max_bpc[k] = b;
+    int bw = 0;
+    if (ffp::parse_occupancy(k, ctx->delim.single != 0, true, &bw) != hipSuccess || bw < 1) bw = 1;
+    ctx->max_bpc_wide[k] = bw < b ? bw : b;
   }
   if (const char* k = getenv("FFP_TILE_K")) {
     const int v = atoi(k);

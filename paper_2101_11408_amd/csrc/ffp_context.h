@@ -26,7 +26,8 @@ struct ffp_ctx {
   bool tile_auto = true;         // tile_k chosen per call (see call_shape)
   int blocks_per_cu = 1;        // chosen schedule
   int block_kib = 0;            // 0: chosen per call from its size
-  int max_bpc[5] = {0, 0, 0, 0, 0};  // occupancy limit per tile_k
+  int max_bpc[5] = {0, 0, 0, 0, 0};  // occupancy limit per tile_k (plain instance)
+  int max_bpc_wide[5] = {0, 0, 0, 0, 0};  // the same for the other instances
   int fb_grid = 0;
 
   uint64_t* d_block_sum = nullptr;  // per-block counts, then their prefix

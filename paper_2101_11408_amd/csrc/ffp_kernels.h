@@ -9,8 +9,9 @@ namespace ffp {
 
 // Bytes per parse tile for tile multiplier k (1, 2 or 4).
 int parse_tile_bytes(int k);
-// Resident workgroups per CU of the parse kernel.
-hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu);
+// Resident workgroups per CU of the parse kernel: of the plain instance
+// without a reduction, or (wide) of the largest of the other instances.
+hipError_t parse_occupancy(int k, bool single_delim, bool wide, int* blocks_per_cu);
 
 hipError_t launch_prep(const PrepParams& P, hipStream_t s);
 hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipStream_t s);

@@ -739,9 +739,10 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
 }
 
 // Registers: within 128 (four waves per SIMD; the LDS of a 16 KiB tile
-// allows four workgroups per CU), and within 96 for the plain and grammar
-// instances of 8 KiB and smaller tiles (five waves per SIMD; the extended
-// instances would spill).  kReduce: the call also keeps the minimum, maximum and count of the
+// allows four workgroups per CU), and within 96 for the plain instance
+// without a reduction at 8 KiB and smaller tiles (five waves per SIMD; at
+// 96 the other instances spill to scratch inside the token loop).
+// kReduce: the call also keeps the minimum, maximum and count of the
 // values.  kMode: kModePlain lexes Section 4's grammar (FFP_REJECT_PLUS
 // aside, no grammar flag); kModeGrammar adds the JSON grammar and inf / nan
 // (FFP_JSON, FFP_INFNAN); kModeExt adds hexadecimal tokens (FFP_HEX) and the
@@ -749,7 +750,8 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
 // nothing for either: its register and branch budget is the tightest.
 template <int K, bool kSingle, bool kReduce, int kMode>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(K <= 2 && kMode != kModeExt ? 5 : 4))) void k_parse(ParseParams P) {
+__attribute__((amdgpu_waves_per_eu(K <= 2 && kMode == kModePlain && !kReduce ? 5 : 4))) void
+k_parse(ParseParams P) {
   constexpr bool kExt = kMode == kModeExt;
   constexpr bool kGrammar = kMode != kModePlain;
   using S = TileSmem<K>;
@@ -1052,19 +1054,24 @@ __global__ void k_reduce_final(FallbackParams P) {
 // ---------------------------------------------------------------------------
 int parse_tile_bytes(int k) { return kThreads * kChunk * k; }
 
-template <int K>
-static hipError_t occ_k(bool single, int* blocks) {
-  return single ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      blocks, k_parse<K, true, false, kModePlain>, kThreads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      blocks, k_parse<K, false, false, kModePlain>, kThreads, 0);
+template <int K, bool kSingle>
+static hipError_t occ_ks(bool wide, int* blocks) {
+  return wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    blocks, k_parse<K, kSingle, true, kModeExt>, kThreads, 0)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    blocks, k_parse<K, kSingle, false, kModePlain>, kThreads, 0);
 }
 
-hipError_t parse_occupancy(int k, bool single_delim, int* blocks_per_cu) {
+template <int K>
+static hipError_t occ_k(bool single, bool wide, int* blocks) {
+  return single ? occ_ks<K, true>(wide, blocks) : occ_ks<K, false>(wide, blocks);
+}
+
+hipError_t parse_occupancy(int k, bool single_delim, bool wide, int* blocks_per_cu) {
   switch (k) {
-    case 1: return occ_k<1>(single_delim, blocks_per_cu);
-    case 2: return occ_k<2>(single_delim, blocks_per_cu);
-    case 4: return occ_k<4>(single_delim, blocks_per_cu);
+    case 1: return occ_k<1>(single_delim, wide, blocks_per_cu);
+    case 2: return occ_k<2>(single_delim, wide, blocks_per_cu);
+    case 4: return occ_k<4>(single_delim, wide, blocks_per_cu);
     default: return hipErrorInvalidValue;
   }
 }

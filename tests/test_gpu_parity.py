@@ -715,3 +715,39 @@ def test_min_max_reduction(ffpmod, fmt):
         c.set_reduce(None)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("flags", [0, 2 | 4, 8 | 0x20])
+@pytest.mark.parametrize("reduce", [False, True])
+def test_instances_at_8k_tiles(ffpmod, flags, reduce):
+    """Every instance family (plain; JSON and inf / nan; hex and a directed
+    mode), with and without the reduction, on 8 KiB tiles set explicitly
+    (by default only the plain instance without a reduction runs there):
+    parity with the oracle, and the reduction's minimum, maximum and
+    count."""
+    rng = np.random.default_rng(120 + flags + reduce)
+    toks = W.mixed_tokens(rng, 30_000) + W.hard_tokens(rng, 600)
+    toks += ["inf", "-nan", "0x1.8p3", "-0x1p-1074", "1.", "01", "-0"]
+    rng.shuffle(toks)
+    buf = W.join_tokens(toks)
+    c = ffpmod.Context(0, flags=flags)
+    out = torch.full((3,), -1, dtype=torch.int64, device="cuda:0")
+    try:
+        c.set_tuning(2, 0, 0)
+        if reduce:
+            c.set_reduce(out)
+        for fmt in ("f64", "f32"):
+            _log("case 8k tiles", hex(flags), reduce, fmt)
+            rc, n, bits, status = run_gpu(c, buf, fmt, offset=5)
+            wb, ws = parse_buffer(buf, fmt, flags=flags)
+            assert rc == len(wb) and n == len(wb)
+            bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                 (status[:n] != np.array(ws, dtype=np.uint8)))
+            assert bad.size == 0, (hex(flags), reduce, fmt, [toks[i] for i in bad[:3]])
+            if reduce:
+                got = [int(x) & 0xFFFFFFFFFFFFFFFF for x in out.cpu().tolist()]
+                assert tuple(got) == _expected_minmax(wb, ws, fmt), (hex(flags), fmt)
+        if reduce:
+            c.set_reduce(None)
+    finally:
+        c.close()
