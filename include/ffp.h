@@ -262,7 +262,9 @@ void ffp_batch_graph_destroy(ffp_graph* g);
  * schedule is set (ffp_set_tuning, ffp_autotune_batch or the FFP_TILE_K
  * environment variable) the tile is chosen per call: 8 KiB for contexts
  * without grammar or rounding flags and calls without a reduction, 16 KiB
- * otherwise; ffp_get_tuning then reports the first choice. */
+ * otherwise, and 16 KiB for a plain call whose capacity allows at most one
+ * token per 64 bytes of text (long tokens); ffp_get_tuning then reports
+ * the first choice.  The schedule never changes results. */
 typedef struct ffp_tuning {
     int32_t tile_k;
     int32_t blocks_per_cu;

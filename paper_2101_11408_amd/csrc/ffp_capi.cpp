@@ -89,15 +89,21 @@ bool plain_instance(const ffp_ctx* ctx, bool reduce) {
 // Tile of a call when the context has no fixed schedule: 8 KiB for the
 // plain instance without a reduction (compiled for five waves per SIMD),
 // 16 KiB for the others (four waves per SIMD either way, where the larger
-// tile halves the per-tile work).
-int auto_tile_k(const ffp_ctx* ctx, bool reduce) { return plain_instance(ctx, reduce) ? 2 : 4; }
+// tile halves the per-tile work).  A call whose output capacity allows at
+// most one token per 64 bytes of text holds long tokens: an 8 KiB tile then
+// has too few of them to fill a round, and each round lasts as long as its
+// longest token, so such calls take 16 KiB tiles too (capacity 0: unknown).
+int auto_tile_k(const ffp_ctx* ctx, bool reduce, uint64_t bytes = 0, uint64_t capacity = 0) {
+  const bool long_tokens = capacity > 0 && bytes / capacity >= 64;
+  return plain_instance(ctx, reduce) && !long_tokens ? 2 : 4;
+}
 
 // The largest block (64, 16 or 4 KiB) that still gives every parse
 // workgroup two blocks; small inputs get small blocks (and tiles no larger
 // than a block) so that they spread over many workgroups.
-CallShape call_shape(const ffp_ctx* ctx, uint64_t bytes, bool reduce) {
+CallShape call_shape(const ffp_ctx* ctx, uint64_t bytes, bool reduce, uint64_t capacity = 0) {
   CallShape cs{};
-  int k = ctx->tile_auto ? auto_tile_k(ctx, reduce) : ctx->tile_k;
+  int k = ctx->tile_auto ? auto_tile_k(ctx, reduce, bytes, capacity) : ctx->tile_k;
   int bpc = ctx->tile_auto ? 0 : ctx->blocks_per_cu;
   const bool plain = plain_instance(ctx, reduce);
   auto grid_for = [&](int kk, int b) {
@@ -217,7 +223,7 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   job.block_begin = 0;
   job.dtype = dtype;
   job.job_id = 0;
-  const CallShape shape = call_shape(ctx, nbytes, ctx->reduce_out != nullptr);
+  const CallShape shape = call_shape(ctx, nbytes, ctx->reduce_out != nullptr, capacity);
   // blocks start at the 16-byte boundary at or below d_text
   const uint64_t vbytes = nbytes ? nbytes + ((uintptr_t)d_text & 15u) : 0;
   const uint64_t nblocks = (vbytes + (1ull << shape.block_shift) - 1) >> shape.block_shift;
