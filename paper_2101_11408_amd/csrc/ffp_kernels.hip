@@ -280,7 +280,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
   __shared__ uint64_t s_carry;
   const int tid = threadIdx.x;
   const uint64_t n = total_blocks_of(P.js);
-  if (tid == 0) s_carry = 0;
+  if (tid == 0) {
+    s_carry = 0;
+    // the call's device state starts clean (the parse kernel appends to the
+    // queue and raises error bits; the reduction starts from its identities)
+    P.st->queue_tail = 0;
+    P.st->error = 0;
+    P.st->red_min = ~0ull;
+    P.st->red_max = 0;
+    P.st->red_count = 0;
+  }
   for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * kScanPer) {
     uint64_t v[kScanPer];
     uint64_t sum = 0;
@@ -307,19 +316,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
     if (tid == 0) s_carry = carry + total;
   }
   __syncthreads();
-  if (tid == 0) {
-    P.block_sum[n] = s_carry;
-    P.st->queue_tail = 0;
-    P.st->error = 0;
-    P.st->red_min = ~0ull;
-    P.st->red_max = 0;
-    P.st->red_count = 0;
+  if (!P.js.jobs) {  // one job: its token count is the total
+    if (tid == 0) {
+      const uint64_t count = s_carry;
+      P.block_sum[n] = count;
+      *P.js.single.count_out = count;
+      if (P.js.single.err_out && count > P.js.single.capacity) *P.js.single.err_out = kErrCapacity;
+    }
+    return;
   }
+  if (tid == 0) P.block_sum[n] = s_carry;
   __syncthreads();
   // token count of every job: prefix at its end minus prefix at its start
-  const uint32_t nj = P.js.jobs ? P.js.njobs : 1;
+  const uint32_t nj = P.js.njobs;
   for (uint32_t j = tid; j < nj; j += kScanThreads) {
-    const JobDesc job = P.js.jobs ? P.js.jobs[j] : P.js.single;
+    const JobDesc job = P.js.jobs[j];
     const uint64_t b0 = job.block_begin, b1 = b0 + job_blocks(job, P.js.block_shift);
     const uint64_t count = P.block_sum[b1] - P.block_sum[b0];
     *job.count_out = count;
