@@ -424,6 +424,10 @@ struct TileSmem {
   // 256 chunks (a row holds at most 2048 starts)
   using Packed = typename std::conditional<(K <= 2), uint32_t, uint64_t>::type;
   unsigned long long pow10[20];
+  // digit-group masks: entry d keeps the low nibbles of bytes d..7 of an
+  // 8-byte window (its last 8 - d bytes), 0 for d >= 8; one LDS read
+  // instead of a 64-bit shift and selects per group
+  unsigned long long keep8[16];
   alignas(16) uint8_t text[kPadFront + kBytes + kExtBytes + kPadBack];
   uint16_t starts[kBytes / 2];
   // bit i of these bitmaps describes byte i of the tile (16 bits per chunk),
@@ -472,10 +476,9 @@ __device__ __forceinline__ uint32_t digits8_before(const TileSmem<K>& sm, int en
   const uint32_t w0 = W[A >> 2], w1 = W[(A >> 2) + 1], w2 = W[(A >> 2) + 2];
   uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)A & 3u);
   uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, (uint32_t)A & 3u);
-  const int drop = 8 - n;  // leading bytes that are not part of the run
-  const uint64_t keep = drop >= 8 ? 0ull : (~0ull << (8 * drop));
-  lo &= (uint32_t)keep & 0x0F0F0F0Fu;
-  hi &= (uint32_t)(keep >> 32) & 0x0F0F0F0Fu;
+  const uint64_t keep = sm.keep8[(8 - n) & 15];  // the 8 - n leading bytes dropped
+  lo &= (uint32_t)keep;
+  hi &= (uint32_t)(keep >> 32);
   return __umul24(value4(lo), 10000u) + value4(hi);
 }
 
@@ -486,8 +489,8 @@ __device__ __forceinline__ uint32_t digits4_before(const TileSmem<K>& sm, int en
   const uint32_t* W = reinterpret_cast<const uint32_t*>(sm.text);
   const uint32_t w0 = W[A >> 2], w1 = W[(A >> 2) + 1];
   const uint32_t x = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)A & 3u);
-  const uint32_t keep = n <= 0 ? 0u : (~0u << (8 * (4 - n)));
-  return value4(x & keep & 0x0F0F0F0Fu);
+  const uint32_t keep = (uint32_t)(sm.keep8[(8 - n) & 15] >> 32);
+  return value4(x & keep);
 }
 
 // Value of the n (0..19) digits ending before `end`; the wave skips groups
@@ -782,6 +785,7 @@ k_parse(ParseParams P) {
     for (int i = 0; i < tid; ++i) p *= 10;
     sm.pow10[tid] = p;
   }
+  if (tid < 16) sm.keep8[tid] = tid >= 8 ? 0ull : (~0ull << (8 * tid)) & 0x0F0F0F0F0F0F0F0Full;
   if (tid < S::kExtChunks + 8) {
     sm.nd[S::kChunks + tid] = 0;
     sm.dg[S::kChunks + tid] = 0;
