@@ -444,7 +444,9 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   if (!ctx) return FFP_E_NOMEM;
   ctx->device = hip_device;
   for (int i = 0; i < 4; ++i) ctx->delim.bits[i] = o.delim_set[i];
-  ctx->delim.single = members == 1 ? 1u : 0u;
+  // the single-delimiter classification assumes a byte below 0x80; other
+  // sets (and a lone byte at or above 0x80) use the 256-entry table
+  ctx->delim.single = members == 1 && first < 0x80 ? 1u : 0u;
   ctx->delim.byte = (uint32_t)first;
   ctx->flags = o.flags;
 

@@ -83,7 +83,7 @@ struct DeviceState {
 
 struct DelimSet {
   uint64_t bits[4];
-  uint32_t single;     // 1 if the set holds exactly one byte
+  uint32_t single;     // 1 if the set holds exactly one byte, below 0x80
   uint32_t byte;       // that byte (or any member, used as padding)
 };
 

@@ -148,17 +148,21 @@ __device__ __forceinline__ uint64_t job_blocks(const JobDesc& job, uint32_t shif
   return (vend + (1ull << shift) - 1) >> shift;
 }
 
-// High bit of each byte of x set for non-delimiter bytes (single delimiter
-// byte replicated in drep) / for ASCII digits; exact per byte (no carry or
-// borrow crosses a byte).
+// High bit of each byte of x set for non-delimiter bytes (a single
+// delimiter byte below 0x80, replicated in drep) / for ASCII digits.  The
+// low seven bits of each byte, after the xor, plus 0x7F (0x76) carry into
+// the byte's high bit when they are nonzero (10 or more); x's own high bit
+// marks the bytes at or above 0x80, which are neither the delimiter nor a
+// digit.  Exact per byte (no carry crosses a byte); three VALU operations
+// per word.
 __device__ __forceinline__ uint32_t nondelim_word(uint32_t x, uint32_t drep) {
-  const uint32_t y = x ^ drep;
-  return (((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y) & 0x80808080u;
+  const uint32_t t = ((x ^ drep) & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+  return (t | x) & 0x80808080u;
 }
 
 __device__ __forceinline__ uint32_t digit_word(uint32_t x) {
-  const uint32_t xh = x | 0x80808080u;
-  return (xh - 0x30303030u) & ~(xh - 0x3A3A3A3Au) & ~x & 0x80808080u;
+  const uint32_t t = ((x ^ 0x30303030u) & 0x7F7F7F7Fu) + 0x76767676u;
+  return ~(t | x) & 0x80808080u;
 }
 
 __device__ __forceinline__ uint32_t nondelim_word_lut(uint32_t x, const uint8_t* lut) {

@@ -751,3 +751,30 @@ def test_instances_at_8k_tiles(ffpmod, flags, reduce):
             c.set_reduce(None)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("delim", [b"\n", b"\x80", b"\xff"])
+def test_high_bytes_and_high_delimiters(ffpmod, delim):
+    """Bytes at or above 0x80 inside tokens (invalid tokens) and as the one
+    delimiter byte: the single-delimiter classification covers bytes below
+    0x80, a lone high delimiter takes the table path; parity either way."""
+    rng = np.random.default_rng(130 + delim[0])
+    toks = [t.encode() for t in W.mixed_tokens(rng, 20_000)]
+    high = [b"\x80", b"\xa0", b"\xb0", b"\xb9", b"\xc3\xa9", b"\xff", b"\x8a", b"\xaa"]
+    for i in rng.integers(0, len(toks), 800).tolist():
+        t = toks[i]
+        k = int(rng.integers(0, len(t) + 1))
+        toks[i] = t[:k] + high[int(rng.integers(0, len(high)))] + t[k:]
+    buf = delim.join(toks) + delim
+    c = ffpmod.Context(0, delims=delim)
+    try:
+        for fmt in ("f64", "f32"):
+            _log("case high bytes", delim, fmt)
+            rc, n, bits, status = run_gpu(c, buf, fmt)
+            wb, ws = parse_buffer(buf, fmt, delims=delim)
+            assert rc == len(wb) and n == len(wb)
+            assert np.array_equal(bits[:n], np.array(wb, dtype=NP_DT[fmt])), (delim, fmt)
+            assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8)), (delim, fmt)
+            assert (status[:n] == 1).sum() >= 500
+    finally:
+        c.close()
