@@ -172,14 +172,16 @@ __device__ __forceinline__ uint32_t nondelim_word_lut(uint32_t x, const uint8_t*
   return h;
 }
 
-// Gather the high bits of the bytes of four words into a 16-bit mask.
+// Gather the high bits of the bytes of four words into a 16-bit mask: byte
+// dot products with weights 1..128 put bytes 8..15 at bits 7..14 of `hi`;
+// shifted up by 8 it is the accumulator of the same for bytes 0..7.
 __device__ __forceinline__ uint32_t pack_high_bits(uint32_t h0, uint32_t h1, uint32_t h2,
                                                    uint32_t h3) {
-  const uint32_t lo = __builtin_amdgcn_udot4(
-      h1, 0x80402010u, __builtin_amdgcn_udot4(h0, 0x08040201u, 0u, false), false);
   const uint32_t hi = __builtin_amdgcn_udot4(
       h3, 0x80402010u, __builtin_amdgcn_udot4(h2, 0x08040201u, 0u, false), false);
-  return (lo >> 7) | ((hi >> 7) << 8);
+  const uint32_t all = __builtin_amdgcn_udot4(
+      h1, 0x80402010u, __builtin_amdgcn_udot4(h0, 0x08040201u, hi << 8, false), false);
+  return all >> 7;
 }
 
 // 16 bytes of virtual text [off, off+16) of a job: one aligned load inside the
@@ -604,7 +606,11 @@ __device__ __forceinline__ FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, u
   const uint64_t fv = digits_before<K>(sm, (int)s + f1, nf);
   r.w = iv * sm.pow10[nf] + fv;
   int ev = 0;
-  if (__any(has_e)) ev = (int)digits8_before<K>(sm, (int)s + e1, has_e ? nexp : 0);
+  if (__any(has_e)) {  // exponents of up to 4 digits in every lane: one 4-digit group
+    const int ne = has_e ? nexp : 0;
+    ev = __all(ne <= 4) ? (int)digits4_before<K>(sm, (int)s + e1, ne)
+                        : (int)digits8_before<K>(sm, (int)s + e1, ne);
+  }
   r.q = (es && cx1 == '-' ? -ev : ev) - nfrac;
   r.code = kFastOk;
   return r;
@@ -829,10 +835,20 @@ k_parse(ParseParams P) {
     for (int t = 0; t < ntiles; ++t) {
       const uint64_t tile_start = bstart + (uint64_t)t * S::kBytes;  // virtual
       if (tile_start >= vend) break;
+      if (tile_start >= align && tile_start + S::kBytes <= vend) {  // the same for every lane
+        // the whole tile lies inside the text: plain 16-byte loads
+        const uint8_t* tp = vbase + tile_start + (uint32_t)tid * kChunk;
 #pragma unroll
-      for (int c = 0; c < K; ++c)
-        pre[c] = load_chunk(vbase, tile_start + (uint64_t)(c * kThreads + tid) * kChunk, align,
-                            vend, P.delim.byte);
+        for (int c = 0; c < K; ++c) {
+          const u32x4 v = gload(reinterpret_cast<const u32x4*>(tp + c * kThreads * kChunk));
+          pre[c] = make_uint4(v.x, v.y, v.z, v.w);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+          pre[c] = load_chunk(vbase, tile_start + (uint64_t)(c * kThreads + tid) * kChunk, align,
+                              vend, P.delim.byte);
+      }
       __syncthreads();  // LDS of the previous tile is consumed
       // -- store the tile to LDS and classify bytes ---------------------
       uint32_t ndm[K];
