@@ -197,7 +197,9 @@ FFP_HD uint64_t alg1_rt(uint64_t w, int q, uint64_t thi, uint64_t tlo, const For
     if (m == 0) st = kStRange;
     return m;  // exponent field 0; m == 2^mant encodes the smallest normal
   }
-  if (zl <= 1 && (m & 1) && (m << (u + F.shift)) == zh) {
+  // an exact tie needs the low product word at 0 or 1: rare, so waves
+  // branch around the rest of the test
+  if (__builtin_expect(zl <= 1, 0) && (m & 1) && (m << (u + F.shift)) == zh) {
     if (F.tie_fallback) {
       abort = true;  // may be an exact midpoint
     } else if (!(m & 2) && q >= F.tie_lo && q <= F.tie_hi) {
