@@ -100,8 +100,11 @@ enum ffp_error {
 /* ---------------------------------------------------------------------------
  * Options.  delim_set is a 256-bit set of delimiter bytes: byte c is a
  * delimiter when bit (c & 63) of delim_set[c >> 6] is set.  It must be
- * non-empty and must not contain any byte of the grammar
- * (0-9 . e E + -).  Passing NULL for the options selects {'\n'} and flags 0.
+ * non-empty and must not contain any byte of the grammar the flags select:
+ * 0-9 . e E + - always, a-f A-F x X p P with FFP_HEX, and the letters of
+ * inf, infinity and nan in either case (a f i n t y A F I N T Y) with
+ * FFP_INFNAN (FFP_E_ARG otherwise).  Passing NULL for the options selects
+ * {'\n'} and flags 0.
  * ------------------------------------------------------------------------- */
 typedef struct ffp_options {
     uint64_t delim_set[4];
@@ -173,9 +176,13 @@ int ffp_parse_f32(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
 /* As above, then waits for the stream.  Returns the token count (>= 0), or a
  * negative ffp_error: FFP_E_CAPACITY when count > capacity (the first
  * `capacity` tokens are still written), FFP_E_QUEUE when the fallback queue
- * overflowed (impossible unless more than 65536 tokens hit the rare
- * inconclusive-product case of Algorithm 1), FFP_E_INTERNAL on a failed
- * device-side consistency check. */
+ * overflowed, FFP_E_INTERNAL on a failed device-side consistency check.
+ * The queue holds every token of more than 19 significant digits the
+ * buffer can contain (a token that reaches the fallback through the w / w+1
+ * test of Section 11 has at least 20 bytes) plus 65536 others; a token of at
+ * most 19 significant digits reaches it only in the inconclusive-product
+ * case of Algorithm 1 (Section 8), so an overflow needs more than 65536 such
+ * tokens in one call. */
 int64_t ffp_parse_f64_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
                            double* d_values, uint8_t* d_status, uint64_t capacity,
                            uint64_t* d_count, void* stream);
@@ -186,9 +193,13 @@ int64_t ffp_parse_f32_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
 /* The same parse with binary16 (IEEE half) or bfloat16 results: the 16-bit
  * encodings, nearest value with ties to even.  The paper names binary16
  * among the standard formats (Section 2) and writes Algorithm 1 for any
- * significand width; these calls use the same table and steps, and send
- * every product that may be an exact midpoint to the exact fallback (the
- * paper's tie windows are derived for binary64 and binary32 only). */
+ * significand width; these calls use the same table and steps.  The
+ * paper's tie windows are derived for binary64 and binary32 only: here a
+ * product that may be an exact midpoint is decided exactly when the product
+ * is exact (q in [0, 27]) or 5^-q divides w (q in [-27, -1], the value is
+ * then (w / 5^-q) * 2^q), and goes to the exact fallback otherwise, which a
+ * token of at most 19 significant digits reaches only in the inconclusive-
+ * product case. */
 int ffp_parse_f16(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
                   uint16_t* d_values, uint8_t* d_status, uint64_t capacity,
                   uint64_t* d_count, void* stream);
@@ -417,14 +428,18 @@ int ffp_server_wait(ffp_server* srv, uint64_t ticket, ffp_result* out);
 
 /* Copies min(count, max_count) values and status bytes of a done request to
  * dst_values / dst_status (device or pinned host memory; either may be
- * NULL), stream-ordered on `stream`.  FFP_E_BUSY if the request is not done. */
+ * NULL), stream-ordered on `stream`.  FFP_E_BUSY if the request is not done.
+ * The request may be released right after this call, without waiting for
+ * the stream: the server keeps its memory out of reuse until the copies
+ * queued here have completed. */
 int ffp_server_copy_result(ffp_server* srv, uint64_t ticket, void* dst_values,
                            uint8_t* dst_status, uint64_t max_count, void* stream);
 
 /* Frees the request's memory.  A request still waiting in the queue is
  * cancelled (never launched, counted in `cancelled`); one that is running is
- * detached: its memory is freed when it completes.  Either way its ticket is
- * forgotten now. */
+ * detached: its memory is freed when it completes.  A done request whose
+ * results are still being copied (ffp_server_copy_result) keeps its memory
+ * until those copies complete.  Either way its ticket is forgotten now. */
 int ffp_server_release(ffp_server* srv, uint64_t ticket);
 
 int ffp_server_stats_read(ffp_server* srv, ffp_server_stats* out);

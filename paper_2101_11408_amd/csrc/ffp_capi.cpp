@@ -36,8 +36,16 @@ struct DeviceGuard {
   }
 };
 
-bool is_grammar_byte(int c) {
-  return (c >= '0' && c <= '9') || c == '.' || c == 'e' || c == 'E' || c == '+' || c == '-';
+// Bytes a token of the grammar selected by `flags` may contain: such a byte
+// cannot be a delimiter (the lexers would read across it).
+bool is_grammar_byte(int c, uint32_t flags) {
+  if ((c >= '0' && c <= '9') || c == '.' || c == 'e' || c == 'E' || c == '+' || c == '-')
+    return true;
+  const int l = c | 0x20;
+  if ((flags & FFP_HEX) && ((l >= 'a' && l <= 'f') || l == 'x' || l == 'p')) return true;
+  if ((flags & FFP_INFNAN) && (l == 'a' || l == 'f' || l == 'i' || l == 'n' || l == 't' || l == 'y'))
+    return true;
+  return false;
 }
 
 template <class T>
@@ -359,6 +367,7 @@ int ctx_clone(const ffp_ctx* src, ffp_ctx** out) {
   o.flags = src->flags;
   const int rc = ffp_create(src->device, &o, out);
   if (rc != FFP_SUCCESS) return rc;
+  (*out)->tile_auto = src->tile_auto;
   (*out)->tile_k = src->tile_k;
   (*out)->blocks_per_cu = src->blocks_per_cu;
   (*out)->block_kib = src->block_kib;
@@ -433,7 +442,7 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   int members = 0, first = -1;
   for (int c = 0; c < 256; ++c) {
     if ((o.delim_set[c >> 6] >> (c & 63)) & 1) {
-      if (is_grammar_byte(c)) return FFP_E_ARG;
+      if (is_grammar_byte(c, o.flags)) return FFP_E_ARG;
       if (first < 0) first = c;
       ++members;
     }

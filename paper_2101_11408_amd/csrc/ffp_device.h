@@ -55,8 +55,11 @@ struct F32 {
 // the round-half-up subnormal step above rest on the paper's proofs for
 // binary64 and binary32 (a short decimal is never an exact midpoint outside
 // the windows, nor among subnormals); for binary16 that fails (2^-25 has 18
-// significant digits), so every product that may be an exact midpoint goes
-// to the exact fallback instead (kTieFallback).
+// significant digits).  For these formats a product that may be an exact
+// midpoint (kTieFallback) is decided exactly where that is cheap -- q in
+// [0, 27], where the product is exact, and q in [-27, -1] with 5^-q dividing
+// w, where the value is (w / 5^-q) * 2^q -- and goes to the exact fallback
+// otherwise.
 struct F16 {
   using bits_t = uint16_t;
   static constexpr int kMant = 10;
@@ -201,7 +204,16 @@ FFP_HD uint64_t alg1_rt(uint64_t w, int q, uint64_t thi, uint64_t tlo, const For
   // branch around the rest of the test
   if (__builtin_expect(zl <= 1, 0) && (m & 1) && (m << (u + F.shift)) == zh) {
     if (F.tie_fallback) {
-      abort = true;  // may be an exact midpoint
+      // For q in [0, 27] the entry is 5^q itself and the product is exact:
+      // the bits below the rounding bit decide (all zero: an exact tie).
+      // Elsewhere the product only approximates the value; q in [-27, -1]
+      // with 5^-q dividing w is decided exactly by the caller, the rest goes
+      // to the exact fallback.
+      if (q >= 0 && q <= 27) {
+        if (zl == 0 && !(m & 2)) m -= 1;
+      } else {
+        abort = true;
+      }
     } else if (!(m & 2) && q >= F.tie_lo && q <= F.tie_hi) {
       m -= 1;  // exact tie with an even lower neighbour: do not round up
     }
@@ -260,6 +272,21 @@ FFP_HD uint32_t round_dir(uint32_t flags, uint32_t neg) {
 //   q > 55         the entry is truncated too: Z in [z, z+2);
 //   q < 0          the entry is a rounded-up reciprocal (or the truncation of
 //                  one): Z in (z-1, z+2).
+// Whether 5^k divides w (1 <= k <= 27), with the quotient in n: n = w times
+// the inverse of 5^k modulo 2^64 is the quotient exactly when n * 5^k does
+// not overflow and gives back w.
+FFP_HD bool exact_div_pow5(uint64_t w, int k, uint64_t& n) {
+  uint64_t p5 = 1, inv = 1;
+  for (int i = 0; i < k; ++i) {
+    p5 *= 5;
+    inv *= 0xCCCCCCCCCCCCCCCDull;  // 5^-1 mod 2^64
+  }
+  n = w * inv;
+  uint64_t hi, lo;
+  mul_64x64(n, p5, hi, lo);
+  return hi == 0 && lo == w;
+}
+
 // v is exactly representable only if its odd part, a multiple of 5^q for
 // q > 0, has at most 53 bits, so never for q >= 23; for q < 0 only if 5^-q
 // divides w.  Let R be the bits of z below the last kept significand bit.
@@ -312,18 +339,9 @@ FFP_HD uint64_t alg1_dir_rt(uint64_t w, int q, uint64_t thi, uint64_t tlo, const
   } else if (q > 55) {
     abort = rtop;
   } else if (q < 0) {
-    if ((rzero || rtop) && q >= -27) {
-      // divisible by 5^-q?  n = w * (5^-q)^-1 mod 2^64 is the quotient if so
-      uint64_t p5 = 1, inv = 1;
-      for (int k = 0; k < -q; ++k) {
-        p5 *= 5;
-        inv *= 0xCCCCCCCCCCCCCCCDull;  // 5^-1 mod 2^64
-      }
-      const uint64_t n = w0 * inv;
-      uint64_t hi, lo;
-      mul_64x64(n, p5, hi, lo);
-      if (hi == 0 && lo == w0) return round_exact(n, q, false, F, away ? kDirAway : kDirTruncate, st);
-    }
+    uint64_t n;
+    if ((rzero || rtop) && q >= -27 && exact_div_pow5(w0, -q, n))
+      return round_exact(n, q, false, F, away ? kDirAway : kDirTruncate, st);
     abort = rzero || rtop;
   }
   if (away && inexact) ++m;
@@ -693,6 +711,14 @@ FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* tabl
     }
   } else {
     d.bits = alg1_rt(L.w, L.q, thi, tlo, fmt, ab, d.status);
+    uint64_t n;
+    if (fmt.tie_fallback && ab && L.kind == kLexExact && L.q < 0 && L.q >= -27 &&
+        exact_div_pow5(L.w, -L.q, n)) {
+      // binary16 / bfloat16: a possible midpoint with w * 10^q = n * 2^q
+      // exactly, rounded directly
+      d.bits = round_exact(n, L.q, false, fmt, kDirNearest, d.status);
+      ab = false;
+    }
     d.fallback = ab;
     if (L.kind == kLexTruncated) {
       bool ab2;

@@ -76,6 +76,9 @@ struct Req {
   uint32_t batch_jobs = 0;
   ReqState state = kQueued;
   bool detached = false;
+  // copies of the results queued by ffp_server_copy_result on callers'
+  // streams: the arena range is not reused before they complete
+  std::vector<hipEvent_t> copies;
 };
 
 struct Slot {
@@ -109,6 +112,8 @@ struct ffp_server {
   ffp::Arena arena;
   std::deque<Req*> queue;
   std::unordered_map<uint64_t, Req*> reqs;
+  // released requests whose result copies are still in flight
+  std::vector<Req*> deferred;
   uint64_t next_ticket = 1;
   uint64_t epoch = 0;  // bumped by every event that can unblock admission
   bool stopping = false;
@@ -126,6 +131,35 @@ struct ffp_server {
   void free_req(Req* r) {
     if (r->offset != kNoOffset) arena.release(r->offset, r->need);
     r->offset = kNoOffset;
+  }
+
+  // Whether every result copy of r has completed; completed events are
+  // destroyed (caller holds mu).
+  static bool copies_done(Req* r) {
+    size_t k = 0;
+    for (hipEvent_t e : r->copies) {
+      if (hipEventQuery(e) == hipErrorNotReady) r->copies[k++] = e;
+      else (void)hipEventDestroy(e);
+    }
+    r->copies.resize(k);
+    return k == 0;
+  }
+
+  // Frees the ranges of released requests whose copies have completed
+  // (caller holds mu); returns whether any are still waiting.
+  bool drain_deferred() {
+    size_t k = 0;
+    for (Req* r : deferred) {
+      if (copies_done(r)) {
+        free_req(r);
+        delete r;
+        ++epoch;
+      } else {
+        deferred[k++] = r;
+      }
+    }
+    deferred.resize(k);
+    return k != 0;
   }
 
   // Admits requests from the head of the queue for one batch (caller holds
@@ -276,6 +310,11 @@ struct ffp_server {
         }
       }
       std::unique_lock<std::mutex> lk(mu);
+      if (!deferred.empty()) {
+        const uint64_t e0 = epoch;
+        busy = drain_deferred() || busy;
+        progressed = progressed || epoch != e0;
+      }
       if (stopping && !busy) break;
       if (progressed) continue;
       if (busy) {
@@ -445,31 +484,39 @@ int ffp_server_wait(ffp_server* srv, uint64_t ticket, ffp_result* out) {
 int ffp_server_copy_result(ffp_server* srv, uint64_t ticket, void* dst_values,
                            uint8_t* dst_status, uint64_t max_count, void* stream) {
   if (!srv) return FFP_E_ARG;
-  const void* src_v = nullptr;
-  const uint8_t* src_s = nullptr;
-  uint64_t n = 0, vsize = 8;
-  {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->reqs.find(ticket);
-    if (it == srv->reqs.end()) return FFP_E_ARG;
-    const Req* r = it->second;
-    if (r->state != kDone) return FFP_E_BUSY;
-    n = std::min(r->count, max_count);
-    vsize = value_bytes(r->dtype);
-    src_v = r->d_values;
-    src_s = r->d_status;
-  }
-  if (n == 0) return FFP_SUCCESS;
+  // The copies and the event that marks their end are queued under the
+  // lock, so that a release from another thread sees the event and keeps
+  // the range out of the allocator until the copies have run.
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return FFP_E_ARG;
+  Req* r = it->second;
+  if (r->state != kDone) return FFP_E_BUSY;
+  const uint64_t n = std::min(r->count, max_count);
+  if (n == 0 || (!dst_values && !dst_status)) return FFP_SUCCESS;
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(srv->device);
+  const hipStream_t s = (hipStream_t)stream;
   int rc = FFP_SUCCESS;
-  if (dst_values && hipMemcpyAsync(dst_values, src_v, n * vsize, hipMemcpyDefault,
-                                   (hipStream_t)stream) != hipSuccess)
+  if (dst_values && hipMemcpyAsync(dst_values, r->d_values, n * value_bytes(r->dtype),
+                                   hipMemcpyDefault, s) != hipSuccess)
     rc = FFP_E_HIP;
   if (rc == FFP_SUCCESS && dst_status &&
-      hipMemcpyAsync(dst_status, src_s, n, hipMemcpyDefault, (hipStream_t)stream) != hipSuccess)
+      hipMemcpyAsync(dst_status, r->d_status, n, hipMemcpyDefault, s) != hipSuccess)
     rc = FFP_E_HIP;
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    ev = nullptr;
+    rc = FFP_E_HIP;
+  } else if (hipEventRecord(ev, s) != hipSuccess) {
+    // the copies (if queued) cannot be tracked: wait for them here
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev);
+    ev = nullptr;
+    rc = FFP_E_HIP;
+  }
+  if (ev) r->copies.push_back(ev);
   if (prev >= 0) (void)hipSetDevice(prev);
   return rc;
 }
@@ -483,8 +530,12 @@ int ffp_server_release(ffp_server* srv, uint64_t ticket) {
     Req* r = it->second;
     srv->reqs.erase(it);
     if (r->state == kDone) {
-      srv->free_req(r);
-      delete r;
+      if (ffp_server::copies_done(r)) {
+        srv->free_req(r);
+        delete r;
+      } else {
+        srv->deferred.push_back(r);  // the dispatcher frees it after the copies
+      }
     } else if (r->state == kQueued) {
       srv->queue.erase(std::find(srv->queue.begin(), srv->queue.end(), r));
       delete r;
@@ -583,8 +634,22 @@ void ffp_server_destroy(ffp_server* srv) {
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(srv->device);
-  for (auto& e : srv->reqs) delete e.second;
+  for (auto& e : srv->reqs) {
+    for (hipEvent_t ev : e.second->copies) {
+      (void)hipEventSynchronize(ev);
+      (void)hipEventDestroy(ev);
+    }
+    delete e.second;
+  }
   srv->reqs.clear();
+  for (Req* r : srv->deferred) {
+    for (hipEvent_t ev : r->copies) {
+      (void)hipEventSynchronize(ev);
+      (void)hipEventDestroy(ev);
+    }
+    delete r;
+  }
+  srv->deferred.clear();
   srv->queue.clear();
   srv->destroy_slots();
   if (srv->d_arena) (void)hipFree(srv->d_arena);

@@ -5,8 +5,11 @@ the library.  PyTorch provides device memory and streams.  If the library has
 not been built, importing the binding raises -- there is no CPU fallback.
 """
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "lib", "libffp.so")
@@ -144,6 +147,35 @@ _SIGNATURES = {
 
 _lib = None
 
+# Live handles, closed by an exit hook before the interpreter tears down its
+# modules: a finalizer that ran during that teardown (or after the HIP
+# runtime's own exit handlers) would call into HIP too late.  Servers are
+# closed first, then graphs, then the contexts they were made from.
+_live = {"server": weakref.WeakSet(), "graph": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+
+
+def _close_all():
+    for kind in ("server", "graph", "ctx"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+atexit.register(_close_all)
+
+
+def _finalize(obj):
+    """__del__ body: close unless the interpreter is already shutting down
+    (the exit hook has closed every live handle by then)."""
+    if sys.is_finalizing():
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
+
 
 def load(path: str = LIB_PATH):
     """Load libffp.so (once) and declare the C-ABI prototypes."""
@@ -242,6 +274,7 @@ class Context:
     def __init__(self, device: int = 0, delims: bytes = b"\n", flags: int = 0):
         self.device = device
         self.handle = ffp_create(device, delims, flags)
+        _live["ctx"].add(self)
 
     def close(self):
         if self.handle:
@@ -249,10 +282,7 @@ class Context:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
     def reserve(self, nbytes: int):
         check(load().ffp_reserve(self.handle, nbytes), "ffp_reserve")
@@ -390,6 +420,7 @@ class BatchGraph:
                                             max_total_bytes, ctypes.byref(out)),
               "ffp_batch_graph_create")
         self.handle = out
+        _live["graph"].add(self)
 
     def launch(self, stream=None):
         check(load().ffp_batch_graph_launch(self.handle, _stream_handle(stream)),
@@ -401,10 +432,7 @@ class BatchGraph:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
 
 # ---------------------------------------------------------------------------
@@ -433,6 +461,7 @@ class Server:
         check(load().ffp_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(out)),
               "ffp_server_create")
         self.handle = out
+        _live["server"].add(self)
 
     def submit_ptr(self, ptr, nbytes, on_device, dtype=DTYPE_F64, arrival_ns=0):
         """Submit raw memory; returns the ticket or raises FFPError."""
@@ -455,6 +484,14 @@ class Server:
         r = ffp_result()
         check(load().ffp_server_wait(self.handle, ticket, ctypes.byref(r)), "wait")
         return r
+
+    def copy_result(self, ticket, values, status, stream=None):
+        """ffp_server_copy_result into caller tensors (device or pinned host),
+        stream-ordered on `stream`; the request may be released right after."""
+        n = min(values.numel(), status.numel())
+        check(load().ffp_server_copy_result(self.handle, ticket, values.data_ptr(),
+                                            status.data_ptr(), n, _stream_handle(stream)),
+              "copy_result")
 
     def result_tensors(self, ticket, device, stream=None):
         """Copies a done request's values and status into new device tensors."""
@@ -506,7 +543,4 @@ class Server:
             self.handle = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)

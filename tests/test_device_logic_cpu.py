@@ -129,8 +129,8 @@ def test_exact_ties_near_one(host_check):
 
 
 def test_half_formats(host_check):
-    """binary16 and bfloat16 through the same logic (exact-midpoint candidates
-    go to the fallback)."""
+    """binary16 and bfloat16 through the same logic; long tokens just above
+    or below a midpoint (w and w + 1 round differently) go to the fallback."""
     rng = np.random.default_rng(48)
     toks = W.mixed_tokens(rng, 20_000) + W.hard_tokens(rng, 1000)
     toks += ["65504", "65519.99", "65520", "5.9604644775390625e-8", "2.98023223876953125e-8",
@@ -140,10 +140,46 @@ def test_half_formats(host_check):
     toks += [str(int(v)) for v in rng.integers(0, 70_000, 5000)]
     toks += ["%.*f" % (int(k), float(x)) for k, x in zip(rng.integers(0, 8, 5000),
                                                          rng.random(5000) * 1000)]
+    toks += ["%d.%s1" % (v, "0" * int(z)) for v, z in zip(range(2049, 2200, 2), rng.integers(18, 30, 76))]
+    toks += ["%d.%s1" % (v, "0" * int(z)) for v, z in zip(range(257, 400, 2), rng.integers(18, 30, 72))]
     buf = W.join_tokens(toks)
     for fmt in ("f16", "bf16"):
         nfb = check(host_check, buf, fmt, "half")
         assert nfb > 0
+
+
+def _half_ties(rng, mant, emin, n):
+    """Exact midpoints between neighbouring values of a format with `mant`
+    stored significand bits and smallest normal exponent `emin`, written
+    with at most 19 significant digits: integers, w * 10^q with 5^-q
+    dividing w, and subnormal midpoints."""
+    toks = []
+    while len(toks) < n:
+        if rng.random() < 0.15:  # between subnormals: (2k + 1) * 2^(emin - mant - 1)
+            num, e = 2 * int(rng.integers(0, 2 ** mant)) + 1, emin - mant - 1
+        else:
+            num = 2 * int(rng.integers(2 ** mant, 2 ** (mant + 1))) + 1
+            e = int(rng.integers(emin - mant, 16)) - 1
+        if e >= 0:
+            toks.append(str(num << e))
+        else:
+            w = num * 5 ** -e
+            if w < 10 ** 19:
+                toks.append("%de%d" % (w, e))
+    return toks
+
+
+def test_half_format_short_ties_inline(host_check):
+    """binary16 / bfloat16 midpoints of up to 19 significant digits are
+    decided without the exact fallback (q in [0, 27]: exact product; q in
+    [-27, -1]: 5^-q divides w), and rounded to even like the oracle."""
+    rng = np.random.default_rng(53)
+    for fmt, mant, emin in (("f16", 10, -14), ("bf16", 7, -126)):
+        toks = _half_ties(rng, mant, emin, 20_000)
+        toks += [str(v) for v in range(2 ** (mant + 1) + 1, 2 ** (mant + 2), 2)]
+        buf = W.join_tokens(toks)
+        nfb = check(host_check, buf, fmt, "half-ties")
+        assert nfb == 0, (fmt, nfb)
 
 
 def _flag_tokens(seed):

@@ -260,3 +260,68 @@ def test_batch_directed_rounding(ffpmod, pool):
         check_jobs(pool, table, values, statuses, spans, "round-down", flags=0x30)
     finally:
         c.close()
+
+
+def _check_against(pool, table, values, statuses, spans, want, label):
+    """Every job's count, error, value bits and status against precomputed
+    oracle results."""
+    host, _ = pool
+    res = table.download()
+    for i, ((st, ln), (count, err), (wb, ws)) in enumerate(zip(spans, res, want)):
+        assert err == 0, (label, i, err)
+        assert count == len(wb), (label, i, count, len(wb))
+        n = len(wb)
+        if n == 0:
+            continue
+        fmt = FMT_OF[values[i].dtype]
+        ib, npb = INT_OF[fmt]
+        got = values[i][:n].view(ib).cpu().numpy().view(npb)
+        gs = statuses[i][:n].cpu().numpy()
+        bad = np.flatnonzero((got != np.array(wb, dtype=npb)) | (gs != np.array(ws, dtype=np.uint8)))
+        assert bad.size == 0, (label, i, fmt, ln, int(bad[0]))
+
+
+@pytest.mark.parametrize("block_kib,tile_k", [(64, 4), (64, 2), (16, 4)])
+def test_batch_4096_jobs_large_blocks(ffpmod, block_kib, tile_k):
+    """The shape of the 4096-buffer workloads: 4096 jobs, blocks of 64 KiB
+    walked in several tiles (and 16 KiB blocks of one 16 KiB tile), jobs
+    from empty to several blocks long, some starting inside a token; the
+    batched call and replays of its captured graph, every job against the
+    oracle."""
+    from oracle_par import parse_many
+    rng = np.random.default_rng(81)
+    toks = W.mixed_tokens(rng, 200_000) + W.hard_tokens(rng, 1500)
+    rng.shuffle(toks)
+    host = W.join_tokens(toks)
+    pool = (host, torch.frombuffer(bytearray(host), dtype=torch.uint8).to("cuda:0"))
+    n = 4096
+    sizes = W.lognormal_sizes(rng, n, 6000, 1.5, 1, 400_000)
+    sizes[:6] = [0, 1, 17, 65536, 65536 + 16, 3 * 65536 - 5]
+    kinds = [torch.float64, torch.float32, torch.float16, torch.bfloat16]
+    dtypes = [kinds[int(k)] for k in rng.choice(4, n, p=[0.7, 0.2, 0.05, 0.05])]
+    table, values, statuses, spans = build_jobs(ffpmod, pool, sizes, None, 82, dtypes)
+    want = parse_many([host[st:st + ln] for st, ln in spans],
+                      [FMT_OF[v.dtype] for v in values])
+    _log("4096 jobs", table.total_bytes, "bytes, blocks", block_kib, "KiB, tile_k", tile_k)
+    c = ffpmod.Context(0)
+    graph = None
+    try:
+        c.set_tuning(tile_k, 0, block_kib)
+        c.parse_batch(table.dev, table.n, table.total_bytes)
+        torch.cuda.synchronize()
+        assert c.last_device_error() == 0
+        _check_against(pool, table, values, statuses, spans, want, "batch")
+        graph = ffpmod.BatchGraph(c, table, table.total_bytes)
+        for rep in range(3):
+            for s in statuses:
+                s.fill_(255)
+            table.upload()  # counts and errors back to zero
+            _ = torch.arange(1 << 20, device="cuda:0").sum().item()  # eager work between
+            graph.launch()
+            torch.cuda.synchronize()
+            _log("graph replay", rep)
+            _check_against(pool, table, values, statuses, spans, want, "graph-%d" % rep)
+    finally:
+        if graph is not None:
+            graph.close()
+        c.close()

@@ -179,6 +179,25 @@ def test_block_sizes(ffpmod, ragged_blocks_case, block_kib, tile_k):
             assert np.array_equal(bits[:n], np.array(wb, dtype=NP_DT[fmt])), (block_kib, tile_k,
                                                                               fmt)
             assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8))
+        # the same text as three jobs of one batched call (cut inside tokens)
+        dev = torch.frombuffer(bytearray(buf), dtype=torch.uint8).to("cuda:0")
+        cuts = [0, len(buf) // 3, 2 * len(buf) // 3 + 7, len(buf)]
+        texts = [dev[a:b] for a, b in zip(cuts, cuts[1:])]
+        fmts = ["f64", "f32", "f64"]
+        vals = [torch.empty(t.numel() // 2 + 1, dtype=TORCH_DT[f], device="cuda:0")
+                for t, f in zip(texts, fmts)]
+        sts = [torch.full((t.numel() // 2 + 1,), 255, dtype=torch.uint8, device="cuda:0")
+               for t in texts]
+        table = ffpmod.JobTable(texts, vals, sts, "cuda:0")
+        c.parse_batch(table.dev, table.n, len(buf))
+        torch.cuda.synchronize()
+        for j, ((count, err), (a, b), f) in enumerate(zip(table.download(), zip(cuts, cuts[1:]),
+                                                          fmts)):
+            wb, ws = parse_buffer(buf[a:b], f)
+            assert err == 0 and count == len(wb), (block_kib, tile_k, j, count, err)
+            got = vals[j][:count].view(INT_DT[f]).cpu().numpy().view(NP_DT[f])
+            assert np.array_equal(got, np.array(wb, dtype=NP_DT[f])), (block_kib, tile_k, j)
+            assert np.array_equal(sts[j][:count].cpu().numpy(), np.array(ws, dtype=np.uint8))
     finally:
         c.close()
 
@@ -425,6 +444,55 @@ def test_delimiter_set_and_flags(ffpmod):
         assert (status[:n] == 1).sum() >= 20000 // 97
     finally:
         c.close()
+
+
+def test_grammar_bytes_rejected_as_delimiters(ffpmod):
+    """A delimiter may not be a byte that a token of the selected grammar can
+    contain: hexadecimal letters, x and p under FFP_HEX, the letters of inf,
+    infinity and nan under FFP_INFNAN."""
+    bad = [(b"p", ffpmod.FFP_HEX), (b"x", ffpmod.FFP_HEX), (b"\nA", ffpmod.FFP_HEX),
+           (b"n", ffpmod.FFP_INFNAN), (b"Y", ffpmod.FFP_INFNAN), (b"\na", ffpmod.FFP_INFNAN),
+           (b"e", 0), (b"-", 0)]
+    for delims, flags in bad:
+        with pytest.raises(ffpmod.FFPError) as e:
+            ffpmod.Context(0, delims=delims, flags=flags)
+        assert e.value.code == ffpmod.FFP_E_ARG, (delims, flags)
+    for delims, flags in [(b"p", 0), (b"n", ffpmod.FFP_HEX), (b"x", ffpmod.FFP_INFNAN),
+                          (b"g", ffpmod.FFP_HEX | ffpmod.FFP_INFNAN)]:
+        c = ffpmod.Context(0, delims=delims, flags=flags)
+        try:
+            buf = delims[:1].join([b"1.5", b"-2", b"7e3"])
+            rc, n, bits, status = run_gpu(c, buf, "f64")
+            wb, ws = parse_buffer(buf, "f64", delims=delims, flags=flags)
+            assert n == len(wb) == 3 and list(map(int, bits[:n])) == wb, (delims, flags)
+        finally:
+            c.close()
+
+
+def test_half_format_short_ties(ctx, ffpmod):
+    """More than 200k exact binary16 / bfloat16 midpoints of few digits in one
+    call: decided in-line (no fallback), rounded to even like the oracle."""
+    rng = np.random.default_rng(57)
+    for fmt, mant, emin in (("f16", 10, -14), ("bf16", 7, -126)):
+        toks = [str(v) for v in range(2 ** (mant + 1) + 1, 2 ** (mant + 2), 2)]
+        # between subnormals: (2k + 1) * 2^(emin - mant - 1)
+        sub = 5 ** (mant + 1 - emin)
+        toks += ["%de%d" % ((2 * k + 1) * sub, emin - mant - 1) for k in range(40)
+                 if (2 * k + 1) * sub < 10 ** 19]
+        while len(toks) < 220_000:
+            num = 2 * int(rng.integers(2 ** mant, 2 ** (mant + 1))) + 1
+            e = int(rng.integers(max(emin - mant, -24), 12)) - 1
+            if e >= 0:
+                toks.append(str(num << e))
+            elif num * 5 ** -e < 10 ** 19:
+                toks.append("%de%d" % (num * 5 ** -e, e))
+        buf = W.join_tokens(toks)
+        ctx.counters(True)
+        ctx.counters_read()
+        n = compare_full(ctx, buf, fmt, "short-ties")
+        cnt = ctx.counters_read()
+        ctx.counters(False)
+        assert n == len(toks) and cnt["fallback"] == 0, (fmt, cnt)
 
 
 def test_path_counters(ctx, ffpmod):

@@ -293,3 +293,39 @@ def test_replay_trace(ctx, ffpmod, pool, reference):
     assert (out["t_done_ns"] >= out["t_launch_ns"]).all()
     assert (out["t_launch_ns"] >= out["t_arrive_ns"]).all()
     assert st["completed"] == len(reqs)
+
+
+def test_release_right_after_copy_result(ctx, ffpmod, pool):
+    """copy_result queues the copies on the caller's stream; releasing the
+    request right away (no host synchronisation) must not let a later
+    request reuse its memory before those copies ran.  The caller's stream
+    is held back by a spin kernel while later requests run."""
+    host, dev, _ = pool
+    ln = 120_000
+    srv = ffpmod.Server(ctx, hbm_budget_bytes=256 << 20, max_batch_bytes=4 << 20, streams=1)
+    side = torch.cuda.Stream()
+    try:
+        for k in range(3):
+            st = 10_000 * k
+            wb, ws = parse_buffer(host[st:st + ln], "f64")
+            t = srv.submit_ptr(dev[st:].data_ptr(), ln, True, ffpmod.DTYPE_F64)
+            r = srv.wait(t)
+            assert r.err == 0 and r.count == len(wb)
+            vals = torch.empty(r.count, dtype=torch.float64).pin_memory()
+            stat = torch.empty(r.count, dtype=torch.uint8).pin_memory()
+            with torch.cuda.stream(side):
+                torch.cuda._sleep(20_000_000)  # a few milliseconds
+            srv.copy_result(t, vals, stat, stream=side)
+            srv.release(t)
+            # requests of other text that would take the same memory
+            for j in range(4):
+                o = 500_000 + 37 * j + 50_000 * k
+                t2 = srv.submit_ptr(dev[o:].data_ptr(), ln, True, ffpmod.DTYPE_F64)
+                assert srv.wait(t2).err == 0
+                srv.release(t2)
+            side.synchronize()
+            got = vals.view(torch.int64).numpy().view(np.uint64)
+            assert np.array_equal(got, np.array(wb, dtype=np.uint64)), k
+            assert np.array_equal(stat.numpy(), np.array(ws, dtype=np.uint8)), k
+    finally:
+        srv.close()
