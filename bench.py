@@ -1,37 +1,46 @@
 """Benchmark: exact decimal -> binary64/binary32 parsing on one MI355X.
 
-Default workload (config2): 10M numbers in one ~198 MB buffer (50% uniform
-[0,1) shortest digits, 25% coordinates with 6-15 fraction digits, 25% random
-finite bit patterns as %.17e) parsed to binary64 by the plain single-buffer
-entry point.  One step = one ffp_parse_f64 call (count, scan, parse and
-fallback kernels) over the whole buffer, text already resident in HBM.
+Default workload (config4u, the HBM target run): 4096 independent buffers with
+lognormal sizes (median 256 KiB, sigma 1.5, 1 KiB - 16 MiB; about 3.06 GB,
+far above the 256 MB Infinity Cache), filled with config-1-format text
+(uniform [0,1) doubles, shortest round-trip digits, newline-separated),
+parsed to binary64.  One step = one replay of the captured batched graph
+(job-table, count, scan, parse and fallback kernels over all 4096 buffers),
+text already resident in HBM.  The same buffers are also parsed with one
+batched call per step and with one plain call per buffer (the comparison
+point), and every output of the three forms is compared.  A short served
+run (config 5's arrivals at 2k-20k requests/s, fewer requests per rate)
+adds p50/p99/p99.9 latency of the continuous-batching server against one
+launch per request.
 
 Other workloads (--workload):
   config1   100k uniform [0,1) shortest digits, one 1.93 MB buffer (latency)
-  config3   2M hard cases (long midpoints, subnormals, overflow ...), binary64
-  config4   4096 buffers, lognormal sizes (median 256 KiB, 1 KiB - 16 MiB),
-            mixed formats; plain (one call per buffer) vs batched vs graph
-  config4u  the same buffer sizes filled with config-1-format text (about
-            3 GB, far above the 256 MB Infinity Cache): the HBM target run
+  config2   10M numbers, one 198 MB buffer: 50% uniform shortest digits, 25%
+            coordinates with 6-15 fraction digits, 25% %.17e of random bits
+  config3   2M hard cases (long midpoints, subnormals, overflow ...)
+  config4   4096 buffers as config4u, filled with config-2's mix of formats
   config5   served requests: Poisson open-loop arrivals at several rates,
             sizes lognormal (median 64 KiB, 512 B - 8 MiB), 90% binary64 /
             10% binary32, 1% hard cases, under a 32 GiB HBM budget; the
-            continuous-batching server vs the plain one-launch-per-request
-            server on the same arrivals, text on the device and in pinned
-            host memory (H2D copy counted); p50/p99/p99.9 latency and GB/s
+            continuous-batching server vs one launch per request, text on
+            the device and in pinned host memory (H2D copy counted)
+  jsondoc, hexfloat   widened rows (JSON document, hexadecimal tokens)
+  copycal   a plain streaming kernel of known size (counter calibration)
 
-Prints one JSON line.  `roofline` reports the parse kernel's algorithmic
-bytes (text read once + value + 1-byte status per token) over its average
-duration measured with HIP events on the launch stream; `cpu_baseline` times
-the CPU oracle on a bounded sample of the same text (config2 only).
+Prints one JSON line.  `roofline`: the parse kernel's algorithmic bytes
+(text read once + value + 1-byte status per token) over its average
+duration measured with HIP events on the launch stream, against 8 TB/s and
+against a streaming copy measured in the same run.  `cpu_baseline`: the CPU
+oracle timed over the workload's distinct text on the machine's CPU share; the
+same oracle results are compared with every GPU output (`parity`).
 """
 
 import argparse
 import hashlib
-import re
 import json
 import multiprocessing as mp
 import os
+import re
 import sys
 import time
 
@@ -51,11 +60,15 @@ WORKLOAD_NAMES = {
 }
 ROUND_FLAGS = {"nearest": 0x00, "zero": 0x10, "up": 0x20, "down": 0x30}
 OUT_NAMES = {"f64": "binary64", "f32": "binary32", "f16": "binary16", "bf16": "bfloat16"}
+VALUE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 METRIC = "GB/s input text + Mfloats/s parsed (bit-exact), batched/served vs plain; p50/p99"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2101_11408_amd/csrc/ffp_kernels.hip",
                   "paper_2101_11408_amd/csrc/ffp_device.h",
                   "paper_2101_11408_amd/csrc/ffp_internal.h"]
+# worker processes for host-side work: the CPU share of one GPU on the
+# measurement boxes
+MAX_WORKERS = 16
 
 
 def out_name(wl, out, rnd="nearest"):
@@ -91,60 +104,237 @@ def load_traffic(workload: str):
     return ent.get("bytes_per_launch")
 
 
-# ---------------------------------------------------------------------------
-# CPU oracle baseline
-# ---------------------------------------------------------------------------
-_SAMPLE = None
+def workers() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(MAX_WORKERS, n))
 
 
-def _oracle_slice(bounds):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------------------
+# Tokens of a text (numpy; no parsing): spans of the runs of non-delimiters
+# ---------------------------------------------------------------------------
+
+def token_spans(text: bytes, delims: bytes = b"\n"):
+    import numpy as np
+    arr = np.frombuffer(text, dtype=np.uint8)
+    lut = np.zeros(256, dtype=bool)
+    lut[list(delims)] = True
+    nd = ~lut[arr]
+    if nd.size == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    prev = np.concatenate([[False], nd[:-1]])
+    nxt = np.concatenate([nd[1:], [False]])
+    return np.flatnonzero(nd & ~prev), np.flatnonzero(nd & ~nxt) + 1
+
+
+class PoolIndex:
+    """Token spans of a pool of text from which buffers or requests are cut.
+    A slice [a, b) of the pool holds the pool's tokens that lie wholly inside
+    it, plus at most one cut token at each end (bytes of a pool token that
+    the slice starts or ends inside of)."""
+
+    def __init__(self, pool: bytes):
+        self.pool = pool
+        self.starts, self.ends = token_spans(pool)
+
+    def slice(self, a: int, b: int):
+        """(k0, k1, head, tail): pool tokens k0..k1-1 lie inside [a, b);
+        head / tail are the cut tokens before / after them (bytes or None)."""
+        import numpy as np
+        s, e = self.starts, self.ends
+        k0 = int(np.searchsorted(s, a, side="left"))   # first token starting at or after a
+        k1 = int(np.searchsorted(e, b, side="right"))  # tokens ending at or before b
+        head = tail = None
+        if k0 > 0 and e[k0 - 1] > a:  # a token that starts before a and ends after it
+            head = self.pool[a:min(int(e[k0 - 1]), b)] or None
+        if k1 < len(s) and a <= s[k1] < b:  # a token that starts inside and ends after b
+            tail = self.pool[int(s[k1]):b]
+        if k1 < k0:  # the slice lies inside one token: it is the head
+            k1 = k0
+        return k0, k1, head, tail
+
+
+# ---------------------------------------------------------------------------
+# The cpu_baseline leg: the CPU oracle over the workload's distinct text,
+# timed, on worker processes; its results are what the GPU outputs are
+# compared with (parity).  The only part of this file that runs the oracle.
+# ---------------------------------------------------------------------------
+_SHARED = {}
+
+
+def _oracle_chunk(args):
     from oracle import parse_buffer
-    a, b = bounds
-    bits, st = parse_buffer(_SAMPLE[a:b], "f64")
-    return len(bits)
+    import numpy as np
+    a, b, fmt = args
+    bits, st = parse_buffer(_SHARED["text"][a:b], fmt, delims=_SHARED["delims"],
+                            flags=_SHARED["flags"])
+    return np.array(bits, dtype=np.uint64), np.array(st, dtype=np.uint8)
 
 
-def cpu_baseline(buf: bytes, sample_tokens: int):
-    global _SAMPLE
-    end = 0
-    for _ in range(sample_tokens):
-        nxt = buf.find(b"\n", end)
-        if nxt < 0:
-            end = len(buf)
-            break
-        end = nxt + 1
-    _SAMPLE = buf[:end]
-    cores = max(1, min(16, os.cpu_count() or 1))
-    step = max(1, end // (cores * 4))
+def _oracle_tokens(args):
+    from oracle import parse_token
+    import numpy as np
+    toks, fmt = args
+    out = [parse_token(t, fmt, _SHARED["flags"]) for t in toks]
+    return (np.array([b for b, _ in out], dtype=np.uint64),
+            np.array([s for _, s in out], dtype=np.uint8))
+
+
+def cpu_baseline_leg(text: bytes, fmts, extra_tokens=(), delims=b"\n", flags=0, what=""):
+    """Times the oracle over every token of `text` (for each output format
+    in `fmts`) and over `extra_tokens` (cut tokens of slices), on the box's
+    CPU share.  Returns (cpu_baseline record, {fmt: (bits, status)} for the
+    text's tokens, {fmt: (bits, status)} for the extra tokens)."""
+    import numpy as np
+    _SHARED.update(text=text, delims=delims, flags=flags)
+    nw = workers()
+    # chunks cut at delimiters, several per worker
+    nchunk = max(1, min(64 * nw, len(text) // 4096 or 1))
     bounds, a = [], 0
-    while a < end:
-        b = min(end, a + step)
-        nl = _SAMPLE.find(b"\n", b)
-        b = end if nl < 0 else nl + 1
-        bounds.append((a, b))
+    lut = set(delims)
+    for k in range(1, nchunk + 1):
+        b = len(text) if k == nchunk else max(a, len(text) * k // nchunk)
+        while b < len(text) and text[b] not in lut:
+            b += 1
+        if b > a:
+            bounds.append((a, b))
         a = b
+    extra = list(extra_tokens)
     ctx = mp.get_context("fork")
-    t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        n = sum(pool.map(_oracle_slice, bounds))
-    dt = time.perf_counter() - t0
-    return {
-        "value": round(end / dt / 1e9, 6),
+    res_text, res_extra, secs = {}, {}, {}
+    with ctx.Pool(nw) as pool:
+        for fmt in fmts:
+            t0 = time.perf_counter()
+            parts = pool.map(_oracle_chunk, [(a, b, fmt) for a, b in bounds], chunksize=1)
+            secs[fmt] = time.perf_counter() - t0
+            res_text[fmt] = (np.concatenate([p[0] for p in parts]) if parts else
+                             np.zeros(0, np.uint64),
+                             np.concatenate([p[1] for p in parts]) if parts else
+                             np.zeros(0, np.uint8))
+            step = max(1, len(extra) // (4 * nw) + 1)
+            eparts = pool.map(_oracle_tokens, [(extra[i:i + step], fmt)
+                                               for i in range(0, len(extra), step)])
+            res_extra[fmt] = (np.concatenate([p[0] for p in eparts]) if eparts else
+                              np.zeros(0, np.uint64),
+                              np.concatenate([p[1] for p in eparts]) if eparts else
+                              np.zeros(0, np.uint8))
+    f0 = fmts[0]
+    ntok = len(res_text[f0][0])
+    dt = secs[f0]
+    rec = {
+        "value": round(len(text) / dt / 1e9, 6),
         "unit": "GB/s",
-        "cores": cores,
+        "cores": nw,
         "kind": "oracle",
-        "sample": "first %d tokens (%.1f MB) of the same buffer, %d worker processes; "
-                  "%.3f Mfloats/s, %.2f s wall" % (n, end / 1e6, cores, n / dt / 1e6, dt),
+        "sample": "%s: %d tokens (%.1f MB), %s output, %d worker processes (the CPU share of "
+                  "one GPU; %d CPUs visible); %.3f Mfloats/s, %.2f s wall"
+                  % (what, ntok, len(text) / 1e6, OUT_NAMES.get(f0, f0), nw,
+                     os.cpu_count() or 0, ntok / dt / 1e6, dt),
+        "mfloats_per_s": round(ntok / dt / 1e6, 3),
+        "cpu_model": cpu_model(),
     }
+    return rec, res_text, res_extra
+
+
+def strtod_context(text: bytes, threads=(1, None)):
+    """The C library's strtod over the same text (context, not a target)."""
+    import ctypes
+    from paper_2101_11408_amd.build import STRTOD_LIB
+    if not os.path.exists(STRTOD_LIB):
+        return None
+    lib = ctypes.CDLL(STRTOD_LIB)
+    fn = lib.ffp_ctx_strtod_seconds
+    fn.restype = ctypes.c_double
+    fn.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                   ctypes.POINTER(ctypes.c_uint64)]
+    out = {}
+    for th in threads:
+        th = th or workers()
+        n = ctypes.c_uint64()
+        s = fn(text, len(text), 0, th, 3, ctypes.byref(n))
+        if s > 0:
+            out["threads_%d" % th] = {"GB/s": round(len(text) / s / 1e9, 4),
+                                      "Mfloats/s": round(n.value / s / 1e6, 2)}
+    return {"what": "glibc strtod over the same text (best of 3), binary64",
+            "cpu_model": cpu_model(), **out}
+
+
+def count_mismatches(got_bits, got_st, want_bits, want_st):
+    import numpy as np
+    if len(got_bits) != len(want_bits):
+        return max(len(got_bits), len(want_bits))
+    return int(np.count_nonzero((got_bits != want_bits) | (got_st != want_st)))
+
+
+def slice_parity(slices, pool_ids, fmts, pool_res, extra_res, got):
+    """Mismatches between GPU outputs of slices of token pools and the
+    oracle.  slices: PoolIndex.slice results; pool_res[pool][fmt]: the
+    oracle's (bits, status) of every token of a pool; extra_res[fmt]: the
+    same for the cut tokens of all slices, in slice order (head, then tail);
+    got(i) -> (bits, status) the GPU produced for slice i."""
+    import numpy as np
+    bad, e = 0, 0
+    for i, ((k0, k1, h, t), pid, f) in enumerate(zip(slices, pool_ids, fmts)):
+        pb, ps = pool_res[pid][f]
+        eb, es = extra_res[f]
+        wb, ws = [pb[k0:k1]], [ps[k0:k1]]
+        if h is not None:
+            wb.insert(0, eb[e:e + 1])
+            ws.insert(0, es[e:e + 1])
+            e += 1
+        if t is not None:
+            wb.append(eb[e:e + 1])
+            ws.append(es[e:e + 1])
+            e += 1
+        gb, gs = got(i)
+        bad += count_mismatches(gb, gs, np.concatenate(wb), np.concatenate(ws))
+    return bad
 
 
 # ---------------------------------------------------------------------------
 # helpers
 # ---------------------------------------------------------------------------
 
-def roofline(alg_bytes, kern_ms, workload):
+def copy_peak(torch, reps=10):
+    """A streaming copy (bitwise NOT of 1 GiB of int64, read once and written
+    once) timed with events on torch's stream: the bandwidth a plain
+    streaming kernel reaches on this GPU, the second roofline denominator."""
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.bitwise_not(src, out=dst)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    del src, dst
+    return 2 * (1 << 30) / (times[len(times) // 2] / 1e3) / 1e9
+
+
+def roofline(alg_bytes, kern_ms, workload, copy_gbs=None):
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9
-    return {
+    rec = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -155,6 +345,10 @@ def roofline(alg_bytes, kern_ms, workload):
         "kernel_avg_ms": round(kern_ms, 4),
         "algorithmic_bytes_per_launch": alg_bytes,
     }
+    if copy_gbs:
+        rec["copy_peak_measured"] = round(copy_gbs, 1)
+        rec["frac_of_copy_peak"] = round(achieved / copy_gbs, 4)
+    return rec
 
 
 def base_record(args, value, ms, workload, config, dtype="u64"):
@@ -179,8 +373,7 @@ def base_record(args, value, ms, workload, config, dtype="u64"):
 def spin_up(torch, fn, ms):
     """Untimed calls for at least `ms` milliseconds of wall time, so that the
     timed steps run at the GPU's steady clocks rather than during the clock
-    ramp after a process starts (a few warmup steps of this size take only
-    a millisecond or two)."""
+    ramp after a process starts."""
     t0 = time.perf_counter()
     while (time.perf_counter() - t0) * 1e3 < ms:
         for _ in range(8):
@@ -205,8 +398,9 @@ def timed_steps(torch, fn, steps, warmup, spinup_ms=0.0):
 # single-buffer workloads
 # ---------------------------------------------------------------------------
 
-def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False, delims=b"\n",
+def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims=b"\n",
               flags=0, expect_ok=None):
+    import numpy as np
     import torch
     from paper_2101_11408_amd import ffp
     dev = torch.device("cuda", 0)
@@ -239,27 +433,40 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=False, delim
     assert ctx.last_device_error() == 0
     assert int(count.item()) == ntok
     kavg = kern_ms / launches
-    vbytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[out_dtype]
-    alg = len(buf) + (vbytes + 1) * ntok
+    alg = len(buf) + (VALUE_BYTES[out_dtype] + 1) * ntok
     log("steps done: %.3f ms/step, parse kernel %.3f ms" % (ms, kavg))
     rec = base_record(args, len(buf) / (ms / 1e3) / 1e9, ms, workload, {
         "description": desc, "tokens": ntok, "bytes": len(buf),
         "output": OUT_NAMES[out_dtype], "parallelism": "single GPU"})
     rec["mfloats_per_s"] = round(ntok / (ms / 1e3) / 1e6, 1)
-    rec["roofline"] = roofline(alg, kavg, workload)
-    rec["cpu_baseline"] = cpu_baseline(buf, min(args.cpu_sample, ntok)) if cpu else None
+    rec["roofline"] = roofline(alg, kavg, workload, None if args.profile else copy_peak(torch))
     if red is not None:
         mn, mx, cnt = [int(x) & 0xFFFFFFFFFFFFFFFF for x in red.cpu().tolist()]
         rec["reduce"] = {"min_bits": hex(mn), "max_bits": hex(mx), "count": cnt}
+    got_bits = values.view({8: torch.int64, 4: torch.int32, 2: torch.int16}[
+        VALUE_BYTES[out_dtype]]).cpu().numpy().astype(np.uint64)
+    got_bits &= np.uint64((1 << (8 * VALUE_BYTES[out_dtype])) - 1)
+    got_st = status.cpu().numpy()
     ctx.close()
+    rec["cpu_baseline"] = None
+    if cpu and not args.profile:
+        cb, res, _ = cpu_baseline_leg(buf, [out_dtype], delims=delims, flags=flags,
+                                      what="the whole buffer")
+        wb, ws = res[out_dtype]
+        rec["cpu_baseline"] = cb
+        rec["parity"] = {"vs": "oracle", "tokens_checked": int(len(wb)),
+                         "tokens": ntok, "full": True,
+                         "mismatches": count_mismatches(got_bits, got_st, wb, ws)}
+        rec["context"] = {"glibc_strtod": strtod_context(buf)} if out_dtype == "f64" and \
+            delims == b"\n" and flags == 0 else {}
     return rec
 
 
 # ---------------------------------------------------------------------------
-# batched workloads (config 4)
+# 4096 buffers (configs 4 and 4u): plain per buffer vs batched vs graph
 # ---------------------------------------------------------------------------
 
-def run_batched(args, kind, workload):
+def run_buffers(args, kind, workload):
     import numpy as np
     import torch
     from gen import workloads as W
@@ -269,25 +476,35 @@ def run_batched(args, kind, workload):
     sizes = W.config4_sizes(4, args.nbuf)
     pool = W.token_pool(44, 2_000_000, "mixed" if kind == "mixed" else "uniform")
     plan = W.slice_plan(np.random.default_rng(4), pool, sizes)
+    pidx = PoolIndex(pool)
+    slices = [pidx.slice(st, st + ln) for st, ln in plan]
+    caps = np.array([(k1 - k0) + (h is not None) + (t is not None)
+                     for k0, k1, h, t in slices], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(caps)])
+    ntok_total = int(offs[-1])
     pool_dev = torch.frombuffer(bytearray(pool), dtype=torch.uint8).to(dev)
-    texts, values, statuses, counts = [], [], [], []
-    ntok_total = 0
+    texts = []
     for st, ln in plan:
-        t = torch.empty(ln, dtype=torch.uint8, device=dev)
+        t = torch.empty(ln, dtype=torch.uint8, device=dev)  # separate allocations
         t.copy_(pool_dev[st:st + ln])
-        cap = pool.count(b"\n", st, st + ln) + 1
-        ntok_total += cap
         texts.append(t)
-        values.append(torch.empty(cap, dtype=torch.float64, device=dev))
-        statuses.append(torch.empty(cap, dtype=torch.uint8, device=dev))
-        counts.append(torch.zeros(1, dtype=torch.int64, device=dev))
     del pool_dev
+    # flat outputs; job i writes values[offs[i] : offs[i] + caps[i]]
+    vals = {k: torch.zeros(ntok_total, dtype=torch.float64, device=dev) for k in ("plain", "batch")}
+    stat = {k: torch.full((ntok_total,), 255, dtype=torch.uint8, device=dev)
+            for k in ("plain", "batch")}
+    counts = torch.zeros(len(texts), dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     total = int(sum(sizes))
-    log("%d buffers, %.1f MB, built in %.1f s" % (len(texts), total / 1e6, time.time() - t0))
+    log("%d buffers, %.1f MB, %d tokens, built in %.1f s"
+        % (len(texts), total / 1e6, ntok_total, time.time() - t0))
+
+    def views(k, i):
+        a, b = int(offs[i]), int(offs[i + 1])
+        return vals[k][a:b], stat[k][a:b]
 
     ctx = ffp.Context(0)
-    table = ffp.JobTable(texts, values, statuses, dev)
+    table = ffp.JobTable(texts, *zip(*[views("batch", i) for i in range(len(texts))]), dev)
     stream = torch.cuda.current_stream()
     if args.schedule:
         ctx.set_tuning(*[int(x) for x in args.schedule.split(",")])
@@ -298,11 +515,13 @@ def run_batched(args, kind, workload):
         log("autotuned schedule (tile_k, workgroups/CU):", tune)
 
     # plain: one call per buffer, back to back on one stream
-    ctx.reserve(int(max(sizes)))
+    pctx = ffp.Context(0)
+    pctx.reserve(int(max(sizes)))
+    pviews = [views("plain", i) for i in range(len(texts))]
 
     def plain_all():
-        for t, v, s, c in zip(texts, values, statuses, counts):
-            ctx.parse_into(t, v, s, c, stream=stream)
+        for i, (t, (v, s)) in enumerate(zip(texts, pviews)):
+            pctx.parse_into(t, v, s, counts[i:i + 1], stream=stream)
     ms_plain = None if args.profile else timed_steps(torch, plain_all,
                                                      max(1, args.steps // 5), 1)
 
@@ -317,31 +536,45 @@ def run_batched(args, kind, workload):
     ctx.timing(False)
     kavg = kern_ms / launches
     res = table.download()
-    ntok = sum(c for c, e in res)
     assert all(e == 0 for c, e in res), "job errors"
+    job_counts = np.array([c for c, e in res], dtype=np.int64)
+    assert np.array_equal(job_counts, caps), "token counts"
+    ntok = int(job_counts.sum())
+    check = {}
+    if not args.profile:
+        assert np.array_equal(counts.cpu().numpy(), caps), "plain token counts"
+        check["batched_vs_plain_mismatches"] = int(
+            ((vals["plain"].view(torch.int64) != vals["batch"].view(torch.int64)) |
+             (stat["plain"] != stat["batch"])).sum().item())
 
-    # captured graph replay
+    # captured graph replay, into outputs cleared first
     if args.profile:
         ms_plain = ms_graph = ms_batch
     else:
+        vals["batch"].fill_(-1.0)
+        stat["batch"].fill_(254)
+        table.upload()
         graph = ffp.BatchGraph(ctx, table, total)
         ms_graph = timed_steps(torch, lambda: graph.launch(stream), args.steps, args.warmup,
                                args.spinup_ms)
         res2 = table.download()
         assert [c for c, e in res2] == [c for c, e in res] and all(e == 0 for c, e in res2)
         graph.close()
-    assert ctx.last_device_error() == 0
+        check["graph_vs_plain_mismatches"] = int(
+            ((vals["plain"].view(torch.int64) != vals["batch"].view(torch.int64)) |
+             (stat["plain"] != stat["batch"])).sum().item())
+    assert ctx.last_device_error() == 0 and pctx.last_device_error() == 0
 
     alg = total + 9 * ntok
     gbs = lambda ms: total / (ms / 1e3) / 1e9
     log("plain %.3f ms, batched %.3f ms, graph %.3f ms, parse kernel %.3f ms"
         % (ms_plain, ms_batch, ms_graph, kavg))
     rec = base_record(args, gbs(ms_graph), ms_graph, workload, {
-        "description": "%d independent buffers, lognormal sizes (median 256 KiB, sigma 1.5, "
-                       "1 KiB - 16 MiB), %s text, binary64; value = one replay of the "
-                       "captured batched graph" % (len(texts),
-                                                   "mixed-format" if kind == "mixed"
-                                                   else "uniform [0,1) shortest-digit"),
+        "description": "%d independent buffers (separate allocations), lognormal sizes "
+                       "(median 256 KiB, sigma 1.5, 1 KiB - 16 MiB), %s text, binary64; "
+                       "value = one replay of the captured batched graph"
+                       % (len(texts), "config-2 mix of formats" if kind == "mixed"
+                          else "config-1 format (uniform [0,1) shortest digits)"),
         "buffers": len(texts), "tokens": ntok, "bytes": total, "output": "binary64",
         "parallelism": "single GPU", "schedule": {"tile_k": tune[0], "workgroups_per_cu": tune[1]}})
     rec["mfloats_per_s"] = round(ntok / (ms_graph / 1e3) / 1e6, 1)
@@ -350,9 +583,28 @@ def run_batched(args, kind, workload):
         "batched_call": {"ms": round(ms_batch, 3), "GB/s": round(gbs(ms_batch), 1)},
         "batched_graph": {"ms": round(ms_graph, 3), "GB/s": round(gbs(ms_graph), 1)},
     }
-    rec["roofline"] = roofline(alg, kavg, workload)
+    rec["roofline"] = roofline(alg, kavg, workload, None if args.profile else copy_peak(torch))
     rec["cpu_baseline"] = None
+    if not args.profile:
+        # the oracle over the pool (every distinct token of the workload) and
+        # the cut tokens at buffer ends; compared with every plain output
+        extra = [x for k0, k1, h, t in slices for x in (h, t) if x is not None]
+        cb, res_pool, res_extra = cpu_baseline_leg(
+            pool, ["f64"], extra, what="the token pool all 4096 buffers are cut from, plus "
+                                       "the tokens cut at buffer ends")
+        got_b = vals["plain"].view(torch.int64).cpu().numpy().view(np.uint64)
+        got_s = stat["plain"].cpu().numpy()
+        bad = slice_parity(slices, [0] * len(slices), ["f64"] * len(slices), [res_pool],
+                           res_extra, lambda i: (got_b[offs[i]:offs[i + 1]],
+                                                 got_s[offs[i]:offs[i + 1]]))
+        rec["cpu_baseline"] = cb
+        check.update({"vs": "oracle (plain outputs), batched and graph outputs vs plain",
+                      "tokens_checked": ntok, "tokens": ntok, "full": True,
+                      "mismatches": bad})
+        rec["parity"] = check
+        rec["context"] = {"glibc_strtod": strtod_context(pool)}
     ctx.close()
+    pctx.close()
     return rec
 
 
@@ -360,7 +612,7 @@ def run_batched(args, kind, workload):
 # served workload (config 5)
 # ---------------------------------------------------------------------------
 
-def serve_once(ffp, ctx, reqs, on_device, opts):
+def serve_once(ffp, ctx, reqs, on_device, opts, dst=None):
     """Replays one arrival schedule against a fresh server (ffp_server_replay:
     submission at each arrival time and in-order collection run in native
     threads); returns per-request latency (ns), counts, batch sizes, the wall
@@ -370,7 +622,9 @@ def serve_once(ffp, ctx, reqs, on_device, opts):
     srv = ffp.Server(ctx, **opts)
     try:
         base = ffp.clock_ns() + 20_000_000
-        out = srv.replay(ptrs, sizes, 1 if on_device else 0, dtypes, base + arrive)
+        kw = {} if dst is None else dict(dst_values=dst[0], dst_status=dst[1],
+                                         dst_capacity=dst[2])
+        out = srv.replay(ptrs, sizes, 1 if on_device else 0, dtypes, base + arrive, **kw)
         st = srv.stats()
     finally:
         srv.close()
@@ -382,14 +636,8 @@ def serve_once(ffp, ctx, reqs, on_device, opts):
     exp = (base + arrive).astype(np.int64)
     off = np.flatnonzero(ta != exp)
     if off.size:
-        raise AssertionError(
-            "arrival mismatch at %d requests, first %s: got %d want %d (done %d launch %d "
-            "count %d err %d)" % (off.size, off[:5].tolist(), int(ta[off[0]]), int(exp[off[0]]),
-                                  int(td[off[0]]), int(out["t_launch_ns"][off[0]]),
-                                  int(out["count"][off[0]]), int(out["err"][off[0]])))
-    log("  arrivals %d..%d done %d..%d max latency %.1f us at %d"
-        % (int(ta.min()) - int(base), int(ta.max()) - int(base), int(td.min()) - int(base),
-           int(td.max()) - int(base), lat.max() / 1e3, int(lat.argmax())))
+        raise AssertionError("arrival mismatch at %d requests, first %s"
+                             % (off.size, off[:5].tolist()))
     span = (int(td.max()) - int(ta.min())) / 1e9
     return lat, out["count"].astype(np.int64), out["batch_jobs"], span, st
 
@@ -409,19 +657,22 @@ def summarize(lat, counts, sizes, batch, span, st):
     }
 
 
-def run_served(args, workload):
+def served_rows(args, rates, extra_rates, requests, modes, parity_rate=None):
+    """Config 5's arrivals at each rate against the servers in `modes`
+    (batched, plain, batched_host_text); with parity_rate, the batched
+    server's results at that rate are copied out by the replay and compared
+    with the oracle.  Returns (rows, parity record or None, cpu_baseline)."""
     import numpy as np
     import torch
     from gen import workloads as W
     from paper_2101_11408_amd import ffp
     dev = torch.device("cuda", 0)
     t0 = time.time()
-    mixed = W.token_pool(55, 1_000_000, "mixed")
-    hard = W.token_pool(56, 40_000, "hard")
+    hosts = [W.token_pool(55, 1_000_000, "mixed"), W.token_pool(56, 40_000, "hard")]
     log("pools: mixed %.1f MB, hard %.1f MB, built in %.1f s"
-        % (len(mixed) / 1e6, len(hard) / 1e6, time.time() - t0))
+        % (len(hosts[0]) / 1e6, len(hosts[1]) / 1e6, time.time() - t0))
     pools = []
-    for host in (mixed, hard):
+    for host in hosts:
         d = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(dev)
         p = torch.empty(len(host), dtype=torch.uint8, pin_memory=True)
         p.copy_(torch.frombuffer(bytearray(host), dtype=torch.uint8))
@@ -429,16 +680,14 @@ def run_served(args, workload):
     torch.cuda.synchronize()
     ctx = ffp.Context(0)
     budget = 32 << 30
-    batched = dict(hbm_budget_bytes=budget, max_batch_bytes=256 << 20,
-                   streams=args.serve_streams, max_batch_jobs=1024,
-                   use_graph=args.serve_graph)
-    plain = dict(hbm_budget_bytes=budget, max_batch_bytes=256 << 20,
-                 mode=ffp.FFP_SERVE_PLAIN, streams=1)
-    rows = []
-    config_rates = [int(r) for r in args.rates.split(",")]
-    extra_rates = [int(r) for r in args.extra_rates.split(",") if r]
-    for ri, rate in enumerate(config_rates + extra_rates):
-        t, sizes, is_f32, is_hard = W.config5_requests(5 + ri, rate, args.requests)
+    opts = {"batched": dict(hbm_budget_bytes=budget, max_batch_bytes=256 << 20,
+                            streams=args.serve_streams, max_batch_jobs=1024,
+                            use_graph=args.serve_graph),
+            "plain": dict(hbm_budget_bytes=budget, max_batch_bytes=256 << 20,
+                          mode=ffp.FFP_SERVE_PLAIN, streams=1)}
+    rows, parity, cpu = [], None, None
+    for ri, rate in enumerate(rates + extra_rates):
+        t, sizes, is_f32, is_hard = W.config5_requests(5 + ri, rate, requests)
         rng = np.random.default_rng(500 + ri)
         which = is_hard.astype(np.int64)
         lim = np.array([pools[k][2] for k in which])
@@ -447,39 +696,64 @@ def run_served(args, workload):
         dtypes = is_f32.astype(np.int64)
         arrive = (t * 1e9).astype(np.int64)
         row = {"rate_req_s": rate, "requests": len(sizes),
-               "beyond_config": rate not in config_rates,
+               "beyond_config": rate not in rates,
                "offered_GB/s": round(float(sizes.sum()) / float(t[-1]) / 1e9, 3),
                "binary32_share": round(float(is_f32.mean()), 3),
                "hard_share": round(float(is_hard.mean()), 4)}
-        for name, opts, on_device in (("batched", batched, True), ("plain", plain, True),
-                                      ("batched_host_text", batched, False)):
+        for name in modes:
+            on_device = name != "batched_host_text"
             ptrs = [(pools[k][0] if on_device else pools[k][1]).data_ptr() + int(s)
                     for k, s in zip(which, starts)]
-            lat, counts, batch, span, st = serve_once(ffp, ctx, (ptrs, sizes, dtypes, arrive),
-                                                      on_device, opts)
+            dst = None
+            if name == "batched" and rate == parity_rate:
+                # outputs for every request, sized by its token count
+                idx = [PoolIndex(h) for h in hosts]
+                sl = [idx[k].slice(int(s), int(s) + int(n)) for k, s, n in zip(which, starts, sizes)]
+                caps = np.array([(k1 - k0) + (h is not None) + (tt is not None)
+                                 for k0, k1, h, tt in sl], dtype=np.int64)
+                offs = np.concatenate([[0], np.cumsum(caps)])
+                dv = torch.zeros(int(offs[-1]) + 1, dtype=torch.int64, device=dev)
+                ds = torch.full((int(offs[-1]) + 1,), 255, dtype=torch.uint8, device=dev)
+                # 8-byte slots; binary32 results are packed 4 bytes apart
+                dst = ([dv.data_ptr() + 8 * int(o) for o in offs[:-1]],
+                       [ds.data_ptr() + int(o) for o in offs[:-1]], caps)
+            lat, counts, batch, span, st = serve_once(
+                ffp, ctx, (ptrs, sizes, dtypes, arrive), on_device,
+                opts["plain" if name == "plain" else "batched"], dst)
             row[name] = summarize(lat, counts, sizes, batch, span, st)
             log("rate %d %s: %s" % (rate, name, json.dumps(row[name])))
+            if dst is not None:
+                assert np.array_equal(counts, caps), "served token counts"
+                got_v = dv.cpu().numpy().view(np.uint64)
+                got_s = ds.cpu().numpy()
+                fmts = ["f32" if d == 1 else "f64" for d in dtypes]
+                # the oracle over both pools (every distinct token) and the
+                # tokens cut at request ends, in both output formats
+                extra = [x for k0, k1, h, tt in sl for x in (h, tt) if x is not None]
+                pool_res = []
+                for k, host in enumerate(hosts):
+                    cb, rt, rx = cpu_baseline_leg(host, ["f64", "f32"], [] if k else extra,
+                                                  what="the mixed request pool" if k == 0
+                                                  else "the hard-case pool")
+                    pool_res.append(rt)
+                    if k == 0:
+                        cpu, extra_res = cb, rx
+
+                def got(i):
+                    a, c = int(offs[i]), int(caps[i])
+                    if fmts[i] == "f64":
+                        return got_v[a:a + c], got_s[a:a + c]
+                    # binary32 results sit 4 bytes apart from the slot's start
+                    return got_v[a:a + (c + 1) // 2].view(np.uint32)[:c].astype(np.uint64), \
+                        got_s[a:a + c]
+                bad = slice_parity(sl, which.tolist(), fmts, pool_res, extra_res, got)
+                parity = {"vs": "oracle", "rate_req_s": rate, "server": "batched",
+                          "requests": len(sizes), "tokens_checked": int(caps.sum()),
+                          "full": True, "mismatches": bad}
+                del dv, ds
         rows.append(row)
     ctx.close()
-    top = [r for r in rows if not r["beyond_config"]][-1]
-    rec = base_record(args, top["batched"]["GB/s"], top["batched"]["p50_us"] / 1e3, workload, {
-        "description": "served parse requests, Poisson open-loop arrivals at %s req/s, %d "
-                       "requests per rate, sizes lognormal (median 64 KiB, sigma 1.5, 512 B - "
-                       "8 MiB), 90%% binary64 / 10%% binary32, 1%% hard cases, 32 GiB HBM "
-                       "budget; value = GB/s served by the continuous-batching server at the "
-                       "highest rate (device-resident text); ms_per_step = its p50 latency"
-                       % (args.rates, args.requests),
-        "streams": args.serve_streams, "graph": bool(args.serve_graph),
-        "parallelism": "single GPU"})
-    rec["steps"] = args.requests
-    rec["p50_us"] = top["batched"]["p50_us"]
-    rec["p99_us"] = top["batched"]["p99_us"]
-    rec["serve"] = rows
-    rec["roofline"] = None
-    rec["roofline_note"] = ("served batches are small and latency-bound; the parse kernel's "
-                            "HBM roofline is measured on config4u")
-    rec["cpu_baseline"] = None
-    return rec
+    return rows, parity, cpu
 
 
 # ---------------------------------------------------------------------------
@@ -617,14 +891,48 @@ def summarize_trace(workload, trace_dir, command, bench_json=None):
     return name
 
 
+
+
+def run_served(args, workload):
+    """Config 5 on its own: every rate, the three servers, parity at the
+    highest configured rate."""
+    rates = [int(r) for r in args.rates.split(",")]
+    extra = [int(r) for r in args.extra_rates.split(",") if r]
+    rows, parity, cpu = served_rows(args, rates, extra, args.requests,
+                                    ["batched", "plain", "batched_host_text"],
+                                    parity_rate=None if args.no_cpu_baseline else rates[-1])
+    top = [r for r in rows if not r["beyond_config"]][-1]
+    rec = base_record(args, top["batched"]["GB/s"], top["batched"]["p50_us"] / 1e3, workload, {
+        "description": "served parse requests, Poisson open-loop arrivals at %s req/s, %d "
+                       "requests per rate, sizes lognormal (median 64 KiB, sigma 1.5, 512 B - "
+                       "8 MiB), 90%% binary64 / 10%% binary32, 1%% hard cases, 32 GiB HBM "
+                       "budget; value = GB/s served by the continuous-batching server at the "
+                       "highest rate (device-resident text); ms_per_step = its p50 latency"
+                       % (args.rates, args.requests),
+        "streams": args.serve_streams, "graph": bool(args.serve_graph),
+        "parallelism": "single GPU"})
+    rec["steps"] = args.requests
+    rec["p50_us"] = top["batched"]["p50_us"]
+    rec["p99_us"] = top["batched"]["p99_us"]
+    rec["p999_us"] = top["batched"]["p999_us"]
+    rec["serve"] = rows
+    rec["roofline"] = None
+    rec["roofline_note"] = ("served batches are small and latency-bound; the parse kernel's "
+                            "HBM roofline is measured on config4u")
+    rec["cpu_baseline"] = cpu
+    if parity:
+        rec["parity"] = parity
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--spinup-ms", type=float, default=200.0,
                     help="untimed calls for this long before the warmup steps (GPU clock ramp)")
-    ap.add_argument("--workload", default="config2",
+    ap.add_argument("--workload", default="config4u",
                     choices=["config1", "config2", "config3", "config4", "config4u",
                              "config5", "copycal", "jsondoc", "hexfloat"])
     ap.add_argument("--round", default="nearest", choices=sorted(ROUND_FLAGS),
@@ -635,19 +943,23 @@ def main():
                     help="plain workloads: also keep the min, max and count of the values")
     ap.add_argument("--out", default="f64", choices=["f64", "f32", "f16", "bf16"],
                     help="plain workloads: output format")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (cpu_baseline and parity)")
     ap.add_argument("--rates", default="2000,5000,10000,20000")
     ap.add_argument("--extra-rates", default="50000,100000",
                     help="served workload: rates beyond the configuration's range, "
                          "reported separately (saturation)")
-    ap.add_argument("--requests", type=int, default=60_000)
+    ap.add_argument("--requests", type=int, default=60_000,
+                    help="served workload: requests per rate")
+    ap.add_argument("--serve-requests", type=int, default=10_000,
+                    help="default workload: requests per rate of its short served run "
+                         "(0: none)")
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-graph", type=int, default=0)
     ap.add_argument("--schedule", default="",
                     help="batched workloads: tile_k,workgroups_per_cu instead of the autotuner")
     ap.add_argument("--profile", action="store_true",
-                    help="batched workloads: only the timed batched calls (for counter runs)")
+                    help="only the timed batched or plain calls (for profiler runs)")
     ap.add_argument("--reduce-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
                                                           "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
                     help="write profiles/traffic.json for --workload from rocprofv3 "
@@ -674,10 +986,13 @@ def main():
               "note (one prefix sum of per-shard token counts), not built; use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.profile:
+        args.no_cpu_baseline = True
 
     from gen import workloads as W
 
     wl = args.workload
+    cpu = not args.no_cpu_baseline
     if wl == "config2":
         n = args.tokens or 10_000_000
         t0 = time.time()
@@ -688,15 +1003,14 @@ def main():
                         "digits, 25%% coordinates (6-15 fraction digits), 25%% random finite "
                         "bit patterns as %%.17e; %s output; one parse call per step"
                         % (len(buf) / 1e6, OUT_NAMES[args.out]), out_dtype=args.out,
-                        cpu=not args.no_cpu_baseline and args.out == "f64" and args.round == "nearest",
-                        flags=ROUND_FLAGS[args.round])
+                        cpu=cpu, flags=ROUND_FLAGS[args.round])
     elif wl == "config1":
         n = args.tokens or 100_000
         buf = W.config1(n=n)
         rec = run_plain(args, buf, n, out_name(wl, args.out, args.round),
                         "100k uniform [0,1) doubles, shortest digits, positional, one "
                         "%.2f MB buffer; %s" % (len(buf) / 1e6, OUT_NAMES[args.out]),
-                        out_dtype=args.out, flags=ROUND_FLAGS[args.round])
+                        out_dtype=args.out, cpu=cpu, flags=ROUND_FLAGS[args.round])
     elif wl == "config3":
         n = args.tokens or 2_000_000
         t0 = time.time()
@@ -706,9 +1020,9 @@ def main():
                         "2M hard cases (midpoints +-1 in the last of 20-800 digits, "
                         "subnormals, overflow, integers to 2^64, sign/zero variants) in one "
                         "%.1f MB buffer; %s" % (len(buf) / 1e6, OUT_NAMES[args.out]),
-                        out_dtype=args.out, flags=ROUND_FLAGS[args.round])
+                        out_dtype=args.out, cpu=cpu, flags=ROUND_FLAGS[args.round])
     elif wl == "config4":
-        rec = run_batched(args, "mixed", WORKLOAD_NAMES[wl])
+        rec = run_buffers(args, "mixed", WORKLOAD_NAMES[wl])
     elif wl == "jsondoc":
         t0 = time.time()
         nfeat = (args.tokens or 10_000_000) // 2000
@@ -720,7 +1034,7 @@ def main():
                         "with 6-15 fraction digits; JSON number grammar, the document's "
                         "structure bytes as delimiters (keys and strings come back invalid); "
                         "%s" % (len(doc) / 1e6, nfeat, OUT_NAMES[args.out]),
-                        out_dtype=args.out, delims=W.JSON_DELIMS, flags=2,
+                        out_dtype=args.out, cpu=cpu, delims=W.JSON_DELIMS, flags=2,
                         expect_ok=nfeat * 2000)
     elif wl == "hexfloat":
         import numpy as np
@@ -733,14 +1047,30 @@ def main():
         rec = run_plain(args, buf, n, out_name(wl, args.out, args.round),
                         "10M random doubles (normal * 10^U[-300,300)) in their own hexadecimal "
                         "form (Appendix C), one %.1f MB buffer; FFP_HEX; %s"
-                        % (len(buf) / 1e6, OUT_NAMES[args.out]), out_dtype=args.out,
+                        % (len(buf) / 1e6, OUT_NAMES[args.out]), out_dtype=args.out, cpu=cpu,
                         flags=8 | ROUND_FLAGS[args.round], expect_ok=n)
     elif wl == "config5":
         rec = run_served(args, WORKLOAD_NAMES[wl])
     elif wl == "copycal":
         rec = run_copycal(args)
-    else:
-        rec = run_batched(args, "uniform", WORKLOAD_NAMES[wl])
+    else:  # config4u: the HBM target run, with a short served run beside it
+        rec = run_buffers(args, "uniform", WORKLOAD_NAMES[wl])
+        if args.serve_requests and not args.profile:
+            rates = [int(r) for r in args.rates.split(",")]
+            rows, parity, _ = served_rows(args, rates, [], args.serve_requests,
+                                          ["batched", "plain"],
+                                          parity_rate=rates[-1] if cpu else None)
+            top = rows[-1]
+            rec["latency_us"] = {
+                "what": "config 5 arrivals (%d requests per rate, text on the device): "
+                        "continuous-batching server vs one launch per request"
+                        % args.serve_requests,
+                "rate_req_s": top["rate_req_s"],
+                "batched": {k: top["batched"][k] for k in ("p50_us", "p99_us", "p999_us")},
+                "plain": {k: top["plain"][k] for k in ("p50_us", "p99_us", "p999_us")}}
+            rec["serve"] = rows
+            if parity:
+                rec["serve_parity"] = parity
     print(json.dumps(rec), flush=True)
 
 

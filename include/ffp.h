@@ -452,15 +452,20 @@ void ffp_server_destroy(ffp_server* srv);
  * submitting thread submits request i at its arrival time (spinning for the
  * last few hundred microseconds; retrying while the server answers
  * FFP_E_BUSY), a collecting thread waits for the requests in submission
- * order, records their timestamps and releases them (the parsed values are
- * discarded).  Blocks until every request is done.  Returns FFP_SUCCESS or
- * the first submission error. */
+ * order, records their timestamps, copies the results of requests that name
+ * destinations (ffp_server_copy_result on a stream of its own; others are
+ * discarded) and releases them.  Blocks until every request is done and
+ * every copy has completed.  Returns FFP_SUCCESS or the first submission
+ * error. */
 typedef struct ffp_replay_request {
     const uint8_t* text;
     uint64_t nbytes;
     int32_t on_device;
     int32_t dtype;
     uint64_t arrival_ns;  /* CLOCK_MONOTONIC */
+    void* dst_values;     /* optional (device or pinned host): the values */
+    uint8_t* dst_status;  /* optional: the status bytes */
+    uint64_t dst_capacity;  /* tokens the destinations hold */
 } ffp_replay_request;
 
 typedef struct ffp_replay_result {

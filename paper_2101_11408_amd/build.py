@@ -58,7 +58,24 @@ def build(verbose: bool = False) -> str:
     if verbose and out.strip():
         print(out)
     os.replace(tmp, LIB)
+    build_strtod_ctx()
     return LIB
+
+
+STRTOD_LIB = os.path.join(LIBDIR, "libstrtod_ctx.so")
+
+
+def build_strtod_ctx() -> str:
+    """The C library's strtod / strtof timed over a buffer: a context line
+    beside the GPU parser's measurements (plain C, host only)."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        raise RuntimeError("no C compiler for the strtod context library")
+    tmp = STRTOD_LIB + ".tmp"
+    subprocess.check_call([cc, "-O2", "-shared", "-fPIC", "-pthread",
+                           os.path.join(CSRC, "strtod_ctx.c"), "-o", tmp])
+    os.replace(tmp, STRTOD_LIB)
+    return STRTOD_LIB
 
 
 if __name__ == "__main__":

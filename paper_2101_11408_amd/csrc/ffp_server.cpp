@@ -571,7 +571,27 @@ int ffp_server_replay(ffp_server* srv, const ffp_replay_request* reqs, uint64_t 
   std::vector<uint64_t> tickets(n, 0);
   std::atomic<uint64_t> submitted{0};
   std::atomic<bool> stop{false};
+  std::atomic<int> copy_rc{FFP_SUCCESS};
   std::thread collector([&] {
+    // results that name destinations are copied on a stream of this thread
+    hipStream_t cs = nullptr;
+    (void)hipSetDevice(srv->device);
+    for (uint64_t i = 0; i < n && !cs; ++i)
+      if ((reqs[i].dst_values || reqs[i].dst_status) &&
+          hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        cs = nullptr;
+        copy_rc = FFP_E_HIP;
+        break;
+      }
+    struct StreamEnd {
+      hipStream_t& s;
+      ~StreamEnd() {
+        if (s) {
+          (void)hipStreamSynchronize(s);
+          (void)hipStreamDestroy(s);
+        }
+      }
+    } stream_end{cs};
     for (uint64_t i = 0; i < n; ++i) {
       while (submitted.load(std::memory_order_acquire) <= i) {
         // stop is set after the last submission is published: once it is
@@ -590,6 +610,10 @@ int ffp_server_replay(ffp_server* srv, const ffp_replay_request* reqs, uint64_t 
         o.count = r.count;
         o.err = r.err;
         o.batch_jobs = r.batch_jobs;
+        if (cs && (reqs[i].dst_values || reqs[i].dst_status) &&
+            ffp_server_copy_result(srv, tickets[i], reqs[i].dst_values, reqs[i].dst_status,
+                                   reqs[i].dst_capacity, cs) != FFP_SUCCESS)
+          copy_rc = FFP_E_HIP;
       } else {
         o = ffp_replay_result{};
         o.err = FFP_E_ARG;
@@ -619,7 +643,7 @@ int ffp_server_replay(ffp_server* srv, const ffp_replay_request* reqs, uint64_t 
   }
   stop.store(true, std::memory_order_release);
   collector.join();
-  return rc;
+  return rc != FFP_SUCCESS ? rc : copy_rc.load();
 }
 
 void ffp_server_destroy(ffp_server* srv) {

@@ -85,7 +85,8 @@ class ffp_result(ctypes.Structure):
 class ffp_replay_request(ctypes.Structure):
     _fields_ = [("text", ctypes.c_void_p), ("nbytes", ctypes.c_uint64),
                 ("on_device", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("arrival_ns", ctypes.c_uint64)]
+                ("arrival_ns", ctypes.c_uint64), ("dst_values", ctypes.c_void_p),
+                ("dst_status", ctypes.c_void_p), ("dst_capacity", ctypes.c_uint64)]
 
 
 class ffp_replay_result(ctypes.Structure):
@@ -510,19 +511,26 @@ class Server:
     def release(self, ticket):
         check(load().ffp_server_release(self.handle, ticket), "release")
 
-    def replay(self, ptrs, sizes, on_device, dtypes, arrival_ns):
+    def replay(self, ptrs, sizes, on_device, dtypes, arrival_ns, dst_values=None,
+               dst_status=None, dst_capacity=None):
         """Replays an arrival trace (ffp_server_replay); returns a numpy
-        structured array of per-request results."""
+        structured array of per-request results.  With dst_* (per-request
+        pointers and capacities) each request's results are copied there."""
         import numpy as np
         n = len(ptrs)
         req = np.zeros(n, dtype=np.dtype([("text", "<u8"), ("nbytes", "<u8"),
                                           ("on_device", "<i4"), ("dtype", "<i4"),
-                                          ("arrival_ns", "<u8")]))
+                                          ("arrival_ns", "<u8"), ("dst_values", "<u8"),
+                                          ("dst_status", "<u8"), ("dst_capacity", "<u8")]))
         req["text"] = ptrs
         req["nbytes"] = sizes
         req["on_device"] = on_device
         req["dtype"] = dtypes
         req["arrival_ns"] = arrival_ns
+        if dst_values is not None:
+            req["dst_values"] = dst_values
+            req["dst_status"] = dst_status
+            req["dst_capacity"] = dst_capacity
         out = np.zeros(n, dtype=np.dtype([("t_arrive_ns", "<u8"), ("t_launch_ns", "<u8"),
                                           ("t_done_ns", "<u8"), ("count", "<u8"),
                                           ("err", "<i4"), ("batch_jobs", "<u4")]))

@@ -277,16 +277,29 @@ def test_replay_trace(ctx, ffpmod, pool, reference):
     rng = np.random.default_rng(21)
     arrive = np.cumsum(rng.exponential(100e-6, size=len(reqs))) * 1e9
     ptrs = [(dev if q[2] else pinned)[q[0]:].data_ptr() if q[1] else 0 for q in reqs]
+    # results copied out by the replay itself (every other request)
+    caps = [a[0] if i % 2 == 0 else 0 for i, a in enumerate(alone)]
+    dv = [torch.empty(max(c, 1), dtype=torch.float32 if q[3] == 1 else torch.float64,
+                      device="cuda:0") for c, q in zip(caps, reqs)]
+    ds = [torch.full((max(c, 1),), 255, dtype=torch.uint8, device="cuda:0") for c in caps]
     srv = ffpmod.Server(ctx, hbm_budget_bytes=2 << 30, max_batch_bytes=64 << 20,
                         max_batch_jobs=32)
     try:
         base = ffpmod.clock_ns() + 5_000_000
         out = srv.replay(ptrs, [q[1] for q in reqs], [1 if q[2] else 0 for q in reqs],
-                         [q[3] for q in reqs], (base + arrive).astype(np.uint64))
+                         [q[3] for q in reqs], (base + arrive).astype(np.uint64),
+                         dst_values=[v.data_ptr() if c else 0 for v, c in zip(dv, caps)],
+                         dst_status=[x.data_ptr() if c else 0 for x, c in zip(ds, caps)],
+                         dst_capacity=caps)
         st = srv.stats()
     finally:
         srv.close()
     assert (out["err"] == 0).all()
+    for i, c in enumerate(caps):
+        if c:
+            ib, npb = (torch.int32, np.uint32) if reqs[i][3] == 1 else (torch.int64, np.uint64)
+            assert np.array_equal(dv[i][:c].view(ib).cpu().numpy().view(npb), alone[i][2]), i
+            assert np.array_equal(ds[i][:c].cpu().numpy(), alone[i][3]), i
     # every request was collected, the last one included
     assert (out["t_arrive_ns"] == (base + arrive).astype(np.uint64)).all()
     assert list(out["count"]) == [a[0] for a in alone]
