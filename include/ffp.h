@@ -58,7 +58,8 @@ enum ffp_error {
     FFP_E_BUDGET = -5,    /* request does not fit the server's HBM budget */
     FFP_E_BUSY = -6,      /* server has no free slot (non-blocking submit) */
     FFP_E_QUEUE = -7,     /* fallback queue overflowed; result incomplete */
-    FFP_E_INTERNAL = -8   /* internal consistency check failed */
+    FFP_E_INTERNAL = -8,  /* internal consistency check failed */
+    FFP_E_SIZE = -9       /* input larger than ffp_parse_f64_noalloc accepts */
 };
 
 /* Reject a leading '+' sign, as JSON does (Section 4). */
@@ -172,6 +173,25 @@ int ffp_parse_f64(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
 int ffp_parse_f32(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
                   float* d_values, uint8_t* d_status, uint64_t capacity,
                   uint64_t* d_count, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * parse as ffp_parse_f64, with the same arguments and results, that calls
+ * no hipMalloc, hipFree or other allocating routine.  Its scratch (device
+ * state, per-block token counts and the fallback queue, about 7.5 MB) is a
+ * fixed array in the library's device image, one per GPU, held until the
+ * process ends; its address is looked up once per device by ffp_create.
+ * Texts of up to 8 MiB (8388608 bytes) are accepted; a larger nbytes returns
+ * FFP_E_SIZE and queues nothing.  Every call on a GPU shares that GPU's
+ * array (from any context or thread): calls whose work overlaps on one GPU
+ * race and give wrong results, so order them on one stream or synchronise
+ * between them.  The array keeps the last call's contents; each call resets
+ * what must start at zero on the device, in stream order.  The context's
+ * timing events and path counters are not used by this call;
+ * ffp_last_device_error reports on it as on any call. */
+int ffp_parse_f64_noalloc(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                          double* d_values, uint8_t* d_status, uint64_t capacity,
+                          uint64_t* d_count, void* stream);
 
 /* As above, then waits for the stream.  Returns the token count (>= 0), or a
  * negative ffp_error: FFP_E_CAPACITY when count > capacity (the first

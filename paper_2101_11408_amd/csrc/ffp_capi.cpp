@@ -142,18 +142,33 @@ CallShape call_shape(const ffp_ctx* ctx, uint64_t bytes, bool reduce, uint64_t c
   return cs;
 }
 
+// The device scratch a call runs on: the context's own (grown as needed) or
+// the fixed array of the entry point that allocates nothing.
+struct Scratch {
+  uint64_t* block_sum;
+  QueueEntry* queue;
+  uint64_t queue_cap;
+  DeviceState* state;
+  bool fixed;  // the fixed array: no timing events, no path counters
+};
+
+Scratch own_scratch(const ffp_ctx* ctx) {
+  return Scratch{ctx->d_block_sum, ctx->d_queue, ctx->queue_cap, ctx->d_state, false};
+}
+
 // count -> scan -> parse -> fallback for a job set whose block count is
 // `nblocks` (plain calls) or on the device (batched calls, nblocks = ~0).
-int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uint64_t nblocks,
-                hipStream_t s) {
+int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const CallShape& shape,
+                uint64_t nblocks, hipStream_t s) {
+  ctx->last_state = sc.state;
   ffp::ScanParams sp{};
   sp.js = js;
-  sp.block_sum = ctx->d_block_sum;
-  sp.st = ctx->d_state;
+  sp.block_sum = sc.block_sum;
+  sp.st = sc.state;
   if (nblocks > 0) {
     ffp::CountParams cp{};
     cp.js = js;
-    cp.block_sum = ctx->d_block_sum;
+    cp.block_sum = sc.block_sum;
     cp.delim = ctx->delim;
     uint64_t grid = (uint64_t)ctx->num_cus * 8;
     if (grid > nblocks) grid = nblocks;
@@ -164,19 +179,20 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uin
 
   ffp::ParseParams P{};
   P.js = js;
-  P.block_prefix = ctx->d_block_sum;
-  P.st = ctx->d_state;
-  P.queue = ctx->d_queue;
-  P.queue_cap = ctx->queue_cap;
+  P.block_prefix = sc.block_sum;
+  P.st = sc.state;
+  P.queue = sc.queue;
+  P.queue_cap = sc.queue_cap;
   P.delim = ctx->delim;
   P.flags = ctx->flags;
-  P.count_paths = ctx->counters ? 1u : 0u;
+  P.count_paths = ctx->counters && !sc.fixed ? 1u : 0u;
   P.reduce_out = js.jobs ? nullptr : ctx->reduce_out;  // plain calls only
   uint64_t grid = (uint64_t)shape.grid;
   if (grid > nblocks) grid = nblocks;
 
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-  if (ctx->timing) {
+  const bool timing = ctx->timing && !sc.fixed;
+  if (timing) {
     if (!ctx->ev_free.empty()) {
       ev = ctx->ev_free.back();
       ctx->ev_free.pop_back();
@@ -192,16 +208,16 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uin
   }
   if (ffp::launch_parse(shape.tile_k, ctx->delim.single != 0, P, (int)grid, s) != hipSuccess)
     return FFP_E_HIP;
-  if (ctx->timing) {
+  if (timing) {
     if (hipEventRecord(ev.second, s) != hipSuccess) return FFP_E_HIP;
     ctx->ev_used.push_back(ev);
   }
 
   ffp::FallbackParams F{};
   F.js = js;
-  F.queue = ctx->d_queue;
-  F.queue_cap = ctx->queue_cap;
-  F.st = ctx->d_state;
+  F.queue = sc.queue;
+  F.queue_cap = sc.queue_cap;
+  F.st = sc.state;
   F.delim = ctx->delim;
   F.reduce_out = P.reduce_out;
   F.flags = P.flags;
@@ -211,14 +227,28 @@ int launch_jobs(ffp_ctx* ctx, const ffp::JobSet& js, const CallShape& shape, uin
 
 int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t nbytes,
                  void* d_values, uint8_t* d_status, uint64_t capacity, uint64_t* d_count,
-                 void* stream, int32_t* d_err = nullptr) {
+                 void* stream, int32_t* d_err = nullptr, bool fixed = false) {
   if (!ctx || !d_count) return FFP_E_ARG;
   if (nbytes >= ffp::kMaxBytes) return FFP_E_ARG;
   if (nbytes > 0 && !d_text) return FFP_E_ARG;
   if (capacity > 0 && (!d_values || !d_status)) return FFP_E_ARG;
+  if (fixed && nbytes > ffp::kNoAllocMaxBytes) return FFP_E_SIZE;
+  if (fixed && !ctx->d_fixed) return FFP_E_HIP;
   DeviceGuard g(ctx->device);
-  int rc = grow(ctx, nbytes, 1);
-  if (rc != FFP_SUCCESS) return rc;
+  Scratch sc{};
+  if (fixed) {
+    // the fixed array: nothing is allocated, grown or freed
+    unsigned char* base = ctx->d_fixed;
+    sc.state = reinterpret_cast<DeviceState*>(base + ffp::kNoAllocStateOff);
+    sc.block_sum = reinterpret_cast<uint64_t*>(base + ffp::kNoAllocBlockOff);
+    sc.queue = reinterpret_cast<QueueEntry*>(base + ffp::kNoAllocQueueOff);
+    sc.queue_cap = ffp::kNoAllocQueue;
+    sc.fixed = true;
+  } else {
+    const int rc = grow(ctx, nbytes, 1);
+    if (rc != FFP_SUCCESS) return rc;
+    sc = own_scratch(ctx);
+  }
 
   JobDesc job{};
   job.text = d_text;
@@ -243,7 +273,7 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   js.block_shift = shape.block_shift;
   js.total_blocks = nblocks;
   js.total_blocks_dev = nullptr;
-  return launch_jobs(ctx, js, shape, nblocks, (hipStream_t)stream);
+  return launch_jobs(ctx, sc, js, shape, nblocks, (hipStream_t)stream);
 }
 
 int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
@@ -272,7 +302,7 @@ int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_tot
   js.total_blocks_dev = reinterpret_cast<const uint64_t*>(&ctx->d_state->total_blocks);
   // grids are sized for the largest batch the scratch allows; kernels read
   // the true block count on the device
-  return launch_jobs(ctx, js, shape, ctx->block_cap - 1, s);
+  return launch_jobs(ctx, own_scratch(ctx), js, shape, ctx->block_cap - 1, s);
 }
 
 int64_t finish_sync(ffp_ctx* ctx, int rc, uint64_t capacity, uint64_t* d_count, void* stream) {
@@ -282,7 +312,7 @@ int64_t finish_sync(ffp_ctx* ctx, int rc, uint64_t capacity, uint64_t* d_count, 
   uint64_t count = 0;
   unsigned err = 0;
   if (hipMemcpy(&count, d_count, sizeof(count), hipMemcpyDeviceToHost) != hipSuccess) return FFP_E_HIP;
-  if (hipMemcpy(&err, &ctx->d_state->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(&err, &ctx->last_state->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
     return FFP_E_HIP;
   if (err & ffp::kDevInternal) return FFP_E_INTERNAL;
   if (err & ffp::kDevQueue) return FFP_E_QUEUE;
@@ -421,6 +451,7 @@ const char* ffp_strerror(int err) {
     case FFP_E_BUSY: return "no free slot";
     case FFP_E_QUEUE: return "fallback queue overflow";
     case FFP_E_INTERNAL: return "internal consistency check failed";
+    case FFP_E_SIZE: return "input larger than the fixed scratch of ffp_parse_f64_noalloc allows";
     default: return "unknown error";
   }
 }
@@ -488,11 +519,20 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
     delete ctx;
     return FFP_E_NOMEM;
   }
+  ctx->last_state = ctx->d_state;
   if (hipMemset(ctx->d_state, 0, sizeof(DeviceState)) != hipSuccess ||
       grow(ctx, 1 << 20, 1) != FFP_SUCCESS) {
     ffp_destroy(ctx);
     return FFP_E_NOMEM;
   }
+  // the fixed scratch of ffp_parse_f64_noalloc: its address on this device
+  // (looked up once per device, with the device current)
+  void* fixed = nullptr;
+  if (ffp::noalloc_scratch(hip_device, &fixed) != hipSuccess) {
+    ffp_destroy(ctx);
+    return FFP_E_HIP;
+  }
+  ctx->d_fixed = static_cast<unsigned char*>(fixed);
   *out = ctx;
   return FFP_SUCCESS;
 }
@@ -534,6 +574,13 @@ int ffp_parse_f32(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes, float* d
                   uint8_t* d_status, uint64_t capacity, uint64_t* d_count, void* stream) {
   return parse_common(ctx, ffp::kF32, d_text, nbytes, d_values, d_status, capacity, d_count,
                       stream);
+}
+
+int ffp_parse_f64_noalloc(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
+                          double* d_values, uint8_t* d_status, uint64_t capacity,
+                          uint64_t* d_count, void* stream) {
+  return parse_common(ctx, ffp::kF64, d_text, nbytes, d_values, d_status, capacity, d_count,
+                      stream, nullptr, true);
 }
 
 int64_t ffp_parse_f64_sync(ffp_ctx* ctx, const uint8_t* d_text, uint64_t nbytes,
@@ -725,7 +772,7 @@ int ffp_last_device_error(ffp_ctx* ctx) {
   if (!ctx) return FFP_E_ARG;
   DeviceGuard g(ctx->device);
   unsigned err = 0;
-  if (hipMemcpy(&err, &ctx->d_state->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(&err, &ctx->last_state->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
     return FFP_E_HIP;
   if (err & ffp::kDevInternal) return FFP_E_INTERNAL;
   if (err & ffp::kDevQueue) return FFP_E_QUEUE;

@@ -37,6 +37,10 @@ struct ffp_ctx {
   JobDesc* d_jobs = nullptr;  // internal job table of batched calls
   uint64_t jobs_cap = 0;
   DeviceState* d_state = nullptr;
+  // the fixed scratch of ffp_parse_f64_noalloc on this context's device
+  unsigned char* d_fixed = nullptr;
+  // device state of the last call (d_state, or the fixed scratch's)
+  DeviceState* last_state = nullptr;
 
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;

@@ -37,6 +37,18 @@ constexpr uint64_t kMaxBytes = 1ull << 47;
 // Algorithm 1 on top of the provable bound for long tokens.
 constexpr uint64_t kAbortReserve = 65536;
 
+// Fixed scratch of the entry point that allocates nothing
+// (ffp_parse_f64_noalloc): texts of up to kNoAllocMaxBytes; the device
+// state, the per-block counts and the fallback queue sized as a regular call
+// on such a text sizes them (one job, blocks of at least 4 KiB).
+constexpr uint64_t kNoAllocMaxBytes = 8ull << 20;
+constexpr uint64_t kNoAllocBlocks = ((kNoAllocMaxBytes + 15) >> kMinBlockShift) + 3;
+constexpr uint64_t kNoAllocQueue = (kNoAllocMaxBytes + 1) / 21 + kAbortReserve;
+constexpr uint64_t kNoAllocStateOff = 0;
+constexpr uint64_t kNoAllocBlockOff = 256;
+constexpr uint64_t kNoAllocQueueOff = kNoAllocBlockOff + ((kNoAllocBlocks * 8 + 255) & ~255ull);
+constexpr uint64_t kNoAllocScratchBytes = kNoAllocQueueOff + kNoAllocQueue * 16;
+
 enum DType : uint32_t { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 
 enum DevError : uint32_t { kDevOk = 0, kDevQueue = 1, kDevInternal = 2 };
@@ -80,6 +92,9 @@ struct DeviceState {
   // min / max of the order keys of the values and their count (reduction)
   unsigned long long red_min, red_max, red_count;
 };
+
+static_assert(sizeof(DeviceState) <= kNoAllocBlockOff, "device state fits its scratch slot");
+static_assert(sizeof(QueueEntry) == 16, "queue entry size");
 
 struct DelimSet {
   uint64_t bits[4];

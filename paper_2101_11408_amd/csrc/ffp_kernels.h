@@ -13,6 +13,10 @@ int parse_tile_bytes(int k);
 // without a reduction, or (wide) of the largest of the other instances.
 hipError_t parse_occupancy(int k, bool single_delim, bool wide, int* blocks_per_cu);
 
+// Device address of the fixed scratch array on `device`, which must be the
+// current device; looked up once per device.
+hipError_t noalloc_scratch(int device, void** ptr);
+
 hipError_t launch_prep(const PrepParams& P, hipStream_t s);
 hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipStream_t s);
 hipError_t launch_scan(const ScanParams& P, hipStream_t s);

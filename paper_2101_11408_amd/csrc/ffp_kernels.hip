@@ -18,6 +18,8 @@
 // No workgroup ever waits for another one.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ffp_device.h"
 #include "ffp_fallback.h"
 #include "ffp_internal.h"
@@ -1082,6 +1084,34 @@ __global__ void k_reduce_final(FallbackParams P) {
   gstore(P.reduce_out + 0, cnt ? key_to_bits(kmin, dt) : nan);
   gstore(P.reduce_out + 1, cnt ? key_to_bits(kmax, dt) : nan);
   gstore(P.reduce_out + 2, (uint64_t)cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing: device state, per-block
+// counts and the fallback queue at fixed offsets (ffp_internal.h).  Each GPU
+// holds its own copy of the array for the life of the process; host code
+// never passes the array's name to a kernel, only the device address
+// returned for it below.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) return hipErrorInvalidDevice;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

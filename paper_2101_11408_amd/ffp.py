@@ -29,6 +29,8 @@ FFP_E_BUDGET = -5
 FFP_E_BUSY = -6
 FFP_E_QUEUE = -7
 FFP_E_INTERNAL = -8
+FFP_E_SIZE = -9
+NOALLOC_MAX_BYTES = 8 << 20
 
 FFP_REJECT_PLUS = 1
 FFP_JSON = 2
@@ -114,6 +116,7 @@ _SIGNATURES = {
     "ffp_strerror": (_c.c_char_p, [_INT]),
     "ffp_reserve": (_INT, [_P, _U64]),
     "ffp_parse_f64": (_INT, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
+    "ffp_parse_f64_noalloc": (_INT, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
     "ffp_parse_f32": (_INT, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
     "ffp_parse_f64_sync": (_I64, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
     "ffp_parse_f32_sync": (_I64, [_P, _P, _U64, _P, _P, _U64, _P, _P]),
@@ -330,6 +333,19 @@ class Context:
         rc = fn(self.handle, text.data_ptr(), nb, values.data_ptr(), status.data_ptr(), cap,
                 count.data_ptr(), _stream_handle(stream))
         return rc if sync else check(rc, "parse")
+
+    def parse_into_noalloc(self, text, values, status, count, nbytes=None, stream=None):
+        """ffp_parse_f64_noalloc into preallocated binary64 outputs: the call
+        that allocates nothing (texts of up to NOALLOC_MAX_BYTES)."""
+        import torch
+        assert text.is_cuda and text.dtype == torch.uint8 and text.is_contiguous()
+        assert values.dtype == torch.float64
+        nb = text.numel() if nbytes is None else nbytes
+        cap = min(values.numel(), status.numel())
+        return check(load().ffp_parse_f64_noalloc(self.handle, text.data_ptr(), nb,
+                                                  values.data_ptr(), status.data_ptr(), cap,
+                                                  count.data_ptr(), _stream_handle(stream)),
+                     "ffp_parse_f64_noalloc")
 
     # -- batched calls -------------------------------------------------
     def parse_batch(self, d_jobs, njobs, max_total_bytes, stream=None):
