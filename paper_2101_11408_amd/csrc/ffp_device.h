@@ -116,6 +116,66 @@ FFP_HD constexpr FormatRT format_of() {
                   F::kTieLo, F::kTieHi, F::kTieFallback ? 1 : 0, F::kSecondMask, F::kInf};
 }
 
+// ---------------------------------------------------------------------------
+// gfx950 instructions the lexer relies on, and wave-wide votes.  On the GPU
+// each is one instruction; the host build of the same logic (the CPU tests)
+// computes the same values in plain C, and takes its wave votes from a hook
+// the test installs (a single host "lane" stands for a wavefront whose other
+// lanes the test chooses).
+// ---------------------------------------------------------------------------
+FFP_HD uint32_t funnel_bits(uint32_t hi, uint32_t lo, uint32_t s) {  // v_alignbit_b32
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_alignbit(hi, lo, s);
+#else
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> (s & 31));
+#endif
+}
+
+FFP_HD uint32_t funnel_bytes(uint32_t hi, uint32_t lo, uint32_t s) {  // v_alignbyte_b32
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_alignbyte(hi, lo, s);
+#else
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * (s & 3)));
+#endif
+}
+
+FFP_HD uint32_t dot4_u8(uint32_t a, uint32_t b, uint32_t c) {  // v_dot4_u32_u8
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_udot4(a, b, c, false);
+#else
+  for (int i = 0; i < 4; ++i) c += ((a >> (8 * i)) & 0xFFu) * ((b >> (8 * i)) & 0xFFu);
+  return c;
+#endif
+}
+
+FFP_HD uint32_t mul_u24(uint32_t a, uint32_t b) {  // v_mul_u32_u24
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul24(a, b);
+#else
+  return (a & 0xFFFFFFu) * (b & 0xFFFFFFu);
+#endif
+}
+
+// Host build: the vote of the wavefront a host lane stands for (null: the
+// lane alone).  A host variable; device code never reads it.
+inline bool (*host_wave_vote)(bool pred, bool all) = nullptr;
+
+FFP_HD bool wave_all(bool p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __all(p);
+#else
+  return host_wave_vote ? host_wave_vote(p, true) : p;
+#endif
+}
+
+FFP_HD bool wave_any(bool p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __any(p);
+#else
+  return host_wave_vote ? host_wave_vote(p, false) : p;
+#endif
+}
+
 constexpr int kQMin = -342;  // table range, Section 5 and Appendix B
 constexpr int kQMax = 308;
 

@@ -282,15 +282,28 @@ __device__ FbToken fb_lex(const uint8_t* text, uint64_t nbytes, uint64_t pos, Fb
   for (;; pos += kFbWindow) {
     uint32_t wd[4];
     const uint64_t base = pos + 16 * (uint64_t)l;
+    // the lane's 16 bytes from the aligned words around them when those lie
+    // inside the text; byte by byte otherwise (bytes past the text read as a
+    // blank)
+    const uint32_t sh = (uint32_t)(((uintptr_t)text + base) & 3u);
+    if (base >= sh && base - sh + (sh ? 20u : 16u) <= nbytes) {
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(text + (base - sh));
+      const uint32_t x0 = w[0], x1 = w[1], x2 = w[2], x3 = w[3], x4 = sh ? w[4] : 0u;
+      wd[0] = __builtin_amdgcn_alignbyte(x1, x0, sh);
+      wd[1] = __builtin_amdgcn_alignbyte(x2, x1, sh);
+      wd[2] = __builtin_amdgcn_alignbyte(x3, x2, sh);
+      wd[3] = __builtin_amdgcn_alignbyte(x4, x3, sh);
+    } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint32_t w = 0;
+      for (int q = 0; q < 4; ++q) {
+        uint32_t w = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const uint64_t i = base + 4 * q + b;
-        w |= (i < nbytes ? (uint32_t)text[i] : (uint32_t)' ') << (8 * b);
+        for (int b = 0; b < 4; ++b) {
+          const uint64_t i = base + 4 * q + b;
+          w |= (i < nbytes ? (uint32_t)text[i] : (uint32_t)' ') << (8 * b);
+        }
+        wd[q] = w;
       }
-      wd[q] = w;
     }
     uint32_t dm = 0, dot = 0, em = 0, endm = 0;
 #pragma unroll
@@ -353,10 +366,15 @@ __device__ FbToken fb_lex(const uint8_t* text, uint64_t nbytes, uint64_t pos, Fb
 // ---------------------------------------------------------------------------
 // The decision.
 // ---------------------------------------------------------------------------
+// pow5: 5^(27 i) for i < kPow5Steps, kWave limbs each (lane i holds limb i).
+constexpr int kPow5Step = 27;
+constexpr int kPow5Steps = 43;
+
 template <class F>
 __device__ void fb_decide(const uint8_t* text, uint64_t nbytes, uint64_t pos,
-                          const unsigned long long* table, FbLds* lds, uint32_t flags,
-                          typename F::bits_t& out_bits, uint32_t& out_status) {
+                          const unsigned long long* table, const unsigned long long* pow5,
+                          FbLds* lds, uint32_t flags, typename F::bits_t& out_bits,
+                          uint32_t& out_status) {
   using Bits = typename F::bits_t;
   const int l = fb_lane();
   const FbToken t = fb_lex(text, nbytes, pos, lds);
@@ -410,12 +428,15 @@ __device__ void fb_decide(const uint8_t* text, uint64_t nbytes, uint64_t pos,
           }
           X = fbig_mul_add(X, p5, 0);
         }
-      } else {  // v = P * 2^f / 5^-f
-        for (int k = -f; k > 0; k -= 27) {
+      } else {  // v = P * 2^f / 5^-f: 5^(27 i) from the table, then the rest
+        int i = -f / kPow5Step;
+        if (i > kPow5Steps - 1) i = kPow5Steps - 1;
+        Y = pow5[i * kWave + l];
+        for (int k = -f - kPow5Step * i; k > 0; k -= 27) {
           uint64_t p5 = k5p27;
           if (k < 27) {
             p5 = 1;
-            for (int i = 0; i < k; ++i) p5 *= 5;
+            for (int r = 0; r < k; ++r) p5 *= 5;
           }
           Y = fbig_mul_add(Y, p5, 0);
         }
