@@ -156,11 +156,19 @@ Scratch own_scratch(const ffp_ctx* ctx) {
   return Scratch{ctx->d_block_sum, ctx->d_queue, ctx->queue_cap, ctx->d_state, false};
 }
 
+// Calls of at most this many blocks run without the scan kernel: each parse
+// workgroup sums the counts of its job's earlier blocks itself (one launch
+// less, which is most of a small call's time).
+constexpr uint64_t kSumInParseMaxBlocks = 1024;
+
 // count -> scan -> parse -> fallback for a job set whose block count is
-// `nblocks` (plain calls) or on the device (batched calls, nblocks = ~0).
+// `nblocks` (plain calls) or on the device (batched calls: nblocks is then
+// the scratch's bound and max_blocks the call's); small calls skip the scan.
 int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const CallShape& shape,
-                uint64_t nblocks, hipStream_t s) {
+                uint64_t nblocks, uint64_t max_blocks, hipStream_t s) {
   ctx->last_state = sc.state;
+  // (the parse kernel's 4 KiB-tile instances carry the summation)
+  const bool sum_in_parse = nblocks > 0 && max_blocks <= kSumInParseMaxBlocks && shape.tile_k == 1;
   ffp::ScanParams sp{};
   sp.js = js;
   sp.block_sum = sc.block_sum;
@@ -170,11 +178,13 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
     cp.js = js;
     cp.block_sum = sc.block_sum;
     cp.delim = ctx->delim;
+    cp.st = sc.state;
+    cp.reset_state = sum_in_parse ? 1u : 0u;
     uint64_t grid = (uint64_t)ctx->num_cus * 8;
     if (grid > nblocks) grid = nblocks;
     if (ffp::launch_count(ctx->delim.single != 0, cp, (int)grid, s) != hipSuccess) return FFP_E_HIP;
   }
-  if (ffp::launch_scan(sp, s) != hipSuccess) return FFP_E_HIP;
+  if (!sum_in_parse && ffp::launch_scan(sp, s) != hipSuccess) return FFP_E_HIP;
   if (nblocks == 0) return FFP_SUCCESS;
 
   ffp::ParseParams P{};
@@ -186,6 +196,7 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
   P.delim = ctx->delim;
   P.flags = ctx->flags;
   P.count_paths = ctx->counters && !sc.fixed ? 1u : 0u;
+  P.sum_in_parse = sum_in_parse ? 1u : 0u;
   P.reduce_out = js.jobs ? nullptr : ctx->reduce_out;  // plain calls only
   uint64_t grid = (uint64_t)shape.grid;
   if (grid > nblocks) grid = nblocks;
@@ -273,7 +284,7 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   js.block_shift = shape.block_shift;
   js.total_blocks = nblocks;
   js.total_blocks_dev = nullptr;
-  return launch_jobs(ctx, sc, js, shape, nblocks, (hipStream_t)stream);
+  return launch_jobs(ctx, sc, js, shape, nblocks, nblocks, (hipStream_t)stream);
 }
 
 int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_total_bytes,
@@ -302,7 +313,11 @@ int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_tot
   js.total_blocks_dev = reinterpret_cast<const uint64_t*>(&ctx->d_state->total_blocks);
   // grids are sized for the largest batch the scratch allows; kernels read
   // the true block count on the device
-  return launch_jobs(ctx, own_scratch(ctx), js, shape, ctx->block_cap - 1, s);
+  // the call's bound on its blocks (every job may start 15 bytes into its
+  // first block and end in a partial one)
+  const uint64_t max_blocks =
+      ((max_total_bytes + 15ull * njobs) >> shape.block_shift) + 2ull * njobs;
+  return launch_jobs(ctx, own_scratch(ctx), js, shape, ctx->block_cap - 1, max_blocks, s);
 }
 
 int64_t finish_sync(ffp_ctx* ctx, int rc, uint64_t capacity, uint64_t* d_count, void* stream) {

@@ -139,6 +139,8 @@ struct CountParams {
   JobSet js;
   uint64_t* block_sum;  // per block: tokens starting in it
   DelimSet delim;
+  DeviceState* st;      // reset here when the call runs without the scan kernel
+  uint32_t reset_state;
 };
 
 struct ScanParams {
@@ -157,6 +159,11 @@ struct ParseParams {
   uint32_t flags;           // FFP_REJECT_PLUS ...
   uint32_t count_paths;
   uint64_t* reduce_out;     // plain calls: min, max, count of the values (or null)
+  // Small calls (4 KiB tiles) run without the scan kernel: block_prefix
+  // then holds each block's own token count, every workgroup sums the counts
+  // of its job's earlier blocks, and the workgroup of a job's last block
+  // writes the job's count (and the capacity error).
+  uint32_t sum_in_parse;
 };
 
 struct FallbackParams {

@@ -197,6 +197,16 @@ __device__ __forceinline__ uint32_t prev_nondelim(const uint8_t* vbase, uint64_t
   return is_delim(d, gload(vbase + off - 1)) ? 0u : 1u;
 }
 
+// The call's device state starts clean: the parse kernel appends to the
+// queue and raises error bits; the reduction starts from its identities.
+__device__ __forceinline__ void reset_call_state(DeviceState* st) {
+  st->queue_tail = 0;
+  st->error = 0;
+  st->red_min = ~0ull;
+  st->red_max = 0;
+  st->red_count = 0;
+}
+
 // ---------------------------------------------------------------------------
 // k_count: tokens starting in each block.  Each thread classifies kRows
 // chunks of 16 bytes (kRows = block bytes / 4 KiB); the start mask of a chunk
@@ -214,6 +224,7 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
   if (!kSingle)
     for (int i = tid; i < 256; i += kThreads) s_lut[i] = is_delim(P.delim, (uint32_t)i);
   const uint32_t drep = P.delim.byte * 0x01010101u;
+  if (P.reset_state && blockIdx.x == 0 && tid == 0) reset_call_state(P.st);
   const uint64_t nblk = total_blocks_of(P.js);
   for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const JobDesc job = job_of_block(P.js, b);
@@ -261,13 +272,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
   const uint64_t n = total_blocks_of(P.js);
   if (tid == 0) {
     s_carry = 0;
-    // the call's device state starts clean (the parse kernel appends to the
-    // queue and raises error bits; the reduction starts from its identities)
-    P.st->queue_tail = 0;
-    P.st->error = 0;
-    P.st->red_min = ~0ull;
-    P.st->red_max = 0;
-    P.st->red_count = 0;
+    reset_call_state(P.st);
   }
   for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * kScanPer) {
     uint64_t v[kScanPer];
@@ -476,7 +481,28 @@ k_parse(ParseParams P) {
     const uint64_t nbytes = job.nbytes;
     const uint64_t vend = nbytes + align;
     const uint64_t bstart = (blk - job.block_begin) << P.js.block_shift;
-    uint64_t next_idx = P.block_prefix[blk] - P.block_prefix[job.block_begin];
+    uint64_t next_idx;
+    if (K == 1 && P.sum_in_parse) {  // small calls: 4 KiB blocks, one tile each
+      // the counts of this job's earlier blocks, summed by the workgroup
+      uint64_t part = 0;
+      for (uint64_t i = job.block_begin + tid; i < blk; i += kThreads) part += P.block_prefix[i];
+      part = wave_sum_u64(part);
+      __syncthreads();  // sm.red_part of the previous block is consumed
+      if (lane == 0) sm.red_part[tid / kWave] = part;
+      __syncthreads();
+      next_idx = 0;
+#pragma unroll
+      for (int w = 0; w < kThreads / kWave; ++w) next_idx += sm.red_part[w];
+      if (tid == 0 && blk + 1 == job.block_begin + job_blocks(job, P.js.block_shift)) {
+        // the job's last block: its token count and the capacity check
+        const uint64_t count = next_idx + P.block_prefix[blk];
+        *job.count_out = count;
+        // a queue overflow reported by another workgroup takes precedence
+        if (job.err_out && count > job.capacity) atomicCAS(job.err_out, 0, kErrCapacity);
+      }
+    } else {
+      next_idx = P.block_prefix[blk] - P.block_prefix[job.block_begin];
+    }
     const GlobalSrc gsrc{job.text, nbytes, P.delim};
 
     // A tile's chunks are loaded at the top of its iteration; the other

@@ -88,6 +88,7 @@ struct TileSmem {
   uint32_t prev_nd;
   uint32_t ext_end;  // the extension holds a delimiter
   unsigned long long red_min, red_max, red_count;  // this workgroup's reduction
+  unsigned long long red_part[kThreads / kWave];    // per-wave sums of block counts
 };
 
 struct LdsSrc {
