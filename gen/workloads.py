@@ -483,3 +483,53 @@ def hex_tokens(rng, n: int):
             toks.append("0x%x.%xp%d" % (int(rng.integers(0, 2 ** 16)), int(rng.integers(0, 2 ** 20)),
                                         int(rng.integers(-30, 30))))
     return toks
+
+
+def json_tricky_document(seed: int, nitems: int, indent=None, long_strings=False) -> bytes:
+    """A JSON document whose strings and keys hold digits, commas, colons,
+    brackets, escaped quotes, backslash runs and unicode escapes, next to
+    numbers of every JSON form (integers, fractions, exponents, signs),
+    true/false/null and nested containers.  With long_strings some strings
+    run for thousands of bytes (across tiles and blocks) and end in long
+    backslash runs."""
+    import json
+
+    rng = np.random.default_rng(seed)
+    pieces = ["12", "3,4", "5.6e7", '"', '\\', '\\"', "-0", ":", "[", "]", "{", "}", " ",
+              "é", "☃", "true", "1e5", "x", "\t", "\n"]
+
+    def rstring():
+        k = int(rng.integers(0, 8))
+        s = "".join(pieces[int(i)] for i in rng.integers(0, len(pieces), k))
+        if long_strings and rng.random() < 0.05:
+            s += "".join(pieces[int(i)] for i in rng.integers(0, len(pieces), 2000))
+            s += "\\" * int(rng.integers(1, 40))
+        return s
+
+    def rnumber():
+        r = rng.random()
+        if r < 0.3:
+            return int(rng.integers(-10 ** 12, 10 ** 12))
+        if r < 0.6:
+            return float(rng.standard_normal() * 10.0 ** int(rng.integers(-30, 30)))
+        if r < 0.7:
+            return int(rng.integers(0, 10))
+        if r < 0.8:
+            return float(rng.uniform(-180, 180))
+        return float(rng.random())
+
+    def value(depth):
+        r = rng.random()
+        if depth < 3 and r < 0.15:
+            return [value(depth + 1) for _ in range(int(rng.integers(0, 6)))]
+        if depth < 3 and r < 0.3:
+            return {rstring(): value(depth + 1) for _ in range(int(rng.integers(0, 5)))}
+        if r < 0.55:
+            return rnumber()
+        if r < 0.8:
+            return rstring()
+        return [True, False, None][int(rng.integers(0, 3))]
+
+    doc = [value(0) for _ in range(nitems)]
+    ensure_ascii = bool(rng.random() < 0.5)
+    return (json.dumps(doc, indent=indent, ensure_ascii=ensure_ascii) + "\n").encode()

@@ -32,13 +32,16 @@ from .grammar import (
     FLAG_HEX,
     FLAG_INFNAN,
     FLAG_JSON,
+    FLAG_JSON_DOCUMENT,
     FLAG_REJECT_PLUS,
     FLAG_ROUND_DOWN,
     FLAG_ROUND_MASK,
     FLAG_ROUND_TOWARD_ZERO,
     FLAG_ROUND_UP,
     decompose,
+    json_number_spans,
     parse_buffer,
+    parse_json_document,
     parse_token,
     rounding_mode,
     split_tokens,
@@ -52,6 +55,7 @@ __all__ = [
     "FLAG_HEX",
     "FLAG_INFNAN",
     "FLAG_JSON",
+    "FLAG_JSON_DOCUMENT",
     "FLAG_REJECT_PLUS",
     "FLAG_ROUND_DOWN",
     "FLAG_ROUND_MASK",
@@ -69,7 +73,9 @@ __all__ = [
     "STATUS_OK",
     "STATUS_OUT_OF_RANGE",
     "decompose",
+    "json_number_spans",
     "parse_buffer",
+    "parse_json_document",
     "parse_token",
     "round_decimal",
     "split_tokens",

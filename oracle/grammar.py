@@ -174,3 +174,52 @@ __all__ = [
     "parse_token",
     "split_tokens",
 ]
+
+
+# ---------------------------------------------------------------------------
+# JSON documents (structural index).  Number tokens of a JSON text are the
+# runs of bytes outside strings that are neither structural characters,
+# whitespace nor quotes, and that start with '-' or a digit (true, false and
+# null start with a letter).  A quote preceded by an odd number of
+# consecutive backslashes is escaped: it neither opens nor closes a string
+# (inside a string that is JSON's escape rule).  Each number token is read
+# with the JSON number grammar.  The library contract for documents; the
+# paper's benchmark reads such a file (Section 12).
+# ---------------------------------------------------------------------------
+FLAG_JSON_DOCUMENT = 0x40
+JSON_STRUCTURE = b"[]{},:"
+JSON_WHITESPACE = b" \t\n\r"
+
+
+def json_number_spans(buf: bytes):
+    """(start, end) of every number token of a JSON text, in order."""
+    spans = []
+    in_string = False
+    backslashes = 0  # consecutive backslashes just before the current byte
+    start = -1       # start of the run being read, -1 outside a run
+    for i, c in enumerate(buf):
+        quote = c == 0x22 and backslashes % 2 == 0
+        token_byte = not in_string and not quote and c not in JSON_STRUCTURE \
+            and c not in JSON_WHITESPACE
+        if quote:
+            in_string = not in_string
+        backslashes = backslashes + 1 if c == 0x5C else 0
+        if token_byte and start < 0:
+            start = i
+        elif not token_byte and start >= 0:
+            spans.append((start, i))
+            start = -1
+    if start >= 0:
+        spans.append((start, len(buf)))
+    return [(a, b) for a, b in spans if buf[a] == 0x2D or 0x30 <= buf[a] <= 0x39]
+
+
+def parse_json_document(buf: bytes, fmt="f64", flags: int = 0):
+    """(bits list, status list) of the number tokens of a JSON text, each
+    read with the JSON number grammar."""
+    bits, status = [], []
+    for a, b in json_number_spans(buf):
+        v, s = parse_token(buf[a:b], fmt, flags | FLAG_JSON)
+        bits.append(v)
+        status.append(s)
+    return bits, status
