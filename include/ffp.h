@@ -80,6 +80,19 @@ enum ffp_error {
  * rounded in the context's rounding direction (exact; no table, no
  * fallback). */
 #define FFP_HEX 8u
+/* JSON documents (a structural index of the numbers of a JSON text, the
+ * paper's canada file being one, Section 12): the buffer is JSON text; bytes
+ * inside strings are skipped, a quote preceded by an odd number of
+ * consecutive backslashes is escaped (it neither opens nor closes a string),
+ * and the tokens are the runs outside strings of bytes other than the
+ * structural characters [ ] { } , : whitespace (space, tab, CR, LF) and
+ * unescaped quotes that start with '-' or a digit -- the number literals, in
+ * document order (keys, strings, true, false and null get no index).  Each is
+ * read with the JSON number grammar (FFP_JSON is implied).  The context's
+ * delimiter set is replaced by the structural characters, whitespace and the
+ * quote.  Plain calls only: batched calls and servers on such a context
+ * return FFP_E_ARG. */
+#define FFP_JSON_DOCUMENT 0x40u
 /* Rounding direction, a two-bit field of the flags (IEEE 754 rounding-
  * direction attributes; the paper rounds to nearest and notes that its
  * method extends to the other modes, footnote of Section 6).  0 selects

@@ -102,6 +102,8 @@ bool plain_instance(const ffp_ctx* ctx, bool reduce) {
 // has too few of them to fill a round, and each round lasts as long as its
 // longest token, so such calls take 16 KiB tiles too (capacity 0: unknown).
 int auto_tile_k(const ffp_ctx* ctx, bool reduce, uint64_t bytes = 0, uint64_t capacity = 0) {
+  // JSON documents: 8 KiB tiles (the 16 KiB instance spills registers)
+  if (ctx->flags & FFP_JSON_DOCUMENT) return 2;
   const bool long_tokens = capacity > 0 && bytes / capacity >= 64;
   return plain_instance(ctx, reduce) && !long_tokens ? 2 : 4;
 }
@@ -168,11 +170,15 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
                 uint64_t nblocks, uint64_t max_blocks, hipStream_t s) {
   ctx->last_state = sc.state;
   // (the parse kernel's 4 KiB-tile instances carry the summation)
-  const bool sum_in_parse = nblocks > 0 && max_blocks <= kSumInParseMaxBlocks && shape.tile_k == 1;
+  // (JSON documents need the scan: it gives each block its string state)
+  const bool json_doc = (ctx->flags & FFP_JSON_DOCUMENT) != 0;
+  const bool sum_in_parse = nblocks > 0 && max_blocks <= kSumInParseMaxBlocks &&
+                            shape.tile_k == 1 && !json_doc;
   ffp::ScanParams sp{};
   sp.js = js;
   sp.block_sum = sc.block_sum;
   sp.st = sc.state;
+  sp.json_doc = json_doc ? 1u : 0u;
   if (nblocks > 0) {
     ffp::CountParams cp{};
     cp.js = js;
@@ -180,6 +186,7 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
     cp.delim = ctx->delim;
     cp.st = sc.state;
     cp.reset_state = sum_in_parse ? 1u : 0u;
+    cp.json_doc = json_doc ? 1u : 0u;
     uint64_t grid = (uint64_t)ctx->num_cus * 8;
     if (grid > nblocks) grid = nblocks;
     if (ffp::launch_count(ctx->delim.single != 0, cp, (int)grid, s) != hipSuccess) return FFP_E_HIP;
@@ -291,6 +298,7 @@ int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_tot
                  hipStream_t s) {
   if (!ctx || !d_jobs || njobs == 0 || njobs > kMaxJobs) return FFP_E_ARG;
   if (max_total_bytes >= kMaxBatchBytes) return FFP_E_ARG;
+  if (ctx->flags & FFP_JSON_DOCUMENT) return FFP_E_ARG;  // plain calls only
   DeviceGuard g(ctx->device);
   // at least two jobs' worth of job table, so that grow() sizes it
   int rc = grow(ctx, max_total_bytes, njobs < 2 ? 2 : njobs);
@@ -483,8 +491,17 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   } else {
     o.delim_set['\n' >> 6] |= 1ull << ('\n' & 63);
   }
-  if (o.flags & ~(FFP_REJECT_PLUS | FFP_JSON | FFP_INFNAN | FFP_HEX | FFP_ROUND_MASK))
+  if (o.flags & ~(FFP_REJECT_PLUS | FFP_JSON | FFP_INFNAN | FFP_HEX | FFP_ROUND_MASK |
+                  FFP_JSON_DOCUMENT))
     return FFP_E_ARG;
+  if (o.flags & FFP_JSON_DOCUMENT) {
+    // JSON text: the structural characters, whitespace and the quote delimit
+    // the number tokens; the JSON number grammar applies
+    o.flags |= FFP_JSON;
+    for (int i = 0; i < 4; ++i) o.delim_set[i] = 0;
+    for (const char* c = "[]{},: \t\r\n\""; *c; ++c)
+      o.delim_set[(unsigned char)*c >> 6] |= 1ull << ((unsigned char)*c & 63);
+  }
   int members = 0, first = -1;
   for (int c = 0; c < 256; ++c) {
     if ((o.delim_set[c >> 6] >> (c & 63)) & 1) {

@@ -141,12 +141,20 @@ struct CountParams {
   DelimSet delim;
   DeviceState* st;      // reset here when the call runs without the scan kernel
   uint32_t reset_state;
+  uint32_t json_doc;    // FFP_JSON_DOCUMENT: counts for both entry states
 };
+
+// JSON documents: a block's count word holds the tokens starting in it when
+// it begins outside a string (bits 0-31) and inside one (bits 32-62), and
+// the parity of its unescaped quotes (bit 63); after the scan, the prefix
+// (bits 0-62) and whether the block begins inside a string (bit 63).
+constexpr uint64_t kPrefixMask = ~0ull >> 1;
 
 struct ScanParams {
   JobSet js;
   uint64_t* block_sum;  // in: counts; out: exclusive prefix over all blocks
   DeviceState* st;
+  uint32_t json_doc;    // count words of JSON documents (see kPrefixMask)
 };
 
 struct ParseParams {

@@ -190,6 +190,78 @@ __device__ __forceinline__ uint32_t nondelim_mask16(uint4 v, uint32_t drep, cons
                         nondelim_word_lut(v.z, lut), nondelim_word_lut(v.w, lut));
 }
 
+// ---------------------------------------------------------------------------
+// JSON documents (FFP_JSON_DOCUMENT).  A quote preceded by an odd number of
+// consecutive backslashes is escaped; the others open and close strings.
+// Token bytes are the non-delimiters (escaped quotes included) outside
+// strings, and a token must start with '-' or a digit.
+// ---------------------------------------------------------------------------
+
+// Whether the quote at text[pos] is escaped: the backslashes right before it,
+// walked back one by one inside the text.
+__device__ __forceinline__ bool quote_escaped(const uint8_t* text, uint64_t pos) {
+  uint32_t odd = 0;
+  while (pos > 0 && gload(text + pos - 1) == '\\') {
+    --pos;
+    odd ^= 1u;
+  }
+  return odd != 0;
+}
+
+struct DocBits {
+  uint32_t uq;  // unescaped quotes
+  uint32_t eq;  // escaped quotes (ordinary bytes)
+  uint32_t ms;  // bytes a number may start with: '-' and digits
+};
+
+// Quote classes of the 16 bytes v whose first byte is text[pos] (pos < 0 for
+// padding before the text: padding holds no quote).  dgm: the digit mask.
+__device__ __forceinline__ DocBits doc_chunk(uint4 v, uint32_t dgm, const uint8_t* text,
+                                             int64_t pos) {
+  constexpr uint32_t kQ = '"' * 0x01010101u, kB = '\\' * 0x01010101u, kM = '-' * 0x01010101u;
+  const uint32_t qm = pack_high_bits(byte_eq_word(v.x, kQ), byte_eq_word(v.y, kQ),
+                                     byte_eq_word(v.z, kQ), byte_eq_word(v.w, kQ));
+  DocBits d;
+  d.uq = qm;
+  d.eq = 0;
+  d.ms = dgm | pack_high_bits(byte_eq_word(v.x, kM), byte_eq_word(v.y, kM),
+                              byte_eq_word(v.z, kM), byte_eq_word(v.w, kM));
+  if (qm) {
+    const uint32_t bm = pack_high_bits(byte_eq_word(v.x, kB), byte_eq_word(v.y, kB),
+                                       byte_eq_word(v.z, kB), byte_eq_word(v.w, kB));
+    // quotes right after a backslash may be escaped
+    uint32_t cand = qm & (bm << 1);
+    if ((qm & 1u) && pos > 0 && gload(text + pos - 1) == '\\') cand |= 1u;
+    while (cand) {
+      const int k = __builtin_ctz(cand);
+      cand &= cand - 1;
+      if (quote_escaped(text, (uint64_t)(pos + k))) {
+        d.uq &= ~(1u << k);
+        d.eq |= 1u << k;
+      }
+    }
+  }
+  return d;
+}
+
+// Bytes inside a string among 16 whose unescaped quotes are uq, given the
+// state before the first of them (an opening quote is outside, a closing
+// one inside).
+__device__ __forceinline__ uint32_t doc_in_string(uint32_t uq, uint32_t carry) {
+  const uint32_t before = (prefix_xor16(uq) << 1) & 0xFFFFu;
+  return carry ? (~before & 0xFFFFu) : before;
+}
+
+// Whether the byte before text[pos] is a token byte, for a position whose
+// string state is `in_string`.
+__device__ __forceinline__ uint32_t doc_prev_token(const uint8_t* text, int64_t pos,
+                                                   uint32_t in_string, const DelimSet& d) {
+  if (pos <= 0 || in_string) return 0;
+  const uint32_t c = gload(text + pos - 1);
+  if (c == '"') return quote_escaped(text, (uint64_t)(pos - 1)) ? 1u : 0u;
+  return is_delim(d, c) ? 0u : 1u;
+}
+
 // Is the byte just before virtual offset off a non-delimiter?
 __device__ __forceinline__ uint32_t prev_nondelim(const uint8_t* vbase, uint64_t off,
                                                   uint64_t align, const DelimSet& d) {
@@ -212,6 +284,72 @@ __device__ __forceinline__ void reset_call_state(DeviceState* st) {
 // chunks of 16 bytes (kRows = block bytes / 4 KiB); the start mask of a chunk
 // needs the last bit of the chunk before it, exchanged through LDS.
 // ---------------------------------------------------------------------------
+// k_count for JSON documents: per block, the tokens starting in it if it
+// begins outside a string and if it begins inside one, and the parity of its
+// unescaped quotes.  Rows of 256 chunks are scanned one after the other for
+// the string state; s_tb (a byte per chunk) passes the last token bit of
+// each chunk, for both entry states, to the next chunk's thread.
+template <int kRows>
+__device__ void count_json_doc(const CountParams& P, const uint8_t* lut, uint32_t* s_scan,
+                               uint8_t* s_tb) {
+  constexpr uint32_t kShift = kRows == 1 ? 12 : (kRows == 4 ? 14 : 16);
+  __shared__ uint32_t s_prev2;
+  const int tid = threadIdx.x;
+  const uint64_t nblk = total_blocks_of(P.js);
+  for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const JobDesc job = job_of_block(P.js, b);
+    const uint64_t align = (uint64_t)(uintptr_t)job.text & 15u;
+    const uint8_t* vbase = job.text - align;
+    const uint64_t vend = job.nbytes + align;
+    const uint64_t bstart = (b - job.block_begin) << kShift;
+    __syncthreads();  // s_tb / s_prev2 / s_scan of the previous block are consumed
+    uint32_t t0[kRows], t1[kRows], ms[kRows];
+    uint32_t parity = 0;  // unescaped quotes before the row, mod 2
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const uint64_t off = bstart + (uint64_t)(r * kThreads + tid) * kChunk;
+      uint32_t base = 0, uq = 0;
+      ms[r] = 0;
+      if (off < vend) {
+        const uint4 v = load_chunk(vbase, off, align, vend, P.delim.byte);
+        const uint32_t dgm = pack_high_bits(digit_word(v.x), digit_word(v.y), digit_word(v.z),
+                                            digit_word(v.w));
+        const DocBits d = doc_chunk(v, dgm, job.text, (int64_t)off - (int64_t)align);
+        base = nondelim_mask16<false>(v, 0u, lut) | d.eq;
+        uq = d.uq;
+        ms[r] = d.ms;
+      }
+      uint32_t rowq;
+      const uint32_t ex = block_excl_scan<kThreads>((uint32_t)__popc(uq), rowq, s_scan);
+      const uint32_t in0 = doc_in_string(uq, (parity + ex) & 1u);
+      t0[r] = base & ~in0;
+      t1[r] = base & in0;
+      s_tb[r * kThreads + tid] = (uint8_t)(((t0[r] >> 15) & 1u) | (((t1[r] >> 15) & 1u) << 1));
+      parity = (parity + rowq) & 1u;
+      __syncthreads();  // s_scan is read before the next row writes it
+    }
+    if (tid == 0) {
+      const int64_t pos = (int64_t)bstart - (int64_t)align;
+      s_prev2 = doc_prev_token(job.text, pos, 0u, P.delim) |
+                (doc_prev_token(job.text, pos, 1u, P.delim) << 1);
+    }
+    __syncthreads();
+    uint32_t n0 = 0, n1 = 0;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const int chunk = r * kThreads + tid;
+      const uint32_t pb = chunk == 0 ? s_prev2 : (uint32_t)s_tb[chunk - 1];
+      n0 += __popc(t0[r] & ~((t0[r] << 1) | (pb & 1u)) & ms[r] & 0xFFFFu);
+      n1 += __popc(t1[r] & ~((t1[r] << 1) | (pb >> 1)) & ms[r] & 0xFFFFu);
+    }
+    uint32_t total;
+    (void)block_excl_scan<kThreads>(n0 | (n1 << 16), total, s_scan);
+    if (tid == 0)
+      P.block_sum[b] = (uint64_t)(total & 0xFFFFu) | ((uint64_t)(total >> 16) << 32) |
+                       ((uint64_t)parity << 63);
+  }
+}
+
 template <bool kSingle, int kRows>
 __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
   constexpr int kCountRows = kRows;
@@ -226,6 +364,10 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
   const uint32_t drep = P.delim.byte * 0x01010101u;
   if (P.reset_state && blockIdx.x == 0 && tid == 0) reset_call_state(P.st);
   const uint64_t nblk = total_blocks_of(P.js);
+  if (!kSingle && P.json_doc) {
+    count_json_doc<kRows>(P, s_lut, s_scan, reinterpret_cast<uint8_t*>(s_nd));
+    return;
+  }
   for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
     const JobDesc job = job_of_block(P.js, b);
     const uint64_t align = (uint64_t)(uintptr_t)job.text & 15u;
@@ -270,18 +412,46 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
   __shared__ uint64_t s_carry;
   const int tid = threadIdx.x;
   const uint64_t n = total_blocks_of(P.js);
+  __shared__ uint32_t s_parity;  // JSON documents: inside a string before the round
   if (tid == 0) {
     s_carry = 0;
+    s_parity = 0;
     reset_call_state(P.st);
   }
   for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * kScanPer) {
     uint64_t v[kScanPer];
     uint64_t sum = 0;
+    uint32_t entry = 0;  // JSON documents: the blocks' string states (bit i)
+    if (P.json_doc) {
+      // a block begins inside a string when the quotes before it are odd in
+      // number; its count is the one for that state
+      uint32_t par = 0;
 #pragma unroll
-    for (int i = 0; i < kScanPer; ++i) {
-      const uint64_t k = base + (uint64_t)tid * kScanPer + i;
-      v[i] = k < n ? P.block_sum[k] : 0;
-      sum += v[i];
+      for (int i = 0; i < kScanPer; ++i) {
+        const uint64_t k = base + (uint64_t)tid * kScanPer + i;
+        v[i] = k < n ? P.block_sum[k] : 0;
+        par += (uint32_t)(v[i] >> 63);
+      }
+      __syncthreads();  // s_parity of the previous round is final
+      uint32_t ptotal;
+      uint32_t run = s_parity + block_excl_scan<kScanThreads>(par, ptotal, s_scan);
+#pragma unroll
+      for (int i = 0; i < kScanPer; ++i) {
+        const uint32_t in = run & 1u;
+        entry |= in << i;
+        run += (uint32_t)(v[i] >> 63);
+        v[i] = in ? (v[i] >> 32) & 0x7FFFFFFFull : v[i] & 0xFFFFFFFFull;
+        sum += v[i];
+      }
+      __syncthreads();  // s_scan is read before the count scan writes it
+      if (tid == 0) s_parity = (s_parity + ptotal) & 1u;
+    } else {
+#pragma unroll
+      for (int i = 0; i < kScanPer; ++i) {
+        const uint64_t k = base + (uint64_t)tid * kScanPer + i;
+        v[i] = k < n ? P.block_sum[k] : 0;
+        sum += v[i];
+      }
     }
     __syncthreads();  // s_carry of the previous round is final
     const uint64_t carry = s_carry;
@@ -293,7 +463,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
 #pragma unroll
     for (int i = 0; i < kScanPer; ++i) {
       const uint64_t k = base + (uint64_t)tid * kScanPer + i;
-      if (k < n) P.block_sum[k] = run;
+      if (k < n) P.block_sum[k] = run | ((uint64_t)((entry >> i) & 1u) << 63);
       run += v[i];
     }
     __syncthreads();
@@ -501,8 +671,11 @@ k_parse(ParseParams P) {
         if (job.err_out && count > job.capacity) atomicCAS(job.err_out, 0, kErrCapacity);
       }
     } else {
-      next_idx = P.block_prefix[blk] - P.block_prefix[job.block_begin];
+      next_idx = (P.block_prefix[blk] & kPrefixMask) - (P.block_prefix[job.block_begin] & kPrefixMask);
     }
+    // JSON documents: whether the block begins inside a string
+    constexpr bool doc = kMode == kModeDoc;
+    const uint32_t block_entry = doc ? (uint32_t)(P.block_prefix[blk] >> 63) : 0u;
     const GlobalSrc gsrc{job.text, nbytes, P.delim};
 
     // A tile's chunks are loaded at the top of its iteration; the other
@@ -511,7 +684,10 @@ k_parse(ParseParams P) {
     // measured no faster.)
     uint4 pre[K];
     // the byte before the block, loaded with the block's first chunks
-    const uint32_t block_prev = tid == 0 ? prev_nondelim(vbase, bstart, align, P.delim) : 0u;
+    const uint32_t block_prev =
+        tid != 0 ? 0u
+        : doc    ? doc_prev_token(job.text, (int64_t)bstart - (int64_t)align, block_entry, P.delim)
+                 : prev_nondelim(vbase, bstart, align, P.delim);
     for (int t = 0; t < ntiles; ++t) {
       const uint64_t tile_start = bstart + (uint64_t)t * S::kBytes;  // virtual
       if (tile_start >= vend) break;
@@ -531,7 +707,7 @@ k_parse(ParseParams P) {
       }
       __syncthreads();  // LDS of the previous tile is consumed
       // -- store the tile to LDS and classify bytes ---------------------
-      uint32_t ndm[K];
+      uint32_t ndm[K], dgm[K];
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         const int chunk = c * kThreads + tid;
@@ -539,8 +715,41 @@ k_parse(ParseParams P) {
         *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + chunk * kChunk]) = v;
         ndm[c] = nondelim_mask16<kSingle>(v, drep, sm.delim_lut);
         sm.nd[chunk] = (uint16_t)ndm[c];
-        sm.dg[chunk] = (uint16_t)pack_high_bits(digit_word(v.x), digit_word(v.y),
-                                                digit_word(v.z), digit_word(v.w));
+        dgm[c] = pack_high_bits(digit_word(v.x), digit_word(v.y), digit_word(v.z), digit_word(v.w));
+        sm.dg[chunk] = (uint16_t)dgm[c];
+      }
+      // JSON documents: token bytes are the non-delimiters outside strings;
+      // the string state of each chunk comes from a block scan of its
+      // unescaped quotes (sm.starts holds the token bitmaps until the
+      // token starts are written)
+      uint32_t tbm[K], msm[K], tile_last_tb = 0, tile_end_str = 0;
+      if (doc) {
+        uint32_t uq[K];
+        Packed pq = 0;
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          const int chunk = c * kThreads + tid;
+          const DocBits d = doc_chunk(pre[c], dgm[c], job.text,
+                                      (int64_t)(tile_start + (uint64_t)chunk * kChunk) - (int64_t)align);
+          uq[c] = d.uq;
+          tbm[c] = ndm[c] | d.eq;
+          msm[c] = d.ms;
+          pq |= (Packed)__popc(d.uq) << (16 * c);
+        }
+        Packed totq;
+        const Packed exq = block_excl_scan<kThreads>(pq, totq, sm.scan);
+        const uint32_t carry_in = t == 0 ? block_entry : sm.prev_str;
+        uint32_t rowq = 0;
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          const int chunk = c * kThreads + tid;
+          const uint32_t cin = (carry_in + rowq + ((uint32_t)(exq >> (16 * c)) & 0xFFFFu)) & 1u;
+          tbm[c] &= ~doc_in_string(uq[c], cin);
+          sm.starts[chunk] = (uint16_t)tbm[c];
+          rowq += (uint32_t)(totq >> (16 * c)) & 0xFFFFu;
+        }
+        tile_last_tb = (tbm[K - 1] >> 15) & 1u;
+        tile_end_str = (carry_in + rowq) & 1u;
       }
       const uint64_t next_start = tile_start + S::kBytes;
       // wave 0 loads the extension (the 1 KiB after the tile: the next
@@ -559,9 +768,12 @@ k_parse(ParseParams P) {
       for (int c = 0; c < K; ++c) {
         const int chunk = c * kThreads + tid;
         const uint32_t prevbit =
-            chunk == 0 ? sm.prev_nd : ((uint32_t)sm.nd[chunk - 1] >> 15) & 1u;
-        const uint32_t m = ndm[c];
+            chunk == 0 ? sm.prev_nd
+            : doc      ? ((uint32_t)sm.starts[chunk - 1] >> 15) & 1u
+                       : ((uint32_t)sm.nd[chunk - 1] >> 15) & 1u;
+        const uint32_t m = doc ? tbm[c] : ndm[c];
         startm[c] = m & ~((m << 1) | prevbit) & 0xFFFFu;
+        if (doc) startm[c] &= msm[c];  // numbers start with '-' or a digit
         packed |= (Packed)__popc(startm[c]) << (16 * c);
       }
       Packed total_packed;
@@ -674,7 +886,14 @@ k_parse(ParseParams P) {
         }
       }
       next_idx += ntok;
-      if (tid == 0) sm.prev_nd = (sm.nd[S::kChunks - 1] >> 15) & 1u;
+      if (doc) {
+        if (tid == kThreads - 1) {  // the thread of the tile's last chunk
+          sm.prev_nd = tile_last_tb;
+          sm.prev_str = tile_end_str;
+        }
+      } else if (tid == 0) {
+        sm.prev_nd = (sm.nd[S::kChunks - 1] >> 15) & 1u;
+      }
     }
   }
 
@@ -848,6 +1067,13 @@ hipError_t launch_scan(const ScanParams& P, hipStream_t s) {
 
 template <int K, bool kSingle, bool kReduce>
 static void launch_parse_mode(const ParseParams& P, int grid, hipStream_t s) {
+  if constexpr (!kSingle) {  // JSON documents: a delimiter set of many bytes
+    if (P.flags & kFlagJsonDoc) {
+      hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModeDoc>), dim3(grid), dim3(kThreads), 0,
+                         s, P);
+      return;
+    }
+  }
   if (P.flags & (kFlagHex | kFlagRoundMask))
     hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModeExt>), dim3(grid), dim3(kThreads), 0, s, P);
   else if (P.flags & (kFlagJson | kFlagInfNan))

@@ -40,6 +40,23 @@ FFP_HD uint32_t nondelim_word_lut(uint32_t x, const uint8_t* lut) {
   return h;
 }
 
+// High bit of each byte of x set where the byte equals c (crep = c repeated
+// in the four bytes): y = x ^ crep is zero exactly there; its low seven bits
+// plus 0x7F carry into bit 7 when nonzero, and y's own bit 7 covers the rest.
+FFP_HD uint32_t byte_eq_word(uint32_t x, uint32_t crep) {
+  const uint32_t y = x ^ crep;
+  return ~(((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y) & 0x80808080u;
+}
+
+// Bit i of the result: parity of bits 0..i of a 16-bit mask.
+FFP_HD uint32_t prefix_xor16(uint32_t x) {
+  x ^= x << 1;
+  x ^= x << 2;
+  x ^= x << 4;
+  x ^= x << 8;
+  return x & 0xFFFFu;
+}
+
 // Gather the high bits of the bytes of four words into a 16-bit mask: byte
 // dot products with weights 1..128 put bytes 8..15 at bits 7..14 of `hi`;
 // shifted up by 8 it is the accumulator of the same for bytes 0..7.
@@ -85,7 +102,8 @@ struct TileSmem {
   alignas(8) uint16_t dg[kChunks + kExtChunks + 8];  // ASCII digit
   uint8_t delim_lut[256];
   Packed scan[kThreads / kWave];
-  uint32_t prev_nd;
+  uint32_t prev_nd;   // the byte before the tile is a token byte
+  uint32_t prev_str;  // JSON documents: the tile begins inside a string
   uint32_t ext_end;  // the extension holds a delimiter
   unsigned long long red_min, red_max, red_count;  // this workgroup's reduction
   unsigned long long red_part[kThreads / kWave];    // per-wave sums of block counts
@@ -178,7 +196,7 @@ FFP_HD uint64_t digits_before(const TileSmem<K>& sm, int end, int n) {
 constexpr uint32_t kFastOk = 0, kFastInvalid = 1, kFastSlow = 2;
 
 // Lexing modes of the parse kernel's instances (see k_parse).
-constexpr int kModePlain = 0, kModeGrammar = 1, kModeExt = 2;
+constexpr int kModePlain = 0, kModeGrammar = 1, kModeExt = 2, kModeDoc = 3;
 
 struct FastLex {
   uint64_t w;

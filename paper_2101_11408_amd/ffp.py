@@ -36,6 +36,7 @@ FFP_REJECT_PLUS = 1
 FFP_JSON = 2
 FFP_INFNAN = 4
 FFP_HEX = 8
+FFP_JSON_DOCUMENT = 0x40
 FFP_ROUND_MASK = 0x30
 FFP_ROUND_NEAREST = 0x00
 FFP_ROUND_TOWARD_ZERO = 0x10

@@ -846,3 +846,68 @@ def test_high_bytes_and_high_delimiters(ffpmod, delim):
             assert (status[:n] == 1).sum() >= 500
     finally:
         c.close()
+
+
+# ---------------------------------------------------------------------------
+# JSON documents: the structural index (FFP_JSON_DOCUMENT)
+# ---------------------------------------------------------------------------
+
+def _json_noise(seed, n):
+    """Bytes from JSON's alphabet in random order (mostly not valid JSON):
+    quotes, backslash runs, digits, signs, structure, letters."""
+    rng = np.random.default_rng(seed)
+    alphabet = np.frombuffer(b'0123456789012345-.eE+"""\\\\\\,,[]{}:  \n\tabtrue', dtype=np.uint8)
+    return bytes(alphabet[rng.integers(0, len(alphabet), n)])
+
+
+@pytest.fixture(scope="module")
+def json_docs():
+    docs = [W.json_tricky_document(91, 3000), W.json_tricky_document(92, 2000, indent=2),
+            W.json_tricky_document(93, 1500, long_strings=True),
+            W.geojson_document(94, 40, 200), _json_noise(95, 300_000)]
+    from oracle import parse_json_document
+    want = [{fmt: parse_json_document(d, fmt) for fmt in ("f64", "f32")} for d in docs]
+    return docs, want
+
+
+@pytest.mark.parametrize("block_kib,tile_k", [(0, 0), (4, 1), (16, 2), (16, 4), (64, 4), (64, 1)])
+def test_json_document_numbers_outside_strings(ffpmod, json_docs, block_kib, tile_k):
+    """Numbers of JSON texts whose strings hold digits, commas, escaped quotes
+    and backslash runs (across chunks, tiles and blocks), and of random
+    JSON-alphabet noise: count, values and status equal the oracle's."""
+    docs, want = json_docs
+    c = ffpmod.Context(0, flags=ffpmod.FFP_JSON_DOCUMENT)
+    try:
+        if tile_k:
+            c.set_tuning(tile_k, 0, block_kib)
+        for i, (doc, w) in enumerate(zip(docs, want)):
+            for fmt in ("f64", "f32"):
+                _log("case json-doc", i, fmt, block_kib, tile_k, len(doc))
+                rc, n, bits, status = run_gpu(c, doc, fmt, offset=i % 16)
+                wb, ws = w[fmt]
+                assert rc == n == len(wb), (i, fmt, rc, n, len(wb))
+                bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                     (status[:n] != np.array(ws, dtype=np.uint8)))
+                assert bad.size == 0, (i, fmt, int(bad[0]))
+    finally:
+        c.close()
+
+
+def test_json_document_plain_calls_only(ffpmod):
+    c = ffpmod.Context(0, flags=ffpmod.FFP_JSON_DOCUMENT)
+    try:
+        t = torch.frombuffer(bytearray(b'[1, "2", 3]'), dtype=torch.uint8).to("cuda:0")
+        v = torch.empty(4, dtype=torch.float64, device="cuda:0")
+        s = torch.empty(4, dtype=torch.uint8, device="cuda:0")
+        table = ffpmod.JobTable([t], [v], [s], "cuda:0")
+        with pytest.raises(ffpmod.FFPError) as e:
+            c.parse_batch(table.dev, 1, t.numel())
+        assert e.value.code == ffpmod.FFP_E_ARG
+        with pytest.raises(ffpmod.FFPError) as e:
+            ffpmod.Server(c, hbm_budget_bytes=64 << 20)
+        assert e.value.code == ffpmod.FFP_E_ARG
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+        assert c.parse_into(t, v, s, cnt, sync=True) == 2
+        assert v[:2].cpu().tolist() == [1.0, 3.0]
+    finally:
+        c.close()
