@@ -176,11 +176,14 @@ _SHARED = {}
 
 
 def _oracle_chunk(args):
-    from oracle import parse_buffer
+    from oracle import parse_buffer, parse_json_document
     import numpy as np
     a, b, fmt = args
-    bits, st = parse_buffer(_SHARED["text"][a:b], fmt, delims=_SHARED["delims"],
-                            flags=_SHARED["flags"])
+    if _SHARED.get("doc"):
+        bits, st = parse_json_document(_SHARED["text"][a:b], fmt, flags=_SHARED["flags"])
+    else:
+        bits, st = parse_buffer(_SHARED["text"][a:b], fmt, delims=_SHARED["delims"],
+                                flags=_SHARED["flags"])
     return np.array(bits, dtype=np.uint64), np.array(st, dtype=np.uint8)
 
 
@@ -193,22 +196,30 @@ def _oracle_tokens(args):
             np.array([s for _, s in out], dtype=np.uint8))
 
 
-def cpu_baseline_leg(text: bytes, fmts, extra_tokens=(), delims=b"\n", flags=0, what=""):
+def cpu_baseline_leg(text: bytes, fmts, extra_tokens=(), delims=b"\n", flags=0, what="",
+                     doc_split=None):
     """Times the oracle over every token of `text` (for each output format
     in `fmts`) and over `extra_tokens` (cut tokens of slices), on the box's
-    CPU share.  Returns (cpu_baseline record, {fmt: (bits, status)} for the
-    text's tokens, {fmt: (bits, status)} for the extra tokens)."""
+    CPU share.  With doc_split the text is a JSON document read as one
+    (numbers outside strings), cut for the workers just after occurrences of
+    doc_split, which must lie outside strings and between tokens.  Returns
+    (cpu_baseline record, {fmt: (bits, status)} for the text's tokens,
+    {fmt: (bits, status)} for the extra tokens)."""
     import numpy as np
-    _SHARED.update(text=text, delims=delims, flags=flags)
+    _SHARED.update(text=text, delims=delims, flags=flags, doc=doc_split is not None)
     nw = workers()
-    # chunks cut at delimiters, several per worker
+    # chunks cut at delimiters (or after doc_split), several per worker
     nchunk = max(1, min(64 * nw, len(text) // 4096 or 1))
     bounds, a = [], 0
     lut = set(delims)
     for k in range(1, nchunk + 1):
         b = len(text) if k == nchunk else max(a, len(text) * k // nchunk)
-        while b < len(text) and text[b] not in lut:
-            b += 1
+        if doc_split is not None:
+            j = text.find(doc_split, b)
+            b = len(text) if j < 0 else j + len(doc_split)
+        else:
+            while b < len(text) and text[b] not in lut:
+                b += 1
         if b > a:
             bounds.append((a, b))
         a = b
@@ -399,7 +410,7 @@ def timed_steps(torch, fn, steps, warmup, spinup_ms=0.0):
 # ---------------------------------------------------------------------------
 
 def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims=b"\n",
-              flags=0, expect_ok=None):
+              flags=0, expect_ok=None, doc_split=None):
     import numpy as np
     import torch
     from paper_2101_11408_amd import ffp
@@ -451,7 +462,7 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims
     rec["cpu_baseline"] = None
     if cpu and not args.profile:
         cb, res, _ = cpu_baseline_leg(buf, [out_dtype], delims=delims, flags=flags,
-                                      what="the whole buffer")
+                                      what="the whole buffer", doc_split=doc_split)
         wb, ws = res[out_dtype]
         rec["cpu_baseline"] = cb
         rec["parity"] = {"vs": "oracle", "tokens_checked": int(len(wb)),
@@ -1027,15 +1038,15 @@ def main():
         t0 = time.time()
         nfeat = (args.tokens or 10_000_000) // 2000
         doc = W.geojson_document(7, nfeat, 1000)
-        ntok = len(re.findall(b"[^" + re.escape(W.JSON_DELIMS) + b"]+", doc))
-        log("generated %d bytes, %d tokens in %.1f s" % (len(doc), ntok, time.time() - t0))
+        ntok = nfeat * 2000  # every number of the document is a coordinate
+        log("generated %d bytes in %.1f s" % (len(doc), time.time() - t0))
         rec = run_plain(args, doc, ntok, out_name(wl, args.out),
                         "GeoJSON-like document (%.1f MB): %d features of 1000 coordinate pairs "
-                        "with 6-15 fraction digits; JSON number grammar, the document's "
-                        "structure bytes as delimiters (keys and strings come back invalid); "
-                        "%s" % (len(doc) / 1e6, nfeat, OUT_NAMES[args.out]),
-                        out_dtype=args.out, cpu=cpu, delims=W.JSON_DELIMS, flags=2,
-                        expect_ok=nfeat * 2000)
+                        "with 6-15 fraction digits, keys and strings around them; "
+                        "FFP_JSON_DOCUMENT (numbers outside strings, JSON number grammar); %s"
+                        % (len(doc) / 1e6, nfeat, OUT_NAMES[args.out]),
+                        out_dtype=args.out, cpu=cpu, flags=0x40, expect_ok=ntok,
+                        doc_split=b"]]}},")
     elif wl == "hexfloat":
         import numpy as np
         n = args.tokens or 10_000_000
