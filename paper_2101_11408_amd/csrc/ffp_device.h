@@ -708,6 +708,22 @@ FFP_HD uint64_t round_exact(uint64_t w, int q, bool sticky, const FormatRT& F, u
   return ((uint64_t)(e + F.bias) << F.mant) | (m & ((1ull << F.mant) - 1));
 }
 
+// The 128-bit table entry for q, q clamped to the table's range (values
+// outside it are decided without the entry).  One 16-byte read: the table
+// is 16-byte aligned.
+struct TableEntry {
+  uint64_t hi, lo;
+};
+
+FFP_HD TableEntry table_entry(const unsigned long long* table, int q) {
+  const int qi = q < kQMin ? kQMin : (q > kQMax ? kQMax : q);
+  struct alignas(16) Entry {
+    unsigned long long hi, lo;
+  };
+  const Entry e = reinterpret_cast<const Entry*>(table)[qi - kQMin];
+  return TableEntry{e.hi, e.lo};
+}
+
 struct DecisionRT {
   uint64_t bits;      // sign applied (sign_bit = 1 << (format width - 1))
   uint32_t status;    // kStOk / kStInvalid / kStRange
@@ -716,11 +732,12 @@ struct DecisionRT {
 };
 
 // qnan / sign: the format's canonical quiet NaN and sign bit; flags: the
-// rounding direction (with kExt).
+// rounding direction (with kExt); pre: the table entry for L.q when the
+// caller has read it already (else it is read here).
 template <bool kExt = true>
 FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* table,
                                   const FormatRT& fmt, uint64_t qnan, uint64_t sign,
-                                  uint32_t flags) {
+                                  uint32_t flags, const TableEntry* pre = nullptr) {
   DecisionRT d;
   d.fallback = false;
   if (L.kind == kLexInvalid) {
@@ -748,12 +765,7 @@ FFP_HD DecisionRT decide_lexed_rt(const Lexed& L, const unsigned long long* tabl
     d.path = kCntEarly;
     return d;
   }
-  const int qi = L.q < kQMin ? kQMin : (L.q > kQMax ? kQMax : L.q);
-  // one 16-byte read of the entry (the table is 16-byte aligned)
-  struct alignas(16) Entry {
-    unsigned long long hi, lo;
-  };
-  const Entry ent = reinterpret_cast<const Entry*>(table)[qi - kQMin];
+  const TableEntry ent = pre ? *pre : table_entry(table, L.q);
   const uint64_t thi = ent.hi, tlo = ent.lo;
   bool ab;
   d.path = (L.q < kQMin || L.q > kQMax) ? kCntEarly : kCntOne;
@@ -803,9 +815,10 @@ struct Decision {
 };
 
 template <class F, bool kExt = true>
-FFP_HD Decision<F> decide_lexed(const Lexed& L, const unsigned long long* table, uint32_t flags) {
+FFP_HD Decision<F> decide_lexed(const Lexed& L, const unsigned long long* table, uint32_t flags,
+                                const TableEntry* pre = nullptr) {
   constexpr FormatRT fmt = format_of<F>();
-  const DecisionRT r = decide_lexed_rt<kExt>(L, table, fmt, F::kQNaN, F::kSign, flags);
+  const DecisionRT r = decide_lexed_rt<kExt>(L, table, fmt, F::kQNaN, F::kSign, flags, pre);
   Decision<F> d;
   d.bits = (typename F::bits_t)r.bits;
   d.status = r.status;

@@ -566,9 +566,10 @@ template <class F, bool kExt>
 __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, const JobDesc& job,
                                             uint64_t first_idx, uint32_t j,
                                             const unsigned long long* table,
+                                            const TableEntry* ent,
                                             const ParseParams& P, uint64_t& bits_out,
                                             uint32_t& status_out) {
-  Decision<F> d = decide_lexed<F, kExt>(L, table, P.flags);
+  Decision<F> d = decide_lexed<F, kExt>(L, table, P.flags, ent);
   bits_out = d.bits;
   status_out = d.fallback ? kPending : d.status;
   uint8_t st = (uint8_t)d.status;
@@ -838,11 +839,12 @@ k_parse(ParseParams P) {
           const bool global = j == global_j;
           FastLex fl;
           if (!global) {
-            fl = fast_lex<K, kGrammar>(sm, s, P.flags);
+            fl = fast_lex<K, kGrammar>(sm, s, P.flags, table);
           } else {
             fl.code = kFastSlow;
           }
           Lexed L;
+          TableEntry ent;  // the table entry for L.q (read by the fast lexer)
           if (fl.code == kFastSlow) {
             if (global)
               L = lex_token<kExt>(gsrc, pos, P.flags);
@@ -850,18 +852,20 @@ k_parse(ParseParams P) {
               L = lex_token<kExt>(lsrc, vpos, P.flags);
             else
               L = long_lex<K>(sm, s, P.flags);
+            ent = table_entry(table, L.q);
           } else {
             L.w = fl.w;
             L.q = fl.q;
             L.neg = fl.neg;
             L.kind = fl.code == kFastInvalid ? kLexInvalid : kLexExact;
+            ent = fl.ent;
           }
           int path;
           switch (job.dtype) {
-            case kF64: path = finish_token<F64, kExt>(L, pos, job, next_idx, j, table, P, vbits, vstatus); break;
-            case kF32: path = finish_token<F32, kExt>(L, pos, job, next_idx, j, table, P, vbits, vstatus); break;
-            case kF16: path = finish_token<F16, kExt>(L, pos, job, next_idx, j, table, P, vbits, vstatus); break;
-            default: path = finish_token<BF16, kExt>(L, pos, job, next_idx, j, table, P, vbits, vstatus); break;
+            case kF64: path = finish_token<F64, kExt>(L, pos, job, next_idx, j, table, &ent, P, vbits, vstatus); break;
+            case kF32: path = finish_token<F32, kExt>(L, pos, job, next_idx, j, table, &ent, P, vbits, vstatus); break;
+            case kF16: path = finish_token<F16, kExt>(L, pos, job, next_idx, j, table, &ent, P, vbits, vstatus); break;
+            default: path = finish_token<BF16, kExt>(L, pos, job, next_idx, j, table, &ent, P, vbits, vstatus); break;
           }
           if (P.count_paths) {
             c_tok += 1;

@@ -203,6 +203,7 @@ struct FastLex {
   int32_t q;
   uint32_t neg;
   uint32_t code;
+  TableEntry ent;  // kFastOk: the power-of-five table entry for q
 };
 
 // Lexer for a token lying wholly inside the tile, from the digit and
@@ -212,9 +213,12 @@ struct FastLex {
 // 19 mantissa digits or more than 8 exponent digits are left to the
 // byte-by-byte lexer (kFastSlow); for all others the result equals
 // lex_token's.  kGrammar: the grammar flags (FFP_JSON, FFP_INFNAN, FFP_HEX)
-// are honoured; without it they must be clear.
+// are honoured; without it they must be clear.  A lexed token also gets its
+// entry of the power-of-five table, read before the mantissa digits are
+// converted so that the read's latency overlaps that work.
 template <int K, bool kGrammar>
-FFP_HD FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, uint32_t flags) {
+FFP_HD FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, uint32_t flags,
+                        const unsigned long long* table) {
   FastLex r;
   r.w = 0;
   r.q = 0;
@@ -281,13 +285,6 @@ FFP_HD FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, uint32_t flags) {
     }
   }
   if (ni + nf > 19 || nexp > 8) return r;
-  const uint64_t fv = digits_before<K>(sm, (int)s + f1, nf);
-  if (wave_all(ni <= 1)) {  // at most one integer digit ("0.5", "7.25", ".5"): read it
-    const uint32_t d = ni ? tb[s + b - 1] - '0' : 0u;
-    r.w = wave_all(d == 0) ? fv : (uint64_t)d * sm.pow10[nf] + fv;
-  } else {
-    r.w = digits_before<K>(sm, (int)s + b, ni) * sm.pow10[nf] + fv;
-  }
   int ev = 0;
   if (wave_any(has_e)) {  // exponents of up to 4 digits in every lane: one 4-digit group
     const int ne = has_e ? nexp : 0;
@@ -295,6 +292,14 @@ FFP_HD FastLex fast_lex(const TileSmem<K>& sm, uint32_t s, uint32_t flags) {
                         : (int)digits8_before<K>(sm, (int)s + e1, ne);
   }
   r.q = (eneg ? -ev : ev) - nfrac;
+  r.ent = table_entry(table, r.q);
+  const uint64_t fv = digits_before<K>(sm, (int)s + f1, nf);
+  if (wave_all(ni <= 1)) {  // at most one integer digit ("0.5", "7.25", ".5"): read it
+    const uint32_t d = ni ? tb[s + b - 1] - '0' : 0u;
+    r.w = wave_all(d == 0) ? fv : (uint64_t)d * sm.pow10[nf] + fv;
+  } else {
+    r.w = digits_before<K>(sm, (int)s + b, ni) * sm.pow10[nf] + fv;
+  }
   r.code = kFastOk;
   return r;
 }

@@ -30,6 +30,10 @@ using namespace ffp;
 namespace {
 
 std::mt19937_64 g_rng;
+
+// A stand-in for the power-of-five table: entry i holds (i + 1000, ~i), so
+// that the entry the fast lexer reads identifies the q it was read for.
+alignas(16) unsigned long long g_table[2 * (kQMax - kQMin + 1)];
 bool g_random_wave = false;
 
 bool vote(bool p, bool all) {
@@ -71,6 +75,10 @@ int main(int argc, char** argv) {
   if (argc < 4) {
     fprintf(stderr, "usage: %s tokens flags seed\n", argv[0]);
     return 2;
+  }
+  for (int i = 0; i < kQMax - kQMin + 1; ++i) {
+    g_table[2 * i] = 1000ull + (unsigned long long)i;
+    g_table[2 * i + 1] = ~(unsigned long long)i;
   }
   FILE* f = fopen(argv[1], "rb");
   if (!f) return 2;
@@ -120,7 +128,7 @@ int main(int argc, char** argv) {
       build_bitmaps(sm);
       const std::string ref_text = t;
       const Lexed ref = lex_token(BufSrc{&ref_text}, 0, flags);
-      const FastLex fl = fast_lex<K, false>(sm, (uint32_t)s, flags);
+      const FastLex fl = fast_lex<K, false>(sm, (uint32_t)s, flags, g_table);
       Lexed got;
       const char* path = "fast";
       if (fl.code == kFastSlow) {
@@ -138,6 +146,10 @@ int main(int argc, char** argv) {
       bool ok = got.kind == ref.kind;
       if (ok && ref.kind != kLexInvalid)
         ok = got.w == ref.w && sat(got.q) == sat(ref.q) && got.neg == ref.neg;
+      if (ok && fl.code == kFastOk) {  // the fast lexer's table entry is q's
+        const TableEntry e = table_entry(g_table, fl.q);
+        ok = fl.ent.hi == e.hi && fl.ent.lo == e.lo;
+      }
       ++n;
       if (!ok) {
         if (bad < 10)
