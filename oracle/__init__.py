@@ -29,6 +29,7 @@ from .exact import (
     round_decimal,
 )
 from .grammar import (
+    FLAG_CSV,
     FLAG_HEX,
     FLAG_INFNAN,
     FLAG_JSON,
@@ -38,9 +39,11 @@ from .grammar import (
     FLAG_ROUND_MASK,
     FLAG_ROUND_TOWARD_ZERO,
     FLAG_ROUND_UP,
+    csv_number_spans,
     decompose,
     json_number_spans,
     parse_buffer,
+    parse_csv,
     parse_json_document,
     parse_token,
     rounding_mode,
@@ -52,6 +55,7 @@ __all__ = [
     "BINARY16",
     "BINARY32",
     "BINARY64",
+    "FLAG_CSV",
     "FLAG_HEX",
     "FLAG_INFNAN",
     "FLAG_JSON",
@@ -72,9 +76,11 @@ __all__ = [
     "STATUS_INVALID",
     "STATUS_OK",
     "STATUS_OUT_OF_RANGE",
+    "csv_number_spans",
     "decompose",
     "json_number_spans",
     "parse_buffer",
+    "parse_csv",
     "parse_json_document",
     "parse_token",
     "round_decimal",

@@ -223,3 +223,52 @@ def parse_json_document(buf: bytes, fmt="f64", flags: int = 0):
         bits.append(v)
         status.append(s)
     return bits, status
+
+
+# ---------------------------------------------------------------------------
+# CSV number columns: the text is a table whose rows end at '\n' and whose
+# fields are separated by ','; a field's column is the number of ',' bytes
+# before it in its row (0-based).  Tokens are the maximal runs of bytes that
+# are not delimiters (',' and '\n' always are; the caller's delimiter set can
+# add others, such as spaces or '\r'), and a token belongs to the column of
+# the field holding it.  Only tokens of the selected columns (a 64-bit mask
+# over columns 0..63) are parsed and numbered, in text order, with the
+# context's grammar flags.  Fields are not quoted.  The library contract for
+# CSV input; the paper names such structural parsing as future work
+# (Section 13).
+# ---------------------------------------------------------------------------
+FLAG_CSV = 0x80
+
+
+def csv_number_spans(buf: bytes, columns: int, delims: bytes = b",\n"):
+    """(start, end) of every token of the selected columns, in order."""
+    seps = set(delims) | {0x2C, 0x0A}
+    spans = []
+    col = 0
+    i, n = 0, len(buf)
+    while i < n:
+        c = buf[i]
+        if c == 0x0A:
+            col = 0
+        elif c == 0x2C:
+            col += 1
+        if c in seps:
+            i += 1
+            continue
+        j = i
+        while j < n and buf[j] not in seps:
+            j += 1
+        if col < 64 and (columns >> col) & 1:
+            spans.append((i, j))
+        i = j
+    return spans
+
+
+def parse_csv(buf: bytes, columns: int, fmt="f64", delims: bytes = b",\n", flags: int = 0):
+    """(bits list, status list) of the tokens of the selected columns."""
+    bits, status = [], []
+    for a, b in csv_number_spans(buf, columns, delims):
+        v, s = parse_token(buf[a:b], fmt, flags)
+        bits.append(v)
+        status.append(s)
+    return bits, status
