@@ -650,12 +650,18 @@ def serve_once(ffp, ctx, reqs, on_device, opts, dst=None):
         raise AssertionError("arrival mismatch at %d requests, first %s"
                              % (off.size, off[:5].tolist()))
     span = (int(td.max()) - int(ta.min())) / 1e9
+    # the two parts of a latency: waiting for a launch, and launch to done
+    tl = out["t_launch_ns"].astype(np.int64)
+    lat = (lat, tl - ta, td - tl)
     return lat, out["count"].astype(np.int64), out["batch_jobs"], span, st
 
 
 def summarize(lat, counts, sizes, batch, span, st):
     import numpy as np
+    lat, wait, run = lat
     q = np.percentile(lat / 1e3, [50, 99, 99.9])
+    qw = np.percentile(wait / 1e3, [50, 99])
+    qr = np.percentile(run / 1e3, [50, 99])
     return {
         "p50_us": round(float(q[0]), 1), "p99_us": round(float(q[1]), 1),
         "p999_us": round(float(q[2]), 1), "mean_us": round(float(lat.mean() / 1e3), 1),
@@ -665,6 +671,8 @@ def summarize(lat, counts, sizes, batch, span, st):
         "mean_batch": round(float(len(lat)) / max(1, st["batches"]), 2),
         "max_batch": int(st["max_batch_seen"]),
         "arena_peak_MB": round(st["arena_peak_bytes"] / 1e6, 1),
+        "wait_p50_p99_us": [round(float(x), 1) for x in qw],
+        "run_p50_p99_us": [round(float(x), 1) for x in qr],
     }
 
 
@@ -693,9 +701,9 @@ def served_rows(args, rates, extra_rates, requests, modes, parity_rate=None):
     budget = 32 << 30
     opts = {"batched": dict(hbm_budget_bytes=budget, max_batch_bytes=256 << 20,
                             streams=args.serve_streams, max_batch_jobs=1024,
-                            use_graph=args.serve_graph),
+                            use_graph=args.serve_graph, spin_us=args.serve_spin_us),
             "plain": dict(hbm_budget_bytes=budget, max_batch_bytes=256 << 20,
-                          mode=ffp.FFP_SERVE_PLAIN, streams=1)}
+                          mode=ffp.FFP_SERVE_PLAIN, streams=1, spin_us=args.serve_spin_us)}
     rows, parity, cpu = [], None, None
     for ri, rate in enumerate(rates + extra_rates):
         t, sizes, is_f32, is_hard = W.config5_requests(5 + ri, rate, requests)
@@ -921,6 +929,7 @@ def run_served(args, workload):
                        "highest rate (device-resident text); ms_per_step = its p50 latency"
                        % (args.rates, args.requests),
         "streams": args.serve_streams, "graph": bool(args.serve_graph),
+        "dispatcher_spin_us": args.serve_spin_us,
         "parallelism": "single GPU"})
     rec["steps"] = args.requests
     rec["p50_us"] = top["batched"]["p50_us"]
@@ -967,6 +976,9 @@ def main():
                          "(0: none)")
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-graph", type=int, default=0)
+    ap.add_argument("--serve-spin-us", type=int, default=200,
+                    help="served workloads: the idle dispatcher polls this long before "
+                         "sleeping (ffp_server_options.spin_us)")
     ap.add_argument("--schedule", default="",
                     help="batched workloads: tile_k,workgroups_per_cu instead of the autotuner")
     ap.add_argument("--profile", action="store_true",

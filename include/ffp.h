@@ -354,6 +354,27 @@ int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches);
 int ffp_set_reduce(ffp_ctx* ctx, uint64_t* d_out);
 
 /* ---------------------------------------------------------------------------
+ * Exact in-kernel sum (an extension of the reduction above; Section 12's
+ * benchmark reduces the parsed values, and summing them is the other common
+ * reduction).  With d_sum set (a device array of two uint64_t), every later
+ * plain parse call on the context also writes, when its last kernel ends:
+ *   d_sum[0]  the binary64 encoding of the sum of the values that the
+ *             reduction above covers (status FFP_OK, not NaN), computed
+ *             exactly and rounded once, to nearest with ties to even, in
+ *             binary64 whatever the call's output format; a sum beyond the
+ *             binary64 range rounds to an infinity of its sign;
+ *   d_sum[1]  1 if that rounding was exact, else 0.
+ * Infinities follow IEEE addition (+inf and -inf together give the
+ * canonical quiet NaN, with d_sum[1] = 0).  An exact zero is -0 only when
+ * every summed value is -0; the empty sum is +0.  The result does not depend
+ * on the order of the tokens or on how the call is split into workgroups.
+ * Exact for every call that fits in device memory (the accumulators'
+ * carries cannot overflow below 2^43 bytes of text).  Independent of
+ * ffp_set_reduce; NULL turns it off.  Batched calls ignore it.
+ * ------------------------------------------------------------------------- */
+int ffp_set_reduce_sum(ffp_ctx* ctx, uint64_t* d_sum);
+
+/* ---------------------------------------------------------------------------
  * Device path counters (Table 5 of the paper reports the same categories on
  * CPUs).  When enabled, the parse kernels count tokens per path; reading
  * synchronises.  counters[0..5]: tokens, invalid, early-exit (zero / out of
@@ -403,7 +424,11 @@ typedef struct ffp_server_options {
     uint32_t mode;             /* FFP_SERVE_BATCHED or FFP_SERVE_PLAIN */
     uint32_t use_graph;        /* batched mode: replay a captured graph of the
                                   batch launch sequence per batch */
-    uint32_t reserved[3];
+    uint32_t spin_us;          /* an idle dispatcher polls for new requests
+                                  this long before it sleeps (0 = it sleeps at
+                                  once): a CPU core spent for a shorter path
+                                  from submission to launch */
+    uint32_t reserved[2];
 } ffp_server_options;
 
 typedef struct ffp_result {

@@ -163,48 +163,87 @@ Scratch own_scratch(const ffp_ctx* ctx) {
 // less, which is most of a small call's time).
 constexpr uint64_t kSumInParseMaxBlocks = 1024;
 
+// Plain calls of at most this many blocks (32 KiB) run without the count
+// kernel as well: each parse workgroup counts the tokens before its block
+// from the text (at most 28 KiB of cached reads) instead of waiting for a
+// kernel launch.  Measured from launch to a synchronised stream: 21.2 us
+// against 23.3 us at 4 KiB, 24.1 against 24.7 at 32 KiB; past that the
+// counting costs more than the launch (26.5 against 24.9 us at 64 KiB).
+constexpr uint64_t kSelfCountMaxBlocks = 8;
+
 // count -> scan -> parse -> fallback for a job set whose block count is
 // `nblocks` (plain calls) or on the device (batched calls: nblocks is then
 // the scratch's bound and max_blocks the call's); small calls skip the scan.
 int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const CallShape& shape,
                 uint64_t nblocks, uint64_t max_blocks, hipStream_t s) {
-  ctx->last_state = sc.state;
   // (the parse kernel's 4 KiB-tile instances carry the summation)
   // (JSON documents need the scan: it gives each block its string state)
   const bool json_doc = (ctx->flags & FFP_JSON_DOCUMENT) != 0;
-  const bool sum_in_parse = nblocks > 0 && max_blocks <= kSumInParseMaxBlocks &&
+  uint64_t* const reduce_out = js.jobs ? nullptr : ctx->reduce_out;  // plain calls only
+  uint64_t* const sum_out = js.jobs ? nullptr : ctx->sum_out;
+  const bool count_paths = ctx->counters && !sc.fixed;
+  // (the reductions and the path counters live in the main state)
+  const bool self_count = !js.jobs && !sc.fixed && ctx->d_spare && nblocks > 0 &&
+                          nblocks <= kSelfCountMaxBlocks && shape.tile_k == 1 &&
+                          js.block_shift == ffp::kMinBlockShift && !json_doc &&
+                          !reduce_out && !sum_out && !count_paths;
+  const bool sum_in_parse = !self_count && nblocks > 0 && max_blocks <= kSumInParseMaxBlocks &&
                             shape.tile_k == 1 && !json_doc;
+  // A call without the count kernel runs on the spare state the previous
+  // call left clean and cleans the other one; every other call cleans its
+  // own state and both spares.
+  DeviceState* st = sc.state;
+  DeviceState* other = nullptr;
+  if (self_count) {
+    st = ctx->d_spare + ctx->spare_sel;
+    other = ctx->d_spare + (1 - ctx->spare_sel);
+    ctx->spare_sel ^= 1;
+  }
+  DeviceState* const spare = sc.fixed ? nullptr : ctx->d_spare;
+  ctx->last_state = st;
   ffp::ScanParams sp{};
   sp.js = js;
   sp.block_sum = sc.block_sum;
-  sp.st = sc.state;
+  sp.st = st;
+  sp.spare = spare;
   sp.json_doc = json_doc ? 1u : 0u;
-  if (nblocks > 0) {
+  if (nblocks > 0 && !self_count) {
     ffp::CountParams cp{};
     cp.js = js;
     cp.block_sum = sc.block_sum;
     cp.delim = ctx->delim;
-    cp.st = sc.state;
+    cp.st = st;
+    cp.spare = spare;
     cp.reset_state = sum_in_parse ? 1u : 0u;
     cp.json_doc = json_doc ? 1u : 0u;
     uint64_t grid = (uint64_t)ctx->num_cus * 8;
     if (grid > nblocks) grid = nblocks;
     if (ffp::launch_count(ctx->delim.single != 0, cp, (int)grid, s) != hipSuccess) return FFP_E_HIP;
   }
-  if (!sum_in_parse && ffp::launch_scan(sp, s) != hipSuccess) return FFP_E_HIP;
-  if (nblocks == 0) return FFP_SUCCESS;
+  if (!sum_in_parse && !self_count && ffp::launch_scan(sp, s) != hipSuccess) return FFP_E_HIP;
+  if (nblocks == 0) {  // no token: the reductions of an empty set
+    ffp::FallbackParams F{};
+    F.st = st;
+    F.js = js;
+    F.reduce_out = reduce_out;
+    F.sum_out = sum_out;
+    return ffp::launch_reduce_final(F, s) == hipSuccess ? FFP_SUCCESS : FFP_E_HIP;
+  }
 
   ffp::ParseParams P{};
   P.js = js;
   P.block_prefix = sc.block_sum;
-  P.st = sc.state;
+  P.st = st;
   P.queue = sc.queue;
   P.queue_cap = sc.queue_cap;
   P.delim = ctx->delim;
   P.flags = ctx->flags;
-  P.count_paths = ctx->counters && !sc.fixed ? 1u : 0u;
+  P.count_paths = count_paths ? 1u : 0u;
   P.sum_in_parse = sum_in_parse ? 1u : 0u;
-  P.reduce_out = js.jobs ? nullptr : ctx->reduce_out;  // plain calls only
+  P.self_count = self_count ? 1u : 0u;
+  P.other_st = other;
+  P.reduce_out = reduce_out;
+  P.sum_out = sum_out;
   uint64_t grid = (uint64_t)shape.grid;
   if (grid > nblocks) grid = nblocks;
 
@@ -235,11 +274,20 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
   F.js = js;
   F.queue = sc.queue;
   F.queue_cap = sc.queue_cap;
-  F.st = sc.state;
+  F.st = st;
   F.delim = ctx->delim;
   F.reduce_out = P.reduce_out;
+  F.sum_out = P.sum_out;
   F.flags = P.flags;
-  if (ffp::launch_fallback(F, ctx->fb_grid, s) != hipSuccess) return FFP_E_HIP;
+  // a small plain call queues at most a few hundred tokens per 4 KiB block:
+  // a grid to match (launching the full grid of idle workgroups costs more
+  // than the usual empty queue's work)
+  uint64_t fb_grid = (uint64_t)ctx->fb_grid;
+  if (!js.jobs && nblocks <= kSumInParseMaxBlocks) {
+    const uint64_t want = nblocks * 8 < 16 ? 16 : nblocks * 8;
+    if (want < fb_grid) fb_grid = want;
+  }
+  if (ffp::launch_fallback(F, (int)fb_grid, s) != hipSuccess) return FFP_E_HIP;
   return FFP_SUCCESS;
 }
 
@@ -279,7 +327,8 @@ int parse_common(ffp_ctx* ctx, uint32_t dtype, const uint8_t* d_text, uint64_t n
   job.block_begin = 0;
   job.dtype = dtype;
   job.job_id = 0;
-  const CallShape shape = call_shape(ctx, nbytes, ctx->reduce_out != nullptr, capacity);
+  const CallShape shape =
+      call_shape(ctx, nbytes, ctx->reduce_out != nullptr || ctx->sum_out != nullptr, capacity);
   // blocks start at the 16-byte boundary at or below d_text
   const uint64_t vbytes = nbytes ? nbytes + ((uintptr_t)d_text & 15u) : 0;
   const uint64_t nblocks = (vbytes + (1ull << shape.block_shift) - 1) >> shape.block_shift;
@@ -547,12 +596,14 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   }
   ctx->blocks_per_cu = ctx->max_bpc[ctx->tile_k];
   ctx->fb_grid = ctx->num_cus * 4;
-  if (hipMalloc(&ctx->d_state, sizeof(DeviceState)) != hipSuccess) {
+  // the main state and the two spares, all clean
+  if (hipMalloc(&ctx->d_state, 3 * sizeof(DeviceState)) != hipSuccess) {
     delete ctx;
     return FFP_E_NOMEM;
   }
+  ctx->d_spare = ctx->d_state + 1;
   ctx->last_state = ctx->d_state;
-  if (hipMemset(ctx->d_state, 0, sizeof(DeviceState)) != hipSuccess ||
+  if (hipMemset(ctx->d_state, 0, 3 * sizeof(DeviceState)) != hipSuccess ||
       grow(ctx, 1 << 20, 1) != FFP_SUCCESS) {
     ffp_destroy(ctx);
     return FFP_E_NOMEM;
@@ -839,6 +890,12 @@ int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches) {
 int ffp_set_reduce(ffp_ctx* ctx, uint64_t* d_out) {
   if (!ctx) return FFP_E_ARG;
   ctx->reduce_out = d_out;
+  return FFP_SUCCESS;
+}
+
+int ffp_set_reduce_sum(ffp_ctx* ctx, uint64_t* d_sum) {
+  if (!ctx) return FFP_E_ARG;
+  ctx->sum_out = d_sum;
   return FFP_SUCCESS;
 }
 

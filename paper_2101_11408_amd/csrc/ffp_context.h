@@ -37,6 +37,10 @@ struct ffp_ctx {
   JobDesc* d_jobs = nullptr;  // internal job table of batched calls
   uint64_t jobs_cap = 0;
   DeviceState* d_state = nullptr;
+  // two more states for the calls that run without the count kernel, used
+  // in turn (d_state + 1 and d_state + 2; one allocation)
+  DeviceState* d_spare = nullptr;
+  int spare_sel = 0;
   // the fixed scratch of ffp_parse_f64_noalloc on this context's device
   unsigned char* d_fixed = nullptr;
   // device state of the last call (d_state, or the fixed scratch's)
@@ -49,6 +53,7 @@ struct ffp_ctx {
 
   bool counters = false;
   uint64_t* reduce_out = nullptr;  // plain calls: min, max, count of the values
+  uint64_t* sum_out = nullptr;     // plain calls: exact sum of the values
 };
 
 struct ffp_graph {

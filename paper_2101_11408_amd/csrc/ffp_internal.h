@@ -45,7 +45,7 @@ constexpr uint64_t kNoAllocMaxBytes = 8ull << 20;
 constexpr uint64_t kNoAllocBlocks = ((kNoAllocMaxBytes + 15) >> kMinBlockShift) + 3;
 constexpr uint64_t kNoAllocQueue = (kNoAllocMaxBytes + 1) / 21 + kAbortReserve;
 constexpr uint64_t kNoAllocStateOff = 0;
-constexpr uint64_t kNoAllocBlockOff = 256;
+constexpr uint64_t kNoAllocBlockOff = 2048;
 constexpr uint64_t kNoAllocQueueOff = kNoAllocBlockOff + ((kNoAllocBlocks * 8 + 255) & ~255ull);
 constexpr uint64_t kNoAllocScratchBytes = kNoAllocQueueOff + kNoAllocQueue * 16;
 
@@ -83,6 +83,20 @@ struct QueueEntry {
   uint64_t index_job;  // token index | (job id << 48)
 };
 
+// Exact sum of the values (ffp_set_reduce_sum): every value of the four
+// output formats is an integer multiple of 2^-1074, below 2^1024 in
+// magnitude.  The magnitudes of the positive and of the negative values are
+// accumulated apart, as fixed-point numbers in units of 2^-1074, in limbs of
+// 32 bits held in 64-bit words: additions put pieces below 2^32 into the
+// words and the carries they collect in the upper halves are resolved once,
+// at the end.  Limbs 0..65 receive the pieces of single values (a 53-bit
+// significand shifted by up to 2046 bits spans three limbs), the rest takes
+// the carries.
+constexpr int kSumLimbs = 68;
+// sum_flags bits: a +inf / -inf was summed, a value other than -0 was
+// summed, some value was summed
+constexpr uint32_t kSumPosInf = 1, kSumNegInf = 2, kSumNotNegZero = 4, kSumAny = 8;
+
 struct DeviceState {
   unsigned int error;
   unsigned int pad;
@@ -91,6 +105,9 @@ struct DeviceState {
   unsigned long long counters[8];
   // min / max of the order keys of the values and their count (reduction)
   unsigned long long red_min, red_max, red_count;
+  // exact sum: accumulators of the positive ([0]) and negative ([1]) values
+  unsigned long long sum_acc[2][kSumLimbs];
+  unsigned int sum_flags;
 };
 
 static_assert(sizeof(DeviceState) <= kNoAllocBlockOff, "device state fits its scratch slot");
@@ -140,6 +157,7 @@ struct CountParams {
   uint64_t* block_sum;  // per block: tokens starting in it
   DelimSet delim;
   DeviceState* st;      // reset here when the call runs without the scan kernel
+  DeviceState* spare;   // with reset_state: the context's two spare states (or null)
   uint32_t reset_state;
   uint32_t json_doc;    // FFP_JSON_DOCUMENT: counts for both entry states
 };
@@ -154,6 +172,7 @@ struct ScanParams {
   JobSet js;
   uint64_t* block_sum;  // in: counts; out: exclusive prefix over all blocks
   DeviceState* st;
+  DeviceState* spare;   // the context's two spare states, reset here (or null)
   uint32_t json_doc;    // count words of JSON documents (see kPrefixMask)
 };
 
@@ -167,11 +186,18 @@ struct ParseParams {
   uint32_t flags;           // FFP_REJECT_PLUS ...
   uint32_t count_paths;
   uint64_t* reduce_out;     // plain calls: min, max, count of the values (or null)
+  uint64_t* sum_out;        // plain calls: exact sum of the values (or null)
   // Small calls (4 KiB tiles) run without the scan kernel: block_prefix
   // then holds each block's own token count, every workgroup sums the counts
   // of its job's earlier blocks, and the workgroup of a job's last block
   // writes the job's count (and the capacity error).
   uint32_t sum_in_parse;
+  // The smallest plain calls run without the count kernel too: each
+  // workgroup counts the tokens before its block from the text itself, and
+  // st is one of the context's two spare states, clean when the call starts;
+  // the call resets the other one (other_st) for the next such call.
+  uint32_t self_count;
+  DeviceState* other_st;
 };
 
 struct FallbackParams {
@@ -181,6 +207,7 @@ struct FallbackParams {
   DeviceState* st;
   DelimSet delim;
   uint64_t* reduce_out;  // as in ParseParams
+  uint64_t* sum_out;     // as in ParseParams
   uint32_t flags;        // as in ParseParams (the rounding direction)
 };
 

@@ -22,5 +22,6 @@ hipError_t launch_count(bool single_delim, const CountParams& P, int grid, hipSt
 hipError_t launch_scan(const ScanParams& P, hipStream_t s);
 hipError_t launch_parse(int k, bool single_delim, const ParseParams& P, int grid, hipStream_t s);
 hipError_t launch_fallback(const FallbackParams& P, int grid, hipStream_t s);
+hipError_t launch_reduce_final(const FallbackParams& P, hipStream_t s);
 
 }  // namespace ffp

@@ -82,6 +82,47 @@ __device__ __forceinline__ uint64_t key_to_bits(uint64_t key, uint32_t dtype) {
   return x >> (64 - dtype_width(dtype));
 }
 
+// An encoding with an order key (status OK, not NaN) as a term of the exact
+// sum: value = (-1)^neg * m * 2^(b - 1074), b >= 0; inf for infinities.
+// Per format: b = max(field, 1) - bias - (precision - 1) + 1074.
+struct SumTerm {
+  uint64_t m;
+  int b;
+  bool neg, inf;
+};
+
+__device__ __forceinline__ SumTerm sum_term(uint64_t bits, uint32_t dtype) {
+  const int t = dtype == kF64 ? 52 : dtype == kF32 ? 23 : dtype == kF16 ? 10 : 7;
+  const int ew = dtype == kF64 ? 11 : dtype == kF16 ? 5 : 8;
+  const int bias = (1 << (ew - 1)) - 1;
+  const uint32_t field = (uint32_t)(bits >> t) & ((1u << ew) - 1);
+  SumTerm r;
+  r.neg = (bits >> (t + ew)) & 1;
+  r.inf = field == (1u << ew) - 1;
+  r.m = (bits & ((1ull << t) - 1)) | (field ? 1ull << t : 0ull);
+  r.b = (int)(field ? field : 1u) - bias - t + 1074;
+  return r;
+}
+
+// Adds a term's magnitude to an accumulator (kSumLimbs words, in LDS or in
+// global memory): m << (b mod 32) in three 32-bit pieces.
+__device__ __forceinline__ void sum_add(unsigned long long* acc, const SumTerm& x) {
+  unsigned long long* a = acc + (x.b >> 5);
+  const int r = x.b & 31;
+  const uint64_t lo = x.m << r;
+  const uint64_t hi = r ? x.m >> (64 - r) : 0ull;
+  if (lo & 0xFFFFFFFFull) atomicAdd(a, (unsigned long long)(lo & 0xFFFFFFFFull));
+  if (lo >> 32) atomicAdd(a + 1, (unsigned long long)(lo >> 32));
+  if (hi) atomicAdd(a + 2, (unsigned long long)hi);
+}
+
+__device__ __forceinline__ uint32_t sum_flag_bits(const SumTerm& x) {
+  uint32_t f = kSumAny;
+  if (x.inf) f |= x.neg ? kSumNegInf : kSumPosInf;
+  if (!(x.neg && x.m == 0)) f |= kSumNotNegZero;
+  return f;
+}
+
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   for (int d = 32; d > 0; d >>= 1) {
     const uint64_t o = __shfl_xor(v, d, kWave);
@@ -277,6 +318,18 @@ __device__ __forceinline__ void reset_call_state(DeviceState* st) {
   st->red_min = ~0ull;
   st->red_max = 0;
   st->red_count = 0;
+  st->sum_flags = 0;
+}
+
+// What a call without the count kernel needs clean: its queue and error.
+__device__ __forceinline__ void reset_spare_state(DeviceState* st) {
+  st->queue_tail = 0;
+  st->error = 0;
+}
+
+// The exact sum's accumulators, cleared by the threads of one workgroup.
+__device__ __forceinline__ void reset_sum_state(DeviceState* st, int tid, int nthreads) {
+  for (int i = tid; i < 2 * kSumLimbs; i += nthreads) (&st->sum_acc[0][0])[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -362,7 +415,16 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
   if (!kSingle)
     for (int i = tid; i < 256; i += kThreads) s_lut[i] = is_delim(P.delim, (uint32_t)i);
   const uint32_t drep = P.delim.byte * 0x01010101u;
-  if (P.reset_state && blockIdx.x == 0 && tid == 0) reset_call_state(P.st);
+  if (P.reset_state && blockIdx.x == 0) {
+    if (tid == 0) {
+      reset_call_state(P.st);
+      if (P.spare) {
+        reset_spare_state(P.spare);
+        reset_spare_state(P.spare + 1);
+      }
+    }
+    reset_sum_state(P.st, tid, kThreads);
+  }
   const uint64_t nblk = total_blocks_of(P.js);
   if (!kSingle && P.json_doc) {
     count_json_doc<kRows>(P, s_lut, s_scan, reinterpret_cast<uint8_t*>(s_nd));
@@ -417,7 +479,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
     s_carry = 0;
     s_parity = 0;
     reset_call_state(P.st);
+    if (P.spare) {
+      reset_spare_state(P.spare);
+      reset_spare_state(P.spare + 1);
+    }
   }
+  reset_sum_state(P.st, tid, kScanThreads);
   for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * kScanPer) {
     uint64_t v[kScanPer];
     uint64_t sum = 0;
@@ -556,6 +623,27 @@ __global__ __launch_bounds__(kScanThreads) void k_prep(PrepParams P) {
   }
 }
 
+// Tokens of a job that start in its first `vbytes` virtual bytes (a multiple
+// of the chunk size; virtual byte v is text[v - align]), counted by the
+// threads of a workgroup (each returns its share): a start is a token byte
+// whose predecessor is a delimiter or lies before the text.
+template <bool kSingle>
+__device__ uint64_t count_starts_before(const uint8_t* vbase, uint64_t align, uint64_t vend,
+                                        uint64_t vbytes, const DelimSet& delim, uint32_t drep,
+                                        const uint8_t* lut, int tid) {
+  uint64_t n = 0;
+  for (uint64_t c = (uint64_t)tid; c * kChunk < vbytes; c += kThreads) {
+    const uint64_t off = c * kChunk;
+    const uint4 v = load_chunk(vbase, off, align, vend, delim.byte);
+    // the byte before the chunk: past the text's first byte for c > 0
+    // (off - 1 >= 15 >= align) and before vbytes <= vend
+    const uint32_t prev = c ? (lut[gload(vbase + off - 1)] ? 0u : 1u) : 0u;
+    const uint32_t m = nondelim_mask16<kSingle>(v, drep, lut);
+    n += __popc(m & ~((m << 1) | prev) & 0xFFFFu);
+  }
+  return n;
+}
+
 // ---------------------------------------------------------------------------
 // k_parse (the tile layout and the lexers are in ffp_lexer.h)
 // ---------------------------------------------------------------------------
@@ -611,6 +699,9 @@ k_parse(ParseParams P) {
   using S = TileSmem<K>;
   using Packed = typename S::Packed;
   __shared__ S sm;
+  // the exact sum's accumulators of this workgroup (reduction instances)
+  __shared__ unsigned long long s_sum[kReduce ? 2 * kSumLimbs : 1];
+  __shared__ uint32_t s_sum_flags;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
 
@@ -634,7 +725,10 @@ k_parse(ParseParams P) {
     sm.red_min = kNoMin;
     sm.red_max = kNoMax;
     sm.red_count = 0;
+    s_sum_flags = 0;
   }
+  if (kReduce)
+    for (int i = tid; i < 2 * kSumLimbs; i += kThreads) s_sum[i] = 0;
   const uint32_t drep = P.delim.byte * 0x01010101u;
   const uint64_t nblk = total_blocks_of(P.js);
   // tiles per block (the host keeps blocks at least one tile long)
@@ -653,10 +747,18 @@ k_parse(ParseParams P) {
     const uint64_t vend = nbytes + align;
     const uint64_t bstart = (blk - job.block_begin) << P.js.block_shift;
     uint64_t next_idx;
-    if (K == 1 && P.sum_in_parse) {  // small calls: 4 KiB blocks, one tile each
-      // the counts of this job's earlier blocks, summed by the workgroup
+    if (K == 1 && (P.sum_in_parse || P.self_count)) {  // small calls: 4 KiB blocks, one tile each
+      // the counts of this job's earlier blocks, summed by the workgroup, or
+      // (self_count) the tokens before the block, counted from the text
       uint64_t part = 0;
-      for (uint64_t i = job.block_begin + tid; i < blk; i += kThreads) part += P.block_prefix[i];
+      if (P.self_count) {
+        if (blk == 0 && tid == 0) reset_spare_state(P.other_st);
+        __syncthreads();  // the delimiter table is written
+        part = count_starts_before<kSingle>(vbase, align, vend, bstart, P.delim,
+                                            P.delim.byte * 0x01010101u, sm.delim_lut, tid);
+      } else {
+        for (uint64_t i = job.block_begin + tid; i < blk; i += kThreads) part += P.block_prefix[i];
+      }
       part = wave_sum_u64(part);
       __syncthreads();  // sm.red_part of the previous block is consumed
       if (lane == 0) sm.red_part[tid / kWave] = part;
@@ -664,7 +766,8 @@ k_parse(ParseParams P) {
       next_idx = 0;
 #pragma unroll
       for (int w = 0; w < kThreads / kWave; ++w) next_idx += sm.red_part[w];
-      if (tid == 0 && blk + 1 == job.block_begin + job_blocks(job, P.js.block_shift)) {
+      if (!P.self_count && tid == 0 &&
+          blk + 1 == job.block_begin + job_blocks(job, P.js.block_shift)) {
         // the job's last block: its token count and the capacity check
         const uint64_t count = next_idx + P.block_prefix[blk];
         *job.count_out = count;
@@ -786,6 +889,13 @@ k_parse(ParseParams P) {
         row_off[c] = ntok;
         ntok += (uint32_t)(total_packed >> (16 * c)) & 0xFFFFu;
       }
+      if (K == 1 && P.self_count && tid == 0 &&
+          blk + 1 == job.block_begin + job_blocks(job, P.js.block_shift)) {
+        // the job's last block (one tile): its token count and the capacity check
+        const uint64_t count = next_idx + ntok;
+        *job.count_out = count;
+        if (job.err_out && count > job.capacity) atomicCAS(job.err_out, 0, kErrCapacity);
+      }
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         uint32_t p = row_off[c] + ((uint32_t)(excl_packed >> (16 * c)) & 0xFFFFu);
@@ -887,6 +997,16 @@ k_parse(ParseParams P) {
             atomicMax(&sm.red_max, (unsigned long long)kmax);
             atomicAdd(&sm.red_count, (unsigned long long)cnt);
           }
+          if (P.sum_out) {  // the same values, into the exact sum
+            const SumTerm x = sum_term(vbits, job.dtype);
+            if (in && !x.inf && x.m) sum_add(s_sum + (x.neg ? kSumLimbs : 0), x);
+            const uint32_t f = in ? sum_flag_bits(x) : 0u;
+            uint32_t fw = 0;
+#pragma unroll
+            for (uint32_t bit = 1; bit <= kSumAny; bit <<= 1)
+              if (__ballot((f & bit) != 0)) fw |= bit;
+            if (lane == 0 && fw) atomicOr(&s_sum_flags, fw);
+          }
         }
       }
       next_idx += ntok;
@@ -897,6 +1017,24 @@ k_parse(ParseParams P) {
         }
       } else if (tid == 0) {
         sm.prev_nd = (sm.nd[S::kChunks - 1] >> 15) & 1u;
+      }
+    }
+    if (kReduce && P.sum_out) {
+      // the block's sum into the call's accumulators: each word (below
+      // 2^47 after a block of at most 2^15 tokens) as two 32-bit pieces
+      __syncthreads();
+      for (int i = tid; i < 2 * kSumLimbs; i += kThreads) {
+        const unsigned long long v = s_sum[i];
+        if (v) {
+          s_sum[i] = 0;
+          unsigned long long* g = &P.st->sum_acc[0][0] + i;
+          atomicAdd(g, v & 0xFFFFFFFFull);
+          if (v >> 32) atomicAdd(g + 1, v >> 32);
+        }
+      }
+      if (tid == 0 && s_sum_flags) {
+        atomicOr(&P.st->sum_flags, s_sum_flags);
+        s_sum_flags = 0;
       }
     }
   }
@@ -936,10 +1074,16 @@ __device__ __forceinline__ void fallback_token(const JobDesc& job, uint64_t pos,
     gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, bits);
     gstore(job.status + idx, (uint8_t)status);
     uint64_t key;
-    if (P.reduce_out && order_key(bits, status, job.dtype, key)) {
+    const bool in = (P.reduce_out || P.sum_out) && order_key(bits, status, job.dtype, key);
+    if (in && P.reduce_out) {
       atomicMin(&P.st->red_min, (unsigned long long)key);
       atomicMax(&P.st->red_max, (unsigned long long)key);
       atomicAdd(&P.st->red_count, 1ull);
+    }
+    if (in && P.sum_out) {
+      const SumTerm x = sum_term(bits, job.dtype);
+      if (!x.inf && x.m) sum_add(&P.st->sum_acc[x.neg ? 1 : 0][0], x);
+      atomicOr(&P.st->sum_flags, sum_flag_bits(x));
     }
   }
 }
@@ -973,8 +1117,87 @@ __global__ __launch_bounds__(kFbThreads) void k_fallback(FallbackParams P) {
 // kernel would need a device-scope fence in every workgroup, which writes
 // back the XCD's L2 each time).
 // ---------------------------------------------------------------------------
+// The exact sum, rounded once to binary64 (nearest, ties to even): the
+// accumulators' carries resolved into 32-bit limbs, the smaller magnitude
+// subtracted from the larger, the leading 53 bits kept with a guard bit and
+// a sticky bit below them.  out[0]: the encoding, out[1]: 1 if the sum is
+// exactly representable.  One thread.
+__device__ void sum_final(DeviceState* st, uint64_t* out) {
+  __shared__ uint32_t mag[2][kSumLimbs];
+  for (int side = 0; side < 2; ++side) {
+    unsigned long long carry = 0;
+    for (int i = 0; i < kSumLimbs; ++i) {
+      const unsigned long long t = st->sum_acc[side][i] + carry;
+      mag[side][i] = (uint32_t)t;
+      carry = t >> 32;
+    }
+  }
+  const uint32_t flags = st->sum_flags;
+  uint64_t bits;
+  bool exact = true;
+  if ((flags & kSumPosInf) && (flags & kSumNegInf)) {
+    bits = F64::kQNaN;
+    exact = false;
+  } else if (flags & (kSumPosInf | kSumNegInf)) {
+    bits = F64::kInf | ((flags & kSumNegInf) ? F64::kSign : 0ull);
+  } else {
+    // sign of the difference: the first limb from the top that differs
+    int cmp = 0;
+    for (int i = kSumLimbs - 1; i >= 0 && cmp == 0; --i)
+      cmp = mag[0][i] > mag[1][i] ? 1 : (mag[0][i] < mag[1][i] ? -1 : 0);
+    const int big = cmp >= 0 ? 0 : 1;
+    __shared__ uint32_t d[kSumLimbs];
+    int64_t borrow = 0;
+    int top = -1;  // index of the highest nonzero limb of |difference|
+    for (int i = 0; i < kSumLimbs; ++i) {
+      const int64_t t = (int64_t)mag[big][i] - (int64_t)mag[1 - big][i] - borrow;
+      borrow = t < 0;
+      d[i] = (uint32_t)(t + (borrow << 32));
+      if (d[i]) top = i;
+    }
+    const uint64_t sign = big ? F64::kSign : 0ull;
+    if (top < 0) {
+      // an exact zero: -0 only when every summed value was -0
+      bits = ((flags & kSumAny) && !(flags & kSumNotNegZero)) ? F64::kSign : 0ull;
+    } else {
+      const int t = top * 32 + 31 - __builtin_clz(d[top]);  // leading bit
+      if (t <= 52) {
+        // below 2^53 units of 2^-1074: the encoding is the integer itself
+        bits = sign | ((uint64_t)d[1] << 32 | d[0]);
+      } else {
+        // bits [t-52, t] of d, then the guard bit t-53 and the sticky rest
+        auto bit_at = [&](int i) -> uint64_t { return (d[i >> 5] >> (i & 31)) & 1u; };
+        uint64_t m = 0;
+        for (int i = t; i >= t - 52; --i) m = (m << 1) | bit_at(i);
+        const uint64_t guard = t >= 53 ? bit_at(t - 53) : 0u;
+        bool sticky = false;
+        for (int i = 0; i < t - 53 && !sticky; ++i) sticky = bit_at(i) != 0;
+        exact = !guard && !sticky;
+        int e = t;
+        if (guard && (sticky || (m & 1))) {
+          if (++m == (1ull << 53)) {
+            m >>= 1;
+            ++e;
+          }
+        }
+        const int field = e - 51;  // 2^t units of 2^-1074 is 2^(t-1074)
+        if (field >= 2047) {
+          bits = sign | F64::kInf;
+          exact = false;
+        } else {
+          bits = sign | ((uint64_t)field << 52) | (m & ((1ull << 52) - 1));
+        }
+      }
+    }
+  }
+  gstore(out + 0, bits);
+  gstore(out + 1, (uint64_t)(exact ? 1u : 0u));
+}
+
 __global__ void k_reduce_final(FallbackParams P) {
   if (threadIdx.x != 0) return;
+  if (P.sum_out) sum_final(P.st, P.sum_out);
+  if (!P.reduce_out) return;
   const unsigned long long kmin = P.st->red_min;
   const unsigned long long kmax = P.st->red_max;
   const unsigned long long cnt = P.st->red_count;
@@ -1090,7 +1313,7 @@ static void launch_parse_mode(const ParseParams& P, int grid, hipStream_t s) {
 
 template <int K, bool kSingle>
 static hipError_t launch_parse_k(const ParseParams& P, int grid, hipStream_t s) {
-  if (P.reduce_out)
+  if (P.reduce_out || P.sum_out)
     launch_parse_mode<K, kSingle, true>(P, grid, s);
   else
     launch_parse_mode<K, kSingle, false>(P, grid, s);
@@ -1108,7 +1331,12 @@ hipError_t launch_parse(int k, bool single_delim, const ParseParams& P, int grid
 
 hipError_t launch_fallback(const FallbackParams& P, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_fallback, dim3(grid), dim3(kFbThreads), 0, s, P);
-  if (P.reduce_out) hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kWave), 0, s, P);
+  return launch_reduce_final(P, s);
+}
+
+hipError_t launch_reduce_final(const FallbackParams& P, hipStream_t s) {
+  if (P.reduce_out || P.sum_out)
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kWave), 0, s, P);
   return hipGetLastError();
 }
 

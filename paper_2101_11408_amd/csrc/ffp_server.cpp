@@ -115,7 +115,10 @@ struct ffp_server {
   // released requests whose result copies are still in flight
   std::vector<Req*> deferred;
   uint64_t next_ticket = 1;
-  uint64_t epoch = 0;  // bumped by every event that can unblock admission
+  // bumped (under mu) by every event that can unblock admission; read
+  // without the lock while the idle dispatcher polls
+  std::atomic<uint64_t> epoch{0};
+  uint64_t spin_ns = 0;  // idle dispatcher: polling time before it sleeps
   bool stopping = false;
   uint64_t n_submitted = 0, n_completed = 0, n_batches = 0, n_bytes = 0, max_batch_seen = 0,
            n_cancelled = 0;
@@ -322,6 +325,22 @@ struct ffp_server {
         std::this_thread::yield();
         continue;
       }
+      if (spin_ns && !stopping) {
+        // poll for new work before sleeping: a condition-variable wake-up
+        // costs several microseconds of a request's latency
+        lk.unlock();
+        const uint64_t t0 = now_ns();
+        bool woke = false;
+        while (now_ns() - t0 < spin_ns) {
+          if (epoch.load(std::memory_order_acquire) != seen_epoch) {
+            woke = true;
+            break;
+          }
+          std::this_thread::yield();
+        }
+        lk.lock();
+        if (woke) continue;
+      }
       cv_work.wait(lk, [&] { return stopping || epoch != seen_epoch; });
     }
   }
@@ -363,6 +382,7 @@ int ffp_server_create(ffp_ctx* ctx, const ffp_server_options* opts, ffp_server**
   srv->device = ctx->device;
   srv->mode = o.mode;
   srv->use_graph = o.mode == FFP_SERVE_BATCHED && o.use_graph != 0;
+  srv->spin_ns = (uint64_t)o.spin_us * 1000u;
   srv->max_batch_bytes = batch_bytes;
   srv->max_batch_jobs = jobs;
   srv->max_inflight = o.max_inflight ? o.max_inflight : kDefaultInflight;

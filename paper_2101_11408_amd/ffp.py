@@ -73,7 +73,8 @@ class ffp_server_options(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_batch_bytes", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_uint32), ("streams", ctypes.c_uint32),
                 ("max_batch_jobs", ctypes.c_uint32), ("mode", ctypes.c_uint32),
-                ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("use_graph", ctypes.c_uint32), ("spin_us", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class ffp_result(ctypes.Structure):
@@ -130,6 +131,7 @@ _SIGNATURES = {
     "ffp_timing_read": (_INT, [_P, _c.POINTER(_c.c_double), _c.POINTER(_U64)]),
     "ffp_counters_enable": (_INT, [_P, _INT]),
     "ffp_set_reduce": (_INT, [_P, _P]),
+    "ffp_set_reduce_sum": (_INT, [_P, _P]),
     "ffp_counters_read": (_INT, [_P, _U64 * 6]),
     "ffp_parse_batch": (_INT, [_P, _P, _c.c_uint32, _U64, _P]),
     "ffp_batch_graph_create": (_INT, [_P, _P, _c.c_uint32, _U64, _c.POINTER(_P)]),
@@ -309,6 +311,13 @@ class Context:
         written by every later plain call; None turns the reduction off."""
         check(load().ffp_set_reduce(self.handle, out.data_ptr() if out is not None else None))
 
+    def set_reduce_sum(self, out=None):
+        """out: device int64 tensor of 2 elements (binary64 bits of the exact
+        sum rounded once, 1 if exact) written by every later plain call;
+        None turns the sum off."""
+        check(load().ffp_set_reduce_sum(self.handle,
+                                        out.data_ptr() if out is not None else None))
+
     def counters_read(self):
         arr = (ctypes.c_uint64 * 6)()
         check(load().ffp_counters_read(self.handle, arr))
@@ -466,8 +475,9 @@ class Server:
     """A request server (continuous batching) created from a Context."""
 
     def __init__(self, ctx, hbm_budget_bytes=0, max_batch_bytes=0, max_inflight=0, streams=0,
-                 max_batch_jobs=0, mode=FFP_SERVE_BATCHED, use_graph=False):
+                 max_batch_jobs=0, mode=FFP_SERVE_BATCHED, use_graph=False, spin_us=0):
         o = ffp_server_options()
+        o.spin_us = spin_us
         o.hbm_budget_bytes = hbm_budget_bytes
         o.max_batch_bytes = max_batch_bytes
         o.max_inflight = max_inflight

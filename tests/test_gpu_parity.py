@@ -911,3 +911,40 @@ def test_json_document_plain_calls_only(ffpmod):
         assert v[:2].cpu().tolist() == [1.0, 3.0]
     finally:
         c.close()
+
+
+def test_small_calls_alternate_device_states(ffpmod):
+    """Plain calls of at most 8 blocks of 4 KiB run without the count kernel,
+    on two spare device states used in turn; larger calls use the main state
+    and clean both spares.  A mixed sequence on one context (fallback tokens
+    queued in some calls, a capacity error in one, texts that start
+    mid-granule): each call matches the oracle and reports its own count and
+    error code."""
+    rng = np.random.default_rng(300)
+    easy = W.join_tokens(W.mixed_tokens(rng, 1200))                     # ~24 KB
+    hard = W.join_tokens(W.hard_tokens(rng, 90))                        # ~29 KB, queued
+    big = W.join_tokens(W.mixed_tokens(rng, 20000) + W.hard_tokens(rng, 200))  # ~450 KB
+    one_block = b"1.5\n-2e3\n" + b"0.1\n" * 900                        # below 4 KiB
+    seq = [("hard", hard, None, 0), ("easy", easy, None, 0), ("big", big, None, 0),
+           ("hard", hard, None, 7), ("hard", hard, None, 0), ("easy-cap", easy, 100, 0),
+           ("one-block", one_block, None, 3), ("easy", easy, None, 5), ("big", big, None, 1),
+           ("one-block", one_block, None, 0)]
+    c = ffpmod.Context(0)
+    try:
+        for label, buf, cap, off in seq:
+            _log("case alternate states", label, len(buf), "bytes, offset", off)
+            for fmt in ("f64", "f32"):
+                rc, n, bits, status = run_gpu(c, buf, fmt, capacity=cap, offset=off)
+                wb, ws = parse_buffer(buf, fmt)
+                assert n == len(wb), (label, fmt, n, len(wb))
+                k = len(wb) if cap is None else min(cap, len(wb))
+                if cap is not None and cap < len(wb):
+                    assert rc == ffpmod.FFP_E_CAPACITY, (label, rc)
+                else:
+                    assert rc == len(wb), (label, rc)
+                bad = np.flatnonzero((bits[:k] != np.array(wb[:k], dtype=NP_DT[fmt])) |
+                                     (status[:k] != np.array(ws[:k], dtype=np.uint8)))
+                assert bad.size == 0, (label, fmt, bad[:5])
+                assert c.last_device_error() == 0, label
+    finally:
+        c.close()
