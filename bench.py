@@ -56,6 +56,7 @@ WORKLOAD_NAMES = {
     "config5": "config5-served-poisson",
     "copycal": "copy-calibration",
     "jsondoc": "jsondoc-10M-coordinates-binary64-plain",
+    "csv": "csv-1M-rows-5-of-10-columns-binary64-plain",
     "hexfloat": "hexfloat-10M-binary64-plain",
 }
 ROUND_FLAGS = {"nearest": 0x00, "zero": 0x10, "up": 0x20, "down": 0x30}
@@ -176,10 +177,13 @@ _SHARED = {}
 
 
 def _oracle_chunk(args):
-    from oracle import parse_buffer, parse_json_document
+    from oracle import parse_buffer, parse_csv, parse_json_document
     import numpy as np
     a, b, fmt = args
-    if _SHARED.get("doc"):
+    if _SHARED.get("csv") is not None:
+        bits, st = parse_csv(_SHARED["text"][a:b], _SHARED["csv"], fmt, _SHARED["delims"],
+                             _SHARED["flags"] & ~0x80)
+    elif _SHARED.get("doc"):
         bits, st = parse_json_document(_SHARED["text"][a:b], fmt, flags=_SHARED["flags"])
     else:
         bits, st = parse_buffer(_SHARED["text"][a:b], fmt, delims=_SHARED["delims"],
@@ -197,7 +201,7 @@ def _oracle_tokens(args):
 
 
 def cpu_baseline_leg(text: bytes, fmts, extra_tokens=(), delims=b"\n", flags=0, what="",
-                     doc_split=None):
+                     doc_split=None, csv_columns=None):
     """Times the oracle over every token of `text` (for each output format
     in `fmts`) and over `extra_tokens` (cut tokens of slices), on the box's
     CPU share.  With doc_split the text is a JSON document read as one
@@ -206,7 +210,10 @@ def cpu_baseline_leg(text: bytes, fmts, extra_tokens=(), delims=b"\n", flags=0, 
     (cpu_baseline record, {fmt: (bits, status)} for the text's tokens,
     {fmt: (bits, status)} for the extra tokens)."""
     import numpy as np
-    _SHARED.update(text=text, delims=delims, flags=flags, doc=doc_split is not None)
+    _SHARED.update(text=text, delims=delims, flags=flags, doc=doc_split is not None,
+                   csv=csv_columns)
+    if csv_columns is not None:  # a CSV table is cut after row ends only
+        doc_split = b"\n"
     nw = workers()
     # chunks cut at delimiters (or after doc_split), several per worker
     nchunk = max(1, min(64 * nw, len(text) // 4096 or 1))
@@ -410,7 +417,7 @@ def timed_steps(torch, fn, steps, warmup, spinup_ms=0.0):
 # ---------------------------------------------------------------------------
 
 def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims=b"\n",
-              flags=0, expect_ok=None, doc_split=None):
+              flags=0, expect_ok=None, doc_split=None, csv_columns=None):
     import numpy as np
     import torch
     from paper_2101_11408_amd import ffp
@@ -422,6 +429,8 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims
     status = torch.empty(ntok, dtype=torch.uint8, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     ctx = ffp.Context(0, delims=delims, flags=flags)
+    if csv_columns is not None:
+        ctx.set_csv_columns(csv_columns)
     ctx.reserve(len(buf))
     red = None
     if args.reduce:
@@ -462,7 +471,8 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims
     rec["cpu_baseline"] = None
     if cpu and not args.profile:
         cb, res, _ = cpu_baseline_leg(buf, [out_dtype], delims=delims, flags=flags,
-                                      what="the whole buffer", doc_split=doc_split)
+                                      what="the whole buffer", doc_split=doc_split,
+                                      csv_columns=csv_columns)
         wb, ws = res[out_dtype]
         rec["cpu_baseline"] = cb
         rec["parity"] = {"vs": "oracle", "tokens_checked": int(len(wb)),
@@ -954,7 +964,7 @@ def main():
                     help="untimed calls for this long before the warmup steps (GPU clock ramp)")
     ap.add_argument("--workload", default="config4u",
                     choices=["config1", "config2", "config3", "config4", "config4u",
-                             "config5", "copycal", "jsondoc", "hexfloat"])
+                             "config5", "copycal", "jsondoc", "hexfloat", "csv"])
     ap.add_argument("--round", default="nearest", choices=sorted(ROUND_FLAGS),
                     help="plain workloads: rounding direction (FFP_ROUND_*)")
     ap.add_argument("--tokens", type=int, default=None)
@@ -1059,6 +1069,19 @@ def main():
                         % (len(doc) / 1e6, nfeat, OUT_NAMES[args.out]),
                         out_dtype=args.out, cpu=cpu, flags=0x40, expect_ok=ntok,
                         doc_split=b"]]}},")
+    elif wl == "csv":
+        t0 = time.time()
+        rows = (args.tokens or 5_000_000) // 5
+        table = W.csv_benchmark_table(8, rows)
+        ntok = rows * 5  # five selected numeric columns, one token each
+        log("generated %d bytes in %.1f s" % (len(table), time.time() - t0))
+        rec = run_plain(args, table, ntok, out_name(wl, args.out),
+                        "CSV table (%.1f MB): %d rows of 10 columns (id, word, two coordinates, "
+                        "a uniform double, a %%.17e double, a flag word, a price, a quantity, a "
+                        "word); FFP_CSV selecting the five decimal columns; %s"
+                        % (len(table) / 1e6, rows, OUT_NAMES[args.out]),
+                        out_dtype=args.out, cpu=cpu, delims=b",\n", flags=0x80,
+                        expect_ok=ntok, csv_columns=W.CSV_BENCH_COLUMNS)
     elif wl == "hexfloat":
         import numpy as np
         n = args.tokens or 10_000_000

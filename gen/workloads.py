@@ -533,3 +533,67 @@ def json_tricky_document(seed: int, nitems: int, indent=None, long_strings=False
     doc = [value(0) for _ in range(nitems)]
     ensure_ascii = bool(rng.random() < 0.5)
     return (json.dumps(doc, indent=indent, ensure_ascii=ensure_ascii) + "\n").encode()
+
+
+def csv_table(rng, rows: int, max_cols: int = 80, extra_space: bool = False, crlf: bool = False,
+              trailing_newline: bool = True, long_field_every: int = 0) -> str:
+    """A CSV table (no quoting) of `rows` rows of 1..max_cols fields: empty
+    fields, words, decimals of all magnitudes, integers, exponents and
+    out-of-range values; with extra_space, spaces around some fields; with
+    crlf, rows end in CR LF; long_field_every > 0 puts a 3-9 KB word field in
+    every such row (rows longer than a 4 KiB window)."""
+    lines = []
+    for r in range(rows):
+        ncol = int(rng.integers(1, max_cols))
+        fields = []
+        for _ in range(ncol):
+            k = rng.integers(0, 6)
+            if k == 0:
+                f = ""
+            elif k == 1:
+                f = "abc%d" % rng.integers(0, 100)
+            elif k == 2:
+                f = "%.17g" % (rng.standard_normal() * 10.0 ** rng.integers(-30, 30))
+            elif k == 3:
+                f = str(int(rng.integers(-10 ** 6, 10 ** 6)))
+            elif k == 4:
+                f = "-%d.%de%d" % (rng.integers(0, 99), rng.integers(0, 99), rng.integers(-20, 20))
+            else:
+                f = "1e999"
+            if extra_space and f and rng.integers(0, 2):
+                f = " " * int(rng.integers(1, 3)) + f + " " * int(rng.integers(0, 2))
+            fields.append(f)
+        if long_field_every and r % long_field_every == 0:
+            fields.insert(int(rng.integers(0, len(fields) + 1)), "w" * int(rng.integers(3000, 9000)))
+        lines.append(",".join(fields))
+    sep = "\r\n" if crlf else "\n"
+    return sep.join(lines) + (sep if trailing_newline else "")
+
+
+# Columns of the CSV benchmark table: id, name, lon, lat, value, big, flag,
+# price, qty, note; the numeric columns selected are lon, lat, value, big
+# and price.
+CSV_BENCH_COLUMNS = (1 << 2) | (1 << 3) | (1 << 4) | (1 << 5) | (1 << 7)
+
+
+def csv_benchmark_table(seed: int, rows: int) -> bytes:
+    """A ten-column CSV table (no quoting, '\\n' rows): an integer id, a
+    word, two coordinates with 6-15 fraction digits, a uniform [0,1) double
+    in shortest digits, a random double as %.17e, a flag word, a price with
+    two decimals, an integer quantity and a word; see CSV_BENCH_COLUMNS."""
+    rng = np.random.default_rng(seed)
+    lon = coordinates(rng, rows)
+    lat = coordinates(rng, rows)
+    val = uniform_shortest(rng, rows)
+    big = random_bits_e17(rng, rows)
+    price = rng.integers(0, 10 ** 7, rows).tolist()
+    qty = rng.integers(0, 1000, rows).tolist()
+    flags = rng.integers(0, 3, rows).tolist()
+    words = ["alpha", "beta", "gamma", "delta", "eps", "zeta12", "eta", "theta"]
+    wi = rng.integers(0, len(words), (rows, 2)).tolist()
+    out = []
+    for i in range(rows):
+        out.append("%d,%s,%s,%s,%s,%s,%s,%d.%02d,%d,%s\n" % (
+            i, words[wi[i][0]], lon[i], lat[i], val[i], big[i], ("yes", "no", "")[flags[i]],
+            price[i] // 100, price[i] % 100, qty[i], words[wi[i][1]]))
+    return "".join(out).encode()

@@ -93,6 +93,19 @@ enum ffp_error {
  * quote.  Plain calls only: batched calls and servers on such a context
  * return FFP_E_ARG. */
 #define FFP_JSON_DOCUMENT 0x40u
+/* CSV number columns (structural parsing of a table, named as future work
+ * in Section 13): the buffer is a table whose rows end at '\n' and whose
+ * fields are separated by ','; a token's column is the number of ',' bytes
+ * between the last '\n' before it (or the buffer's start) and the token.
+ * Tokens are the runs of non-delimiter bytes as usual (the delimiter set
+ * must contain ',' and '\n'; other members, such as ' ' or '\r', delimit
+ * tokens without starting a field or a row), and only the tokens of the
+ * columns selected by ffp_set_csv_columns get indices, in buffer order; the
+ * other flags' grammar applies to them.  Fields are not quoted.  Does not
+ * combine with FFP_HEX, a directed rounding mode or FFP_JSON_DOCUMENT
+ * (FFP_E_ARG).  Plain calls only: batched calls and servers on such a
+ * context return FFP_E_ARG. */
+#define FFP_CSV 0x80u
 /* Rounding direction, a two-bit field of the flags (IEEE 754 rounding-
  * direction attributes; the paper rounds to nearest and notes that its
  * method extends to the other modes, footnote of Section 6).  0 selects
@@ -352,6 +365,11 @@ int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches);
  * NULL turns it off.  Batched calls ignore it.
  * ------------------------------------------------------------------------- */
 int ffp_set_reduce(ffp_ctx* ctx, uint64_t* d_out);
+
+/* Columns of a FFP_CSV context whose tokens are parsed: bit c selects column
+ * c (columns from 64 on are never selected).  Default: every column below 64.
+ * Applies to the calls made after it. */
+int ffp_set_csv_columns(ffp_ctx* ctx, uint64_t columns);
 
 /* ---------------------------------------------------------------------------
  * Exact in-kernel sum (an extension of the reduction above; Section 12's

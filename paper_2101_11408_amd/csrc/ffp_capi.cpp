@@ -102,8 +102,8 @@ bool plain_instance(const ffp_ctx* ctx, bool reduce) {
 // has too few of them to fill a round, and each round lasts as long as its
 // longest token, so such calls take 16 KiB tiles too (capacity 0: unknown).
 int auto_tile_k(const ffp_ctx* ctx, bool reduce, uint64_t bytes = 0, uint64_t capacity = 0) {
-  // JSON documents: 8 KiB tiles (the 16 KiB instance spills registers)
-  if (ctx->flags & FFP_JSON_DOCUMENT) return 2;
+  // JSON documents and CSV: 8 KiB tiles (the 16 KiB instances spill registers)
+  if (ctx->flags & (FFP_JSON_DOCUMENT | FFP_CSV)) return 2;
   const bool long_tokens = capacity > 0 && bytes / capacity >= 64;
   return plain_instance(ctx, reduce) && !long_tokens ? 2 : 4;
 }
@@ -179,13 +179,14 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
   // (the parse kernel's 4 KiB-tile instances carry the summation)
   // (JSON documents need the scan: it gives each block its string state)
   const bool json_doc = (ctx->flags & FFP_JSON_DOCUMENT) != 0;
+  const bool csv = (ctx->flags & FFP_CSV) != 0;
   uint64_t* const reduce_out = js.jobs ? nullptr : ctx->reduce_out;  // plain calls only
   uint64_t* const sum_out = js.jobs ? nullptr : ctx->sum_out;
   const bool count_paths = ctx->counters && !sc.fixed;
   // (the reductions and the path counters live in the main state)
   const bool self_count = !js.jobs && !sc.fixed && ctx->d_spare && nblocks > 0 &&
                           nblocks <= kSelfCountMaxBlocks && shape.tile_k == 1 &&
-                          js.block_shift == ffp::kMinBlockShift && !json_doc &&
+                          js.block_shift == ffp::kMinBlockShift && !json_doc && !csv &&
                           !reduce_out && !sum_out && !count_paths;
   const bool sum_in_parse = !self_count && nblocks > 0 && max_blocks <= kSumInParseMaxBlocks &&
                             shape.tile_k == 1 && !json_doc;
@@ -216,6 +217,8 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
     cp.spare = spare;
     cp.reset_state = sum_in_parse ? 1u : 0u;
     cp.json_doc = json_doc ? 1u : 0u;
+    cp.csv = csv ? 1u : 0u;
+    cp.csv_columns = ctx->csv_columns;
     uint64_t grid = (uint64_t)ctx->num_cus * 8;
     if (grid > nblocks) grid = nblocks;
     if (ffp::launch_count(ctx->delim.single != 0, cp, (int)grid, s) != hipSuccess) return FFP_E_HIP;
@@ -242,6 +245,7 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
   P.sum_in_parse = sum_in_parse ? 1u : 0u;
   P.self_count = self_count ? 1u : 0u;
   P.other_st = other;
+  P.csv_columns = ctx->csv_columns;
   P.reduce_out = reduce_out;
   P.sum_out = sum_out;
   uint64_t grid = (uint64_t)shape.grid;
@@ -347,7 +351,7 @@ int batch_common(ffp_ctx* ctx, ffp_job* d_jobs, uint32_t njobs, uint64_t max_tot
                  hipStream_t s) {
   if (!ctx || !d_jobs || njobs == 0 || njobs > kMaxJobs) return FFP_E_ARG;
   if (max_total_bytes >= kMaxBatchBytes) return FFP_E_ARG;
-  if (ctx->flags & FFP_JSON_DOCUMENT) return FFP_E_ARG;  // plain calls only
+  if (ctx->flags & (FFP_JSON_DOCUMENT | FFP_CSV)) return FFP_E_ARG;  // plain calls only
   DeviceGuard g(ctx->device);
   // at least two jobs' worth of job table, so that grow() sizes it
   int rc = grow(ctx, max_total_bytes, njobs < 2 ? 2 : njobs);
@@ -541,8 +545,14 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
     o.delim_set['\n' >> 6] |= 1ull << ('\n' & 63);
   }
   if (o.flags & ~(FFP_REJECT_PLUS | FFP_JSON | FFP_INFNAN | FFP_HEX | FFP_ROUND_MASK |
-                  FFP_JSON_DOCUMENT))
+                  FFP_JSON_DOCUMENT | FFP_CSV))
     return FFP_E_ARG;
+  if (o.flags & FFP_CSV) {
+    // CSV: ',' and '\n' separate fields and rows; hexadecimal tokens,
+    // directed rounding and JSON documents do not combine with it
+    if (o.flags & (FFP_HEX | FFP_ROUND_MASK | FFP_JSON_DOCUMENT)) return FFP_E_ARG;
+    if (!((o.delim_set[0] >> ',') & 1) || !((o.delim_set[0] >> '\n') & 1)) return FFP_E_ARG;
+  }
   if (o.flags & FFP_JSON_DOCUMENT) {
     // JSON text: the structural characters, whitespace and the quote delimit
     // the number tokens; the JSON number grammar applies
@@ -570,6 +580,7 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   ctx->delim.single = members == 1 && first < 0x80 ? 1u : 0u;
   ctx->delim.byte = (uint32_t)first;
   ctx->flags = o.flags;
+  ctx->csv_columns = ~0ull;
 
   DeviceGuard g(hip_device);
   hipDeviceProp_t prop;
@@ -890,6 +901,12 @@ int ffp_timing_read(ffp_ctx* ctx, double* total_ms, uint64_t* launches) {
 int ffp_set_reduce(ffp_ctx* ctx, uint64_t* d_out) {
   if (!ctx) return FFP_E_ARG;
   ctx->reduce_out = d_out;
+  return FFP_SUCCESS;
+}
+
+int ffp_set_csv_columns(ffp_ctx* ctx, uint64_t columns) {
+  if (!ctx) return FFP_E_ARG;
+  ctx->csv_columns = columns;
   return FFP_SUCCESS;
 }
 

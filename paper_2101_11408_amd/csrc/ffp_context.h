@@ -54,6 +54,7 @@ struct ffp_ctx {
   bool counters = false;
   uint64_t* reduce_out = nullptr;  // plain calls: min, max, count of the values
   uint64_t* sum_out = nullptr;     // plain calls: exact sum of the values
+  uint64_t csv_columns = ~0ull;    // FFP_CSV: the selected columns
 };
 
 struct ffp_graph {

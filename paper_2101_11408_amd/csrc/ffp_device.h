@@ -458,6 +458,7 @@ constexpr uint32_t kFlagJson = 2;    // JSON number grammar
 constexpr uint32_t kFlagInfNan = 4;  // inf, infinity, nan in any case
 constexpr uint32_t kFlagHex = 8;     // hexadecimal floating-point tokens
 constexpr uint32_t kFlagJsonDoc = 0x40;  // JSON documents: numbers outside strings
+constexpr uint32_t kFlagCsv = 0x80;      // CSV: tokens of the selected columns
 
 FFP_HD int hex_value(uint32_t c) {
   if (c - '0' < 10u) return (int)(c - '0');

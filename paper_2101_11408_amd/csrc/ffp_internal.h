@@ -160,6 +160,8 @@ struct CountParams {
   DeviceState* spare;   // with reset_state: the context's two spare states (or null)
   uint32_t reset_state;
   uint32_t json_doc;    // FFP_JSON_DOCUMENT: counts for both entry states
+  uint32_t csv;         // FFP_CSV: only tokens of the selected columns count
+  uint64_t csv_columns; // FFP_CSV: bit c selects column c (c < 64)
 };
 
 // JSON documents: a block's count word holds the tokens starting in it when
@@ -198,6 +200,7 @@ struct ParseParams {
   // the call resets the other one (other_st) for the next such call.
   uint32_t self_count;
   DeviceState* other_st;
+  uint64_t csv_columns;  // FFP_CSV: bit c selects column c (c < 64)
 };
 
 struct FallbackParams {

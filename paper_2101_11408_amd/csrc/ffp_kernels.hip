@@ -403,6 +403,165 @@ __device__ void count_json_doc(const CountParams& P, const uint8_t* lut, uint32_
   }
 }
 
+// ---------------------------------------------------------------------------
+// CSV number columns (FFP_CSV): rows end at '\n', fields are separated by
+// ',', and a token's column is the number of ',' bytes between the last '\n'
+// before it (or the text's start) and the token.  The column state is a
+// segmented count: a '\n' resets it, a ',' adds one.
+// ---------------------------------------------------------------------------
+struct CsvBits {
+  uint32_t nl, cm;  // '\n' and ',' bytes of 16 (bits outside the text cleared)
+};
+
+// The bytes of a chunk at virtual offset off that lie in the text [align, vend).
+__device__ __forceinline__ uint32_t text_bits(uint64_t off, uint64_t align, uint64_t vend) {
+  uint32_t valid = 0xFFFFu;
+  if (off < align) valid &= 0xFFFFu << (uint32_t)(align - off);
+  if (off + kChunk > vend) valid &= off >= vend ? 0u : (1u << (uint32_t)(vend - off)) - 1u;
+  return valid;
+}
+
+__device__ __forceinline__ CsvBits csv_chunk(uint4 v, uint32_t valid) {
+  constexpr uint32_t kNl = '\n' * 0x01010101u, kCm = ',' * 0x01010101u;
+  CsvBits b;
+  b.nl = pack_high_bits(byte_eq_word(v.x, kNl), byte_eq_word(v.y, kNl), byte_eq_word(v.z, kNl),
+                        byte_eq_word(v.w, kNl)) & valid;
+  b.cm = pack_high_bits(byte_eq_word(v.x, kCm), byte_eq_word(v.y, kCm), byte_eq_word(v.z, kCm),
+                        byte_eq_word(v.w, kCm)) & valid;
+  return b;
+}
+
+// Segment word of a run of bytes: bit 31 set when the run holds a '\n';
+// bits 0..30 the ',' bytes after its last '\n' (all of them without one).
+constexpr uint32_t kSegNl = 0x80000000u;
+
+__device__ __forceinline__ uint32_t csv_seg(const CsvBits& b) {
+  if (b.nl) return kSegNl | (uint32_t)__popc(b.cm >> (31 - __builtin_clz(b.nl)));
+  return (uint32_t)__popc(b.cm);
+}
+
+// The segment word of run a followed by run b (0 is the empty run).
+__device__ __forceinline__ uint32_t csv_seg_then(uint32_t a, uint32_t b) {
+  return (b & kSegNl) ? b : (a & kSegNl) | ((a + b) & ~kSegNl);
+}
+
+// Exclusive scan of segment words over the kThreads threads of a block (in
+// thread order); `total` receives the whole block's word.  s_tmp holds
+// kThreads / kWave words and must not be reused before the next barrier.
+__device__ __forceinline__ uint32_t block_excl_segscan(uint32_t x, uint32_t& total,
+                                                       uint32_t* s_tmp) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d, kWave);
+    if (lane >= d) inc = csv_seg_then(o, inc);
+  }
+  if (lane == kWave - 1) s_tmp[wid] = inc;
+  uint32_t ex = __shfl_up(inc, 1, kWave);
+  if (lane == 0) ex = 0;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / kWave; ++w) {
+    if (w < wid) pre = csv_seg_then(pre, s_tmp[w]);
+    tot = csv_seg_then(tot, s_tmp[w]);
+  }
+  total = tot;
+  return csv_seg_then(pre, ex);
+}
+
+// Column at virtual offset vstart (a multiple of the chunk size) of a job:
+// the ',' bytes back to the last '\n' before it, read backwards 4 KiB at a
+// time by the whole workgroup (the same value in every thread).
+__device__ uint32_t csv_entry_column(const uint8_t* vbase, uint64_t align, uint64_t vend,
+                                     uint64_t vstart, uint32_t* s_tmp) {
+  const int tid = threadIdx.x;
+  uint32_t acc = 0;  // segment word of [window start, vstart)
+  uint64_t hi = vstart;
+  while (hi > 0) {
+    const uint64_t lo = hi > (uint64_t)kThreads * kChunk ? hi - (uint64_t)kThreads * kChunk : 0;
+    const uint64_t off = lo + (uint64_t)tid * kChunk;
+    uint32_t seg = 0;
+    if (off < hi) seg = csv_seg(csv_chunk(load_chunk(vbase, off, align, vend, 0u),
+                                          text_bits(off, align, vend)));
+    uint32_t tot;
+    (void)block_excl_segscan(seg, tot, s_tmp);
+    __syncthreads();  // s_tmp is consumed
+    acc = csv_seg_then(tot, acc);
+    if (acc & kSegNl) break;  // the same in every thread
+    hi = lo;
+  }
+  return acc & ~kSegNl;
+}
+
+// The starts among `starts` (bits of one chunk) whose column, given the
+// column `entry` at the chunk's first byte, is selected.
+__device__ __forceinline__ uint32_t csv_select(uint32_t starts, const CsvBits& b, uint32_t entry,
+                                               uint64_t columns) {
+  uint32_t keep = 0;
+  while (starts) {
+    const int k = __builtin_ctz(starts);
+    starts &= starts - 1;
+    const uint32_t below = (1u << k) - 1u;
+    const uint32_t nlb = b.nl & below;
+    uint32_t col;
+    if (nlb) {
+      const uint32_t after = ~((2u << (31 - __builtin_clz(nlb))) - 1u);
+      col = (uint32_t)__popc(b.cm & below & after);
+    } else {
+      col = entry + (uint32_t)__popc(b.cm & below);
+    }
+    if (col < 64 && ((columns >> col) & 1u)) keep |= 1u << k;
+  }
+  return keep;
+}
+
+// k_count for CSV: per block, the tokens of the selected columns.  The
+// column at the block's start comes from a backward read to the last '\n';
+// within the block, rows of 256 chunks are scanned one after the other.
+template <int kRows>
+__device__ void count_csv(const CountParams& P, const uint8_t* lut, uint32_t* s_scan,
+                          uint16_t* s_nd) {
+  constexpr uint32_t kShift = kRows == 1 ? 12 : (kRows == 4 ? 14 : 16);
+  __shared__ uint32_t s_prev;
+  const int tid = threadIdx.x;
+  const uint64_t nblk = total_blocks_of(P.js);
+  for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const JobDesc job = job_of_block(P.js, b);
+    const uint64_t align = (uint64_t)(uintptr_t)job.text & 15u;
+    const uint8_t* vbase = job.text - align;
+    const uint64_t vend = job.nbytes + align;
+    const uint64_t bstart = (b - job.block_begin) << kShift;
+    __syncthreads();  // s_nd / s_prev / s_scan of the previous block are consumed
+    uint32_t col = csv_entry_column(vbase, align, vend, bstart, s_scan);
+    if (tid == 0) s_prev = prev_nondelim(vbase, bstart, align, P.delim);
+    uint32_t n = 0;
+    // one row at a time (no per-row arrays: this kernel serves every
+    // delimiter set, and its registers bound its occupancy)
+#pragma unroll 1
+    for (int r = 0; r < kRows; ++r) {
+      const int chunk = r * kThreads + tid;
+      const uint64_t off = bstart + (uint64_t)chunk * kChunk;
+      const uint4 v = load_chunk(vbase, off, align, vend, P.delim.byte);
+      const uint32_t m = off < vend ? nondelim_mask16<false>(v, 0u, lut) : 0u;
+      const CsvBits cb = csv_chunk(v, text_bits(off, align, vend));
+      s_nd[chunk] = (uint16_t)m;
+      uint32_t row;
+      // (its barrier also publishes s_nd and s_prev)
+      const uint32_t ex = block_excl_segscan(csv_seg(cb), row, s_scan);
+      const uint32_t pb = chunk == 0 ? s_prev : ((uint32_t)s_nd[chunk - 1] >> 15);
+      const uint32_t entry = (ex & kSegNl) ? (ex & ~kSegNl) : col + ex;
+      n += __popc(csv_select(m & ~((m << 1) | pb) & 0xFFFFu, cb, entry, P.csv_columns));
+      col = (row & kSegNl) ? (row & ~kSegNl) : col + row;
+      __syncthreads();  // s_scan is read before the next row writes it
+    }
+    uint32_t total;
+    (void)block_excl_scan<kThreads>(n, total, s_scan);
+    if (tid == 0) P.block_sum[b] = total;
+  }
+}
+
 template <bool kSingle, int kRows>
 __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
   constexpr int kCountRows = kRows;
@@ -428,6 +587,11 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
   const uint64_t nblk = total_blocks_of(P.js);
   if (!kSingle && P.json_doc) {
     count_json_doc<kRows>(P, s_lut, s_scan, reinterpret_cast<uint8_t*>(s_nd));
+    return;
+  }
+  if (!kSingle && P.csv) {
+    __syncthreads();  // the delimiter table is written
+    count_csv<kRows>(P, s_lut, s_scan, s_nd);
     return;
   }
   for (uint64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
@@ -701,6 +865,9 @@ k_parse(ParseParams P) {
   __shared__ S sm;
   // the exact sum's accumulators of this workgroup (reduction instances)
   __shared__ unsigned long long s_sum[kReduce ? 2 * kSumLimbs : 1];
+  // CSV: the column scans' wave totals
+  constexpr bool csv = kMode == kModeCsv;
+  __shared__ uint32_t s_seg[csv ? kThreads / kWave : 1];
   __shared__ uint32_t s_sum_flags;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -792,6 +959,13 @@ k_parse(ParseParams P) {
         tid != 0 ? 0u
         : doc    ? doc_prev_token(job.text, (int64_t)bstart - (int64_t)align, block_entry, P.delim)
                  : prev_nondelim(vbase, bstart, align, P.delim);
+    // CSV: the column at the block's start (then carried from tile to tile;
+    // the same value in every thread)
+    uint32_t csv_col = 0;
+    if (csv) {
+      __syncthreads();  // s_seg of the previous block is consumed
+      csv_col = csv_entry_column(vbase, align, vend, bstart, s_seg);
+    }
     for (int t = 0; t < ntiles; ++t) {
       const uint64_t tile_start = bstart + (uint64_t)t * S::kBytes;  // virtual
       if (tile_start >= vend) break;
@@ -812,6 +986,7 @@ k_parse(ParseParams P) {
       __syncthreads();  // LDS of the previous tile is consumed
       // -- store the tile to LDS and classify bytes ---------------------
       uint32_t ndm[K], dgm[K];
+      CsvBits cb[csv ? K : 1];
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         const int chunk = c * kThreads + tid;
@@ -821,6 +996,20 @@ k_parse(ParseParams P) {
         sm.nd[chunk] = (uint16_t)ndm[c];
         dgm[c] = pack_high_bits(digit_word(v.x), digit_word(v.y), digit_word(v.z), digit_word(v.w));
         sm.dg[chunk] = (uint16_t)dgm[c];
+        if (csv)
+          cb[c] = csv_chunk(v, text_bits(tile_start + (uint64_t)chunk * kChunk, align, vend));
+      }
+      // CSV: the column at each chunk's first byte, row after row of the tile
+      uint32_t csv_entry[csv ? K : 1];
+      if (csv) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          uint32_t row;
+          const uint32_t ex = block_excl_segscan(csv_seg(cb[c]), row, s_seg);
+          csv_entry[c] = (ex & kSegNl) ? (ex & ~kSegNl) : csv_col + ex;
+          csv_col = (row & kSegNl) ? (row & ~kSegNl) : csv_col + row;
+          __syncthreads();  // s_seg is read before the next row writes it
+        }
       }
       // JSON documents: token bytes are the non-delimiters outside strings;
       // the string state of each chunk comes from a block scan of its
@@ -878,6 +1067,7 @@ k_parse(ParseParams P) {
         const uint32_t m = doc ? tbm[c] : ndm[c];
         startm[c] = m & ~((m << 1) | prevbit) & 0xFFFFu;
         if (doc) startm[c] &= msm[c];  // numbers start with '-' or a digit
+        if (csv) startm[c] = csv_select(startm[c], cb[c], csv_entry[c], P.csv_columns);
         packed |= (Packed)__popc(startm[c]) << (16 * c);
       }
       Packed total_packed;
@@ -1294,9 +1484,14 @@ hipError_t launch_scan(const ScanParams& P, hipStream_t s) {
 
 template <int K, bool kSingle, bool kReduce>
 static void launch_parse_mode(const ParseParams& P, int grid, hipStream_t s) {
-  if constexpr (!kSingle) {  // JSON documents: a delimiter set of many bytes
+  if constexpr (!kSingle) {  // JSON documents and CSV: delimiter sets of many bytes
     if (P.flags & kFlagJsonDoc) {
       hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModeDoc>), dim3(grid), dim3(kThreads), 0,
+                         s, P);
+      return;
+    }
+    if (P.flags & kFlagCsv) {
+      hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModeCsv>), dim3(grid), dim3(kThreads), 0,
                          s, P);
       return;
     }

@@ -196,7 +196,7 @@ FFP_HD uint64_t digits_before(const TileSmem<K>& sm, int end, int n) {
 constexpr uint32_t kFastOk = 0, kFastInvalid = 1, kFastSlow = 2;
 
 // Lexing modes of the parse kernel's instances (see k_parse).
-constexpr int kModePlain = 0, kModeGrammar = 1, kModeExt = 2, kModeDoc = 3;
+constexpr int kModePlain = 0, kModeGrammar = 1, kModeExt = 2, kModeDoc = 3, kModeCsv = 4;
 
 struct FastLex {
   uint64_t w;

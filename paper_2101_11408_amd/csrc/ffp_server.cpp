@@ -365,7 +365,7 @@ uint64_t ffp_clock_ns(void) { return now_ns(); }
 int ffp_server_create(ffp_ctx* ctx, const ffp_server_options* opts, ffp_server** out) {
   if (!ctx || !out) return FFP_E_ARG;
   *out = nullptr;
-  if (ctx->flags & FFP_JSON_DOCUMENT) return FFP_E_ARG;  // batches need plain tokens
+  if (ctx->flags & (FFP_JSON_DOCUMENT | FFP_CSV)) return FFP_E_ARG;  // batches need plain tokens
   ffp_server_options o{};
   if (opts) o = *opts;
   if (o.mode != FFP_SERVE_BATCHED && o.mode != FFP_SERVE_PLAIN) return FFP_E_ARG;

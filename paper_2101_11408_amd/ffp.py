@@ -37,6 +37,7 @@ FFP_JSON = 2
 FFP_INFNAN = 4
 FFP_HEX = 8
 FFP_JSON_DOCUMENT = 0x40
+FFP_CSV = 0x80
 FFP_ROUND_MASK = 0x30
 FFP_ROUND_NEAREST = 0x00
 FFP_ROUND_TOWARD_ZERO = 0x10
@@ -132,6 +133,7 @@ _SIGNATURES = {
     "ffp_counters_enable": (_INT, [_P, _INT]),
     "ffp_set_reduce": (_INT, [_P, _P]),
     "ffp_set_reduce_sum": (_INT, [_P, _P]),
+    "ffp_set_csv_columns": (_INT, [_P, _U64]),
     "ffp_counters_read": (_INT, [_P, _U64 * 6]),
     "ffp_parse_batch": (_INT, [_P, _P, _c.c_uint32, _U64, _P]),
     "ffp_batch_graph_create": (_INT, [_P, _P, _c.c_uint32, _U64, _c.POINTER(_P)]),
@@ -289,7 +291,8 @@ class Context:
             self.handle = None
 
     def __del__(self):
-        _finalize(self)
+        if _finalize is not None:  # None once the module is torn down
+            _finalize(self)
 
     def reserve(self, nbytes: int):
         check(load().ffp_reserve(self.handle, nbytes), "ffp_reserve")
@@ -310,6 +313,10 @@ class Context:
         """out: device int64 tensor of 3 elements (min bits, max bits, count)
         written by every later plain call; None turns the reduction off."""
         check(load().ffp_set_reduce(self.handle, out.data_ptr() if out is not None else None))
+
+    def set_csv_columns(self, columns: int):
+        """FFP_CSV contexts: bit c of `columns` selects column c."""
+        check(load().ffp_set_csv_columns(self.handle, columns & 0xFFFFFFFFFFFFFFFF))
 
     def set_reduce_sum(self, out=None):
         """out: device int64 tensor of 2 elements (binary64 bits of the exact
@@ -459,7 +466,8 @@ class BatchGraph:
             self.handle = None
 
     def __del__(self):
-        _finalize(self)
+        if _finalize is not None:  # None once the module is torn down
+            _finalize(self)
 
 
 # ---------------------------------------------------------------------------
@@ -578,4 +586,5 @@ class Server:
             self.handle = None
 
     def __del__(self):
-        _finalize(self)
+        if _finalize is not None:  # None once the module is torn down
+            _finalize(self)

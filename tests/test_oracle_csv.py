@@ -7,35 +7,8 @@ import io
 import numpy as np
 import pytest
 
+from gen.workloads import csv_table as random_table
 from oracle import csv_number_spans, parse_csv, parse_token, split_tokens
-
-
-def random_table(rng, rows, extra_space=False, crlf=False, trailing_newline=True):
-    lines = []
-    for _ in range(rows):
-        ncol = int(rng.integers(1, 80))
-        fields = []
-        for _ in range(ncol):
-            k = rng.integers(0, 6)
-            if k == 0:
-                f = ""
-            elif k == 1:
-                f = "abc%d" % rng.integers(0, 100)
-            elif k == 2:
-                f = "%.17g" % (rng.standard_normal() * 10.0 ** rng.integers(-30, 30))
-            elif k == 3:
-                f = str(int(rng.integers(-10 ** 6, 10 ** 6)))
-            elif k == 4:
-                f = "-%d.%de%d" % (rng.integers(0, 99), rng.integers(0, 99), rng.integers(-20, 20))
-            else:
-                f = "1e999"
-            if extra_space and f and rng.integers(0, 2):
-                f = " " * int(rng.integers(1, 3)) + f + " " * int(rng.integers(0, 2))
-            fields.append(f)
-        lines.append(",".join(fields))
-    sep = "\r\n" if crlf else "\n"
-    text = sep.join(lines) + (sep if trailing_newline else "")
-    return text
 
 
 def csv_module_tokens(text, columns, split_spaces):
@@ -52,7 +25,8 @@ def test_spans_match_csv_module(seed):
     rng = np.random.default_rng(400 + seed)
     extra_space = seed % 2 == 1
     crlf = seed % 4 == 3
-    text = random_table(rng, 60, extra_space, crlf, trailing_newline=seed % 3 != 0)
+    text = random_table(rng, 60, extra_space=extra_space, crlf=crlf,
+                        trailing_newline=seed % 3 != 0, long_field_every=seed % 5)
     buf = text.encode()
     delims = b",\n" + (b" " if extra_space else b"") + (b"\r" if crlf else b"")
     for columns in [1, 0b101, 1 << 63, (1 << 64) - 1, int(rng.integers(0, 1 << 62)), 0]:
