@@ -66,6 +66,8 @@ METRIC = "GB/s input text + Mfloats/s parsed (bit-exact), batched/served vs plai
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2101_11408_amd/csrc/ffp_kernels.hip",
                   "paper_2101_11408_amd/csrc/ffp_device.h",
+                  "paper_2101_11408_amd/csrc/ffp_lexer.h",
+                  "paper_2101_11408_amd/csrc/ffp_fallback.h",
                   "paper_2101_11408_amd/csrc/ffp_internal.h"]
 # worker processes for host-side work: the CPU share of one GPU on the
 # measurement boxes
@@ -913,7 +915,8 @@ def summarize_trace(workload, trace_dir, command, bench_json=None):
                       rf.get("kernel_avg_ms", float("nan")) * 1e3, rec["value"], rec["unit"],
                       rec["ms_per_step"])]
         if rec.get("config", {}).get("schedule"):
-            lines.append("Schedule chosen by the autotuner: %s." % rec["config"]["schedule"])
+            lines.append("Schedule (the autotuner's choice, or --schedule): %s."
+                         % rec["config"]["schedule"])
     name = "k_parse_%s.md" % workload
     with open(os.path.join(ROOT, "profiles", name), "w") as f:
         f.write("\n".join(lines) + "\n")
