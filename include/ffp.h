@@ -32,7 +32,11 @@ extern "C" {
 #endif
 
 /* ---------------------------------------------------------------------------
- * Per-token status, one byte per token in the caller's status array.
+ * Per-token status, one byte per token in the caller's status array.  The
+ * paper leaves error reporting to the application (Section 4: a parser may
+ * fail on a malformed number); this is the library's contract.  Overflow and
+ * underflow follow Algorithm 1's early exits (Section 5: q > 308 is
+ * infinite, q < -342 is zero) and its subnormal branch (Section 9.3).
  * ------------------------------------------------------------------------- */
 enum ffp_token_status {
     /* The correctly rounded value.  A zero significand gives a signed zero,
@@ -176,6 +180,17 @@ int ffp_reserve(ffp_ctx* ctx, uint64_t max_nbytes);
 
 /* ---------------------------------------------------------------------------
  * Plain parse: one buffer, one stream-ordered launch sequence.
+ *
+ * Each token (a maximal run of non-delimiter bytes) is read with the grammar
+ * of Section 4 (sign, digits with an optional point, optional exponent) and
+ * converted as Sections 5-10 describe: the first 19 significant digits w
+ * and the decimal exponent q, Algorithm 1 with the 128-bit table entry for
+ * q (Section 5, Appendix B), the second product when the first one cannot
+ * decide (Sections 7-9), the tie and subnormal rules (Sections 6 and 9)
+ * and the binary exponent of Section 10; longer significands are decided
+ * from w and w+1 or, when those disagree, by an exact comparison with the
+ * halfway points (Section 11).  The result is the nearest binary64
+ * (binary32) value, ties to even (Section 2).
  *
  *   d_text    device pointer to nbytes bytes of text (read only; bytes
  *             outside [d_text, d_text+nbytes) are never read).  nbytes may

@@ -606,7 +606,7 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
     }
   }
   ctx->blocks_per_cu = ctx->max_bpc[ctx->tile_k];
-  ctx->fb_grid = ctx->num_cus * 4;
+  ctx->fb_grid = ctx->num_cus * 6;  // six workgroups of four waves per CU: six waves per SIMD
   // the main state and the two spares, all clean
   if (hipMalloc(&ctx->d_state, 3 * sizeof(DeviceState)) != hipSuccess) {
     delete ctx;

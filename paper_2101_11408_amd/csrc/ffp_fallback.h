@@ -272,9 +272,11 @@ struct FbToken {
 __device__ FbToken fb_lex(const uint8_t* text, uint64_t nbytes, uint64_t pos, FbLds* lds) {
   const int l = fb_lane();
   FbToken t;
-  const uint32_t c0 = pos < nbytes ? text[pos] : 0u;
-  t.neg = c0 == '-';
-  if (c0 == '-' || c0 == '+') ++pos;
+  // a leading sign stays in the first window: it is neither a digit nor a
+  // '.', an exponent marker or an end byte, so the scans below pass over it
+  // (no dependent load of the first byte before the window's loads)
+  t.neg = false;
+  bool first = true;
   FbDigits mant, expo;
   int64_t nint = -1;  // digits before the point, -1 without a point
   int state = 0;      // 0 mantissa, 1 exponent sign or first digit, 2 exponent digits
@@ -304,6 +306,10 @@ __device__ FbToken fb_lex(const uint8_t* text, uint64_t nbytes, uint64_t pos, Fb
         }
         wd[q] = w;
       }
+    }
+    if (first) {
+      t.neg = fb_byte_at(wd, 0) == '-';
+      first = false;
     }
     uint32_t dm = 0, dot = 0, em = 0, endm = 0;
 #pragma unroll
