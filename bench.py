@@ -414,6 +414,24 @@ def timed_steps(torch, fn, steps, warmup, spinup_ms=0.0):
     return (time.perf_counter() - t0) * 1e3 / steps if steps else 0.0
 
 
+def repeat_stats(torch, fn, reps):
+    """Min and median of `reps` calls, each bracketed by HIP events on the
+    current stream (the paper reports the minimum and the median over
+    repetitions, Section 12); run after the timed steps, apart from them."""
+    if reps <= 0:
+        return None
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in evs)
+    return {"reps": reps, "min_ms": round(ts[0], 4), "median_ms": round(ts[len(ts) // 2], 4),
+            "how": "HIP events around each call on the launch stream, after the timed steps"}
+
+
 # ---------------------------------------------------------------------------
 # single-buffer workloads
 # ---------------------------------------------------------------------------
@@ -452,6 +470,8 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims
     kern_ms, launches = ctx.timing_read()
     ctx.timing(False)
     assert launches == args.steps
+    rep = None if args.profile else repeat_stats(
+        torch, lambda: ctx.parse_into(text, values, status, count, stream=stream), args.reps)
     assert ctx.last_device_error() == 0
     assert int(count.item()) == ntok
     kavg = kern_ms / launches
@@ -461,6 +481,7 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims
         "description": desc, "tokens": ntok, "bytes": len(buf),
         "output": OUT_NAMES[out_dtype], "parallelism": "single GPU"})
     rec["mfloats_per_s"] = round(ntok / (ms / 1e3) / 1e6, 1)
+    rec["repeat"] = rep
     rec["roofline"] = roofline(alg, kavg, workload, None if args.profile else copy_peak(torch))
     if red is not None:
         mn, mx, cnt = [int(x) & 0xFFFFFFFFFFFFFFFF for x in red.cpu().tolist()]
@@ -571,6 +592,7 @@ def run_buffers(args, kind, workload):
              (stat["plain"] != stat["batch"])).sum().item())
 
     # captured graph replay, into outputs cleared first
+    rep = None
     if args.profile:
         ms_plain = ms_graph = ms_batch
     else:
@@ -580,6 +602,7 @@ def run_buffers(args, kind, workload):
         graph = ffp.BatchGraph(ctx, table, total)
         ms_graph = timed_steps(torch, lambda: graph.launch(stream), args.steps, args.warmup,
                                args.spinup_ms)
+        rep = repeat_stats(torch, lambda: graph.launch(stream), args.reps)
         res2 = table.download()
         assert [c for c, e in res2] == [c for c, e in res] and all(e == 0 for c, e in res2)
         graph.close()
@@ -606,6 +629,7 @@ def run_buffers(args, kind, workload):
         "batched_call": {"ms": round(ms_batch, 3), "GB/s": round(gbs(ms_batch), 1)},
         "batched_graph": {"ms": round(ms_graph, 3), "GB/s": round(gbs(ms_graph), 1)},
     }
+    rec["repeat"] = rep  # graph replays one by one
     rec["roofline"] = roofline(alg, kavg, workload, None if args.profile else copy_peak(torch))
     rec["cpu_baseline"] = None
     if not args.profile:
@@ -963,6 +987,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=100,
+                    help="after the timed steps: calls timed one by one (min and median)")
     ap.add_argument("--spinup-ms", type=float, default=200.0,
                     help="untimed calls for this long before the warmup steps (GPU clock ramp)")
     ap.add_argument("--workload", default="config4u",
