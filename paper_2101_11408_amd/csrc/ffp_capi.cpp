@@ -579,6 +579,20 @@ int ffp_create(int hip_device, const ffp_options* opts, ffp_ctx** out) {
   // sets (and a lone byte at or above 0x80) use the 256-entry table
   ctx->delim.single = members == 1 && first < 0x80 ? 1u : 0u;
   ctx->delim.byte = (uint32_t)first;
+  // sets of 2 to 4 bytes below 0x80: byte comparisons instead of a table
+  ctx->delim.nfew = 0;
+  if (members >= 2 && members <= 4) {
+    uint32_t k = 0;
+    bool low = true;
+    for (int c = 0; c < 256; ++c) {
+      if ((o.delim_set[c >> 6] >> (c & 63)) & 1) {
+        low = low && c < 0x80;
+        ctx->delim.few[k++] = (uint32_t)c * 0x01010101u;
+      }
+    }
+    for (; k < 4; ++k) ctx->delim.few[k] = ctx->delim.few[0];
+    if (low) ctx->delim.nfew = (uint32_t)members;
+  }
   ctx->flags = o.flags;
   ctx->csv_columns = ~0ull;
 

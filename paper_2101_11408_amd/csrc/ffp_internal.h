@@ -117,6 +117,11 @@ struct DelimSet {
   uint64_t bits[4];
   uint32_t single;     // 1 if the set holds exactly one byte, below 0x80
   uint32_t byte;       // that byte (or any member, used as padding)
+  // Sets of 2 to 4 bytes, all below 0x80: their members repeated in the four
+  // bytes of a word (unused slots repeat the first), classified by byte
+  // comparisons instead of table lookups; nfew = 0 for other sets.
+  uint32_t nfew;
+  uint32_t few[4];
 };
 
 // Jobs: either one job passed by value (plain calls) or a device table

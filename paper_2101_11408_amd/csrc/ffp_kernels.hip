@@ -222,11 +222,26 @@ __device__ __forceinline__ uint4 load_chunk(const uint8_t* vbase, uint64_t off, 
   return make_uint4(wds[0], wds[1], wds[2], wds[3]);
 }
 
+// High bit of each byte of x set when the byte is not in a set of 2 to 4
+// bytes (DelimSet::few): one byte comparison per member.
+__device__ __forceinline__ uint32_t nondelim_word_few(uint32_t x, const DelimSet& d) {
+  uint32_t eq = byte_eq_word(x, d.few[0]) | byte_eq_word(x, d.few[1]);
+  if (d.nfew > 2) eq |= byte_eq_word(x, d.few[2]) | byte_eq_word(x, d.few[3]);
+  return ~eq & 0x80808080u;
+}
+
+// Non-delimiter bits of 16 bytes: a lone delimiter below 0x80 by the
+// three-operation byte test, sets of 2 to 4 such bytes by one comparison per
+// member, larger sets from the LDS table.
 template <bool kSingle>
-__device__ __forceinline__ uint32_t nondelim_mask16(uint4 v, uint32_t drep, const uint8_t* lut) {
+__device__ __forceinline__ uint32_t nondelim_mask16(uint4 v, uint32_t drep, const uint8_t* lut,
+                                                    const DelimSet& d) {
   if (kSingle)
     return pack_high_bits(nondelim_word(v.x, drep), nondelim_word(v.y, drep),
                           nondelim_word(v.z, drep), nondelim_word(v.w, drep));
+  if (d.nfew)
+    return pack_high_bits(nondelim_word_few(v.x, d), nondelim_word_few(v.y, d),
+                          nondelim_word_few(v.z, d), nondelim_word_few(v.w, d));
   return pack_high_bits(nondelim_word_lut(v.x, lut), nondelim_word_lut(v.y, lut),
                         nondelim_word_lut(v.z, lut), nondelim_word_lut(v.w, lut));
 }
@@ -368,7 +383,7 @@ __device__ void count_json_doc(const CountParams& P, const uint8_t* lut, uint32_
         const uint32_t dgm = pack_high_bits(digit_word(v.x), digit_word(v.y), digit_word(v.z),
                                             digit_word(v.w));
         const DocBits d = doc_chunk(v, dgm, job.text, (int64_t)off - (int64_t)align);
-        base = nondelim_mask16<false>(v, 0u, lut) | d.eq;
+        base = nondelim_mask16<false>(v, 0u, lut, P.delim) | d.eq;
         uq = d.uq;
         ms[r] = d.ms;
       }
@@ -544,7 +559,7 @@ __device__ void count_csv(const CountParams& P, const uint8_t* lut, uint32_t* s_
       const int chunk = r * kThreads + tid;
       const uint64_t off = bstart + (uint64_t)chunk * kChunk;
       const uint4 v = load_chunk(vbase, off, align, vend, P.delim.byte);
-      const uint32_t m = off < vend ? nondelim_mask16<false>(v, 0u, lut) : 0u;
+      const uint32_t m = off < vend ? nondelim_mask16<false>(v, 0u, lut, P.delim) : 0u;
       const CsvBits cb = csv_chunk(v, text_bits(off, align, vend));
       s_nd[chunk] = (uint16_t)m;
       uint32_t row;
@@ -606,7 +621,8 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
     for (int r = 0; r < kCountRows; ++r) {
       const uint64_t off = bstart + (uint64_t)(r * kThreads + tid) * kChunk;
       m[r] = off < vend ? nondelim_mask16<kSingle>(
-                              load_chunk(vbase, off, align, vend, P.delim.byte), drep, s_lut)
+                              load_chunk(vbase, off, align, vend, P.delim.byte), drep, s_lut,
+                              P.delim)
                         : 0u;
       s_nd[r * kThreads + tid] = (uint16_t)m[r];
     }
@@ -802,7 +818,7 @@ __device__ uint64_t count_starts_before(const uint8_t* vbase, uint64_t align, ui
     // the byte before the chunk: past the text's first byte for c > 0
     // (off - 1 >= 15 >= align) and before vbytes <= vend
     const uint32_t prev = c ? (lut[gload(vbase + off - 1)] ? 0u : 1u) : 0u;
-    const uint32_t m = nondelim_mask16<kSingle>(v, drep, lut);
+    const uint32_t m = nondelim_mask16<kSingle>(v, drep, lut, delim);
     n += __popc(m & ~((m << 1) | prev) & 0xFFFFu);
   }
   return n;
@@ -992,7 +1008,7 @@ k_parse(ParseParams P) {
         const int chunk = c * kThreads + tid;
         const uint4 v = pre[c];
         *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + chunk * kChunk]) = v;
-        ndm[c] = nondelim_mask16<kSingle>(v, drep, sm.delim_lut);
+        ndm[c] = nondelim_mask16<kSingle>(v, drep, sm.delim_lut, P.delim);
         sm.nd[chunk] = (uint16_t)ndm[c];
         dgm[c] = pack_high_bits(digit_word(v.x), digit_word(v.y), digit_word(v.z), digit_word(v.w));
         sm.dg[chunk] = (uint16_t)dgm[c];
@@ -1114,7 +1130,7 @@ k_parse(ParseParams P) {
         if (tid < S::kExtChunks) {  // wave 0: chunk tid of the next tile
           const uint4 v = ext_v;
           *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + S::kBytes + tid * kChunk]) = v;
-          const uint32_t m = nondelim_mask16<kSingle>(v, drep, sm.delim_lut);
+          const uint32_t m = nondelim_mask16<kSingle>(v, drep, sm.delim_lut, P.delim);
           sm.nd[S::kChunks + tid] = (uint16_t)m;
           sm.dg[S::kChunks + tid] = (uint16_t)pack_high_bits(digit_word(v.x), digit_word(v.y),
                                                              digit_word(v.z), digit_word(v.w));

@@ -446,6 +446,40 @@ def test_delimiter_set_and_flags(ffpmod):
         c.close()
 
 
+@pytest.mark.parametrize("delims", [b",\n", b"\x00\x7f", b" \t\n", b",;\r\n", b"\n\x80",
+                                    b",; \t\r\n"])
+def test_small_delimiter_sets(ffpmod, delims):
+    """Sets of 2 to 4 bytes below 0x80 are classified by byte comparisons,
+    other sets (a member at or above 0x80, more members) by the table:
+    parity either way, with the neighbours of each member (0x7f next to
+    0x80, NUL) inside tokens, every tile size and a ragged start."""
+    rng = np.random.default_rng(150 + len(delims) + delims[0])
+    toks = [t.encode() for t in W.mixed_tokens(rng, 12_000)]
+    near = bytes(sorted({(d + k) & 0xFF for d in delims for k in (-1, 1)} - set(delims)))
+    parts = []
+    for i, t in enumerate(toks):
+        if i % 53 == 0 and near:  # a token holding a byte next to a delimiter: invalid
+            t = t[:2] + near[i % len(near):i % len(near) + 1] + t[2:]
+        parts.append(t)
+        parts.append(delims[i % len(delims):i % len(delims) + 1] *
+                     int(rng.integers(1, 3)))
+    buf = b"".join(parts)
+    wb, ws = parse_buffer(buf, "f64", delims=delims)
+    c = ffpmod.Context(0, delims=delims)
+    try:
+        for tk, kib in ((0, 0), (1, 4), (4, 16)):
+            if tk:
+                c.set_tuning(tk, 0, kib)
+            _log("case small delimiter set", delims, tk)
+            rc, n, bits, status = run_gpu(c, buf, "f64", offset=7)
+            assert rc == n == len(wb)
+            bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=np.uint64)) |
+                                 (status[:n] != np.array(ws, dtype=np.uint8)))
+            assert bad.size == 0, (delims, tk, bad[:5])
+    finally:
+        c.close()
+
+
 def test_grammar_bytes_rejected_as_delimiters(ffpmod):
     """A delimiter may not be a byte that a token of the selected grammar can
     contain: hexadecimal letters, x and p under FFP_HEX, the letters of inf,
