@@ -32,6 +32,7 @@
 
 #include "ffp_device.h"
 #include "ffp_internal.h"
+#include "ffp_lexer.h"
 
 namespace ffp {
 
@@ -230,10 +231,10 @@ __device__ __forceinline__ void fb_feed(FbDigits& s, uint32_t dm, const uint32_t
   const uint32_t pre = fb_excl_scan(cnt);
   const uint32_t total = fb_read32(pre + cnt, kWave - 1);
   if (s.z < 0) {
-    uint32_t nz = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) nz |= (fb_byte(wd, k) != '0' ? 1u : 0u) << k;
-    nz &= dm;
+    constexpr uint32_t kZero = '0' * 0x01010101u;
+    const uint32_t zm = pack_high_bits(byte_eq_word(wd[0], kZero), byte_eq_word(wd[1], kZero),
+                                       byte_eq_word(wd[2], kZero), byte_eq_word(wd[3], kZero));
+    const uint32_t nz = dm & ~zm;
     const uint64_t B = fb_ballot(nz != 0);
     if (B) {
       const int L = __builtin_ctzll(B);
@@ -311,17 +312,23 @@ __device__ FbToken fb_lex(const uint8_t* text, uint64_t nbytes, uint64_t pos, Fb
       t.neg = fb_byte_at(wd, 0) == '-';
       first = false;
     }
-    uint32_t dm = 0, dot = 0, em = 0, endm = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const uint32_t c = fb_byte(wd, k);
-      const bool isd = (c - '0') < 10u;
-      const bool ise = (c | 0x20u) == 'e';
-      dm |= (isd ? 1u : 0u) << k;
-      dot |= (c == '.' ? 1u : 0u) << k;
-      em |= (ise ? 1u : 0u) << k;
-      endm |= (!isd && !ise && c != '.' && c != '+' && c != '-' ? 1u : 0u) << k;
-    }
+    // byte classes of the lane's 16 bytes, four at a time (the parse
+    // kernel's exact per-byte tests): digits, '.', 'e' or 'E', and the end
+    // bytes (anything but those and the signs)
+    constexpr uint32_t kDot = '.' * 0x01010101u, kE = 'e' * 0x01010101u;
+    constexpr uint32_t kPlus = '+' * 0x01010101u, kMinus = '-' * 0x01010101u;
+    const uint32_t dm = pack_high_bits(digit_word(wd[0]), digit_word(wd[1]), digit_word(wd[2]),
+                                       digit_word(wd[3]));
+    const uint32_t dot = pack_high_bits(byte_eq_word(wd[0], kDot), byte_eq_word(wd[1], kDot),
+                                        byte_eq_word(wd[2], kDot), byte_eq_word(wd[3], kDot));
+    const uint32_t em = pack_high_bits(
+        byte_eq_word(wd[0] | 0x20202020u, kE), byte_eq_word(wd[1] | 0x20202020u, kE),
+        byte_eq_word(wd[2] | 0x20202020u, kE), byte_eq_word(wd[3] | 0x20202020u, kE));
+    const uint32_t sgn = pack_high_bits(byte_eq_word(wd[0], kPlus) | byte_eq_word(wd[0], kMinus),
+                                        byte_eq_word(wd[1], kPlus) | byte_eq_word(wd[1], kMinus),
+                                        byte_eq_word(wd[2], kPlus) | byte_eq_word(wd[2], kMinus),
+                                        byte_eq_word(wd[3], kPlus) | byte_eq_word(wd[3], kMinus));
+    const uint32_t endm = ~(dm | dot | em | sgn) & 0xFFFFu;
     const int endp = fb_first(endm);
     int es = 0;  // start of the exponent part in this window
     if (state == 0) {
