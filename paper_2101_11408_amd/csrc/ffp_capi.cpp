@@ -208,6 +208,9 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
   sp.st = st;
   sp.spare = spare;
   sp.json_doc = json_doc ? 1u : 0u;
+  // the 16 KiB plain parse keeps at most 4096 starts per tile; a block with
+  // no more than that cannot have a tile with more
+  sp.dense_limit = json_doc ? 0u : 4096u;
   if (nblocks > 0 && !self_count) {
     ffp::CountParams cp{};
     cp.js = js;

@@ -108,6 +108,10 @@ struct DeviceState {
   // exact sum: accumulators of the positive ([0]) and negative ([1]) values
   unsigned long long sum_acc[2][kSumLimbs];
   unsigned int sum_flags;
+  // set by the scan kernel when a block of the call holds more token starts
+  // than ScanParams::dense_limit (then the 16 KiB plain parse runs with the
+  // full start list)
+  unsigned int dense;
 };
 
 static_assert(sizeof(DeviceState) <= kNoAllocBlockOff, "device state fits its scratch slot");
@@ -181,6 +185,7 @@ struct ScanParams {
   DeviceState* st;
   DeviceState* spare;   // the context's two spare states, reset here (or null)
   uint32_t json_doc;    // count words of JSON documents (see kPrefixMask)
+  uint32_t dense_limit; // DeviceState::dense: block counts above this (0: never)
 };
 
 struct ParseParams {

@@ -330,6 +330,7 @@ __device__ __forceinline__ uint32_t prev_nondelim(const uint8_t* vbase, uint64_t
 __device__ __forceinline__ void reset_call_state(DeviceState* st) {
   st->queue_tail = 0;
   st->error = 0;
+  st->dense = 0;
   st->red_min = ~0ull;
   st->red_max = 0;
   st->red_count = 0;
@@ -665,6 +666,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
     }
   }
   reset_sum_state(P.st, tid, kScanThreads);
+  bool dense = false;  // a block above P.dense_limit starts (plain counts only)
   for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * kScanPer) {
     uint64_t v[kScanPer];
     uint64_t sum = 0;
@@ -698,6 +700,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
         const uint64_t k = base + (uint64_t)tid * kScanPer + i;
         v[i] = k < n ? P.block_sum[k] : 0;
         sum += v[i];
+        dense = dense || (P.dense_limit && v[i] > P.dense_limit);
       }
     }
     __syncthreads();  // s_carry of the previous round is final
@@ -716,7 +719,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
     __syncthreads();
     if (tid == 0) s_carry = carry + total;
   }
-  __syncthreads();
+  // (the barrier also makes s_carry final)
+  if (__syncthreads_or(dense) && tid == 0) P.st->dense = 1;
   if (!P.js.jobs) {  // one job: its token count is the total
     if (tid == 0) {
       const uint64_t count = s_carry;
@@ -860,10 +864,10 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
   return (int)d.path;
 }
 
-// Registers: within 128 (four waves per SIMD; the LDS of a 16 KiB tile
-// allows four workgroups per CU), and within 96 for the plain instance
-// without a reduction at 8 KiB and smaller tiles (five waves per SIMD; at
-// 96 the other instances spill to scratch inside the token loop).
+// Registers: within 128 (four waves per SIMD), and within 96 for the plain
+// instance without a reduction (five waves per SIMD; at 96 the other
+// instances spill to scratch inside the token loop).  Five 16 KiB-tile
+// workgroups fit a CU's LDS with the shorter start list of that instance.
 // kReduce: the call also keeps the minimum, maximum and count of the
 // values.  kMode: kModePlain lexes Section 4's grammar (FFP_REJECT_PLUS
 // aside, no grammar flag); kModeGrammar adds the JSON grammar and inf / nan
@@ -872,10 +876,10 @@ __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, c
 // nothing for either: its register and branch budget is the tightest.
 template <int K, bool kSingle, bool kReduce, int kMode>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(K <= 2 && kMode == kModePlain && !kReduce ? 5 : 4))) void
+__attribute__((amdgpu_waves_per_eu(kMode == kModePlain && !kReduce ? 5 : 4))) void
 k_parse(ParseParams P) {
   constexpr bool kExt = kMode == kModeExt;
-  constexpr bool kGrammar = kMode != kModePlain;
+  constexpr bool kGrammar = kMode != kModePlain && kMode != kModePlainDense;
   using S = TileSmem<K>;
   using Packed = typename S::Packed;
   __shared__ S sm;
@@ -884,6 +888,19 @@ k_parse(ParseParams P) {
   // CSV: the column scans' wave totals
   constexpr bool csv = kMode == kModeCsv;
   __shared__ uint32_t s_seg[csv ? kThreads / kWave : 1];
+  // Token starts of a tile (offsets in the tile), in token order.  A tile
+  // can hold kBytes / 2 tokens; the plain 16 KiB instance without a
+  // reduction keeps a list half that long (its LDS then lets five workgroups
+  // share a CU).  It runs when no block of the call has more starts than
+  // that (the scan kernel's DeviceState::dense), its twin kModePlainDense
+  // with the full list otherwise: both are launched, and the one not
+  // needed returns at once.  The JSON document instance also keeps its
+  // token bitmaps here until the starts are written.
+  constexpr bool kShortStarts = K == 4 && kMode == kModePlain && !kReduce;
+  constexpr int kStartsCap = kShortStarts ? S::kBytes / 4 : S::kBytes / 2;
+  __shared__ uint16_t s_starts[kStartsCap];
+  if (kShortStarts && P.st->dense) return;
+  if (kMode == kModePlainDense && !P.st->dense) return;
   __shared__ uint32_t s_sum_flags;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -1029,7 +1046,7 @@ k_parse(ParseParams P) {
       }
       // JSON documents: token bytes are the non-delimiters outside strings;
       // the string state of each chunk comes from a block scan of its
-      // unescaped quotes (sm.starts holds the token bitmaps until the
+      // unescaped quotes (s_starts holds the token bitmaps until the
       // token starts are written)
       uint32_t tbm[K], msm[K], tile_last_tb = 0, tile_end_str = 0;
       if (doc) {
@@ -1054,7 +1071,7 @@ k_parse(ParseParams P) {
           const int chunk = c * kThreads + tid;
           const uint32_t cin = (carry_in + rowq + ((uint32_t)(exq >> (16 * c)) & 0xFFFFu)) & 1u;
           tbm[c] &= ~doc_in_string(uq[c], cin);
-          sm.starts[chunk] = (uint16_t)tbm[c];
+          s_starts[chunk] = (uint16_t)tbm[c];
           rowq += (uint32_t)(totq >> (16 * c)) & 0xFFFFu;
         }
         tile_last_tb = (tbm[K - 1] >> 15) & 1u;
@@ -1078,7 +1095,7 @@ k_parse(ParseParams P) {
         const int chunk = c * kThreads + tid;
         const uint32_t prevbit =
             chunk == 0 ? sm.prev_nd
-            : doc      ? ((uint32_t)sm.starts[chunk - 1] >> 15) & 1u
+            : doc      ? ((uint32_t)s_starts[chunk - 1] >> 15) & 1u
                        : ((uint32_t)sm.nd[chunk - 1] >> 15) & 1u;
         const uint32_t m = doc ? tbm[c] : ndm[c];
         startm[c] = m & ~((m << 1) | prevbit) & 0xFFFFu;
@@ -1102,6 +1119,12 @@ k_parse(ParseParams P) {
         *job.count_out = count;
         if (job.err_out && count > job.capacity) atomicCAS(job.err_out, 0, kErrCapacity);
       }
+      const bool straddle = (sm.nd[S::kChunks - 1] >> 15) & 1u;
+      const LdsSrc lsrc{sm.text + S::kPadFront, tile_start, sm.delim_lut};
+      // tokens of this tile that fit the caller's capacity
+      const uint32_t nfit = next_idx >= job.capacity ? 0u
+                            : (job.capacity - next_idx < ntok ? (uint32_t)(job.capacity - next_idx)
+                                                              : ntok);
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         uint32_t p = row_off[c] + ((uint32_t)(excl_packed >> (16 * c)) & 0xFFFFu);
@@ -1109,23 +1132,16 @@ k_parse(ParseParams P) {
         const uint32_t base = (uint32_t)((c * kThreads + tid) * kChunk);
         while (m) {
           const uint32_t k = __ffs(m) - 1;
-          sm.starts[p++] = (uint16_t)(base + k);
+          s_starts[p++] = (uint16_t)(base + k);
           m &= m - 1;
         }
       }
-      __syncthreads();
-
       // -- one lane per token -------------------------------------------
       // When the tile's last byte belongs to a token, that token (the last
       // one starting here) continues past the tile: the extension is filled
-      // before its round; if the token also runs past the extension it is
-      // read from global memory, which returns a delimiter past the text.
-      const bool straddle = (sm.nd[S::kChunks - 1] >> 15) & 1u;
-      const LdsSrc lsrc{sm.text + S::kPadFront, tile_start, sm.delim_lut};
-      // tokens of this tile that fit the caller's capacity
-      const uint32_t nfit = next_idx >= job.capacity ? 0u
-                            : (job.capacity - next_idx < ntok ? (uint32_t)(job.capacity - next_idx)
-                                                              : ntok);
+      // before the rounds (no other token reads it); if the token also runs
+      // past the extension it is read from global memory, which returns a
+      // delimiter past the text.
       if (straddle && nfit == ntok) {  // the last token is decided here: fill the extension
         if (tid < S::kExtChunks) {  // wave 0: chunk tid of the next tile
           const uint4 v = ext_v;
@@ -1137,8 +1153,8 @@ k_parse(ParseParams P) {
           const uint64_t has_delim = (uint64_t)__ballot(m != 0xFFFFu);
           if (tid == 0) sm.ext_end = has_delim != 0;
         }
-        __syncthreads();
       }
+      __syncthreads();
       // the token read from global memory, if any (index; ~0: none)
       const uint32_t global_j = straddle && nfit == ntok && !sm.ext_end ? ntok - 1 : ~0u;
       // whole rounds of 256 tokens: lanes without a token in the last round
@@ -1149,7 +1165,7 @@ k_parse(ParseParams P) {
         uint64_t vbits = 0;
         uint32_t vstatus = kStInvalid;
         if (has_token) {
-          const uint32_t s = sm.starts[j];
+          const uint32_t s = s_starts[j];
           const uint64_t vpos = tile_start + s;  // virtual
           const uint64_t pos = vpos - align;     // offset in the text
           const bool global = j == global_j;
@@ -1522,9 +1538,13 @@ static void launch_parse_mode(const ParseParams& P, int grid, hipStream_t s) {
   else if (P.flags & (kFlagJson | kFlagInfNan))
     hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModeGrammar>), dim3(grid), dim3(kThreads), 0, s,
                        P);
-  else
+  else {
     hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModePlain>), dim3(grid), dim3(kThreads), 0, s,
                        P);
+    if constexpr (K == 4 && !kReduce)  // the full-list twin for dense calls
+      hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModePlainDense>), dim3(grid),
+                         dim3(kThreads), 0, s, P);
+  }
 }
 
 template <int K, bool kSingle>

@@ -94,7 +94,6 @@ struct TileSmem {
   // instead of a 64-bit shift and selects per group
   unsigned long long keep8[16];
   alignas(16) uint8_t text[kPadFront + kBytes + kExtBytes + kPadBack];
-  uint16_t starts[kBytes / 2];
   // bit i of these bitmaps describes byte i of the tile (16 bits per chunk),
   // then the extension, then 128 zero bits so that 32-bit windows stay in
   // range
@@ -197,6 +196,9 @@ constexpr uint32_t kFastOk = 0, kFastInvalid = 1, kFastSlow = 2;
 
 // Lexing modes of the parse kernel's instances (see k_parse).
 constexpr int kModePlain = 0, kModeGrammar = 1, kModeExt = 2, kModeDoc = 3, kModeCsv = 4;
+// The plain grammar with the full start list of a 16 KiB tile: the twin of
+// the plain instance for calls with a block denser than its short list.
+constexpr int kModePlainDense = 5;
 
 struct FastLex {
   uint64_t w;

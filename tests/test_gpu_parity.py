@@ -248,6 +248,48 @@ def test_many_tiny_tokens(ctx):
     compare_full(ctx, buf, "f64", "dense")
 
 
+@pytest.mark.parametrize("block_kib", [16, 64])
+def test_dense_tiles_at_16k(ffpmod, block_kib):
+    """16 KiB tiles: the plain instance keeps at most 4096 starts per tile and
+    runs when no block of the call has more; otherwise its full-list twin
+    runs.  Dense text (one-digit tokens: 8192 per tile), sparse text, and a
+    text dense in one block only, in plain calls and in one batched call
+    mixing them; every output against the oracle."""
+    rng = np.random.default_rng(170 + block_kib)
+    dense = b"7\n" * 150_000 + b"8"
+    sparse = W.join_tokens(W.mixed_tokens(rng, 20_000))
+    mixed = sparse[:300_000] + b"\n" + b"1\n" * 40_000 + sparse[300_000:]
+    c = ffpmod.Context(0)
+    try:
+        c.set_tuning(4, 0, block_kib)
+        for label, buf in (("dense", dense), ("sparse", sparse), ("mixed", mixed)):
+            for fmt in ("f64", "f32"):
+                _log("case dense tiles", block_kib, label, fmt)
+                rc, n, bits, status = run_gpu(c, buf, fmt, offset=9)
+                wb, ws = parse_buffer(buf, fmt)
+                assert rc == n == len(wb), (label, rc, n, len(wb))
+                bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                     (status[:n] != np.array(ws, dtype=np.uint8)))
+                assert bad.size == 0, (label, fmt, bad[:5])
+        # one batched call: the flag covers the whole call
+        dev = torch.device("cuda", 0)
+        texts = [torch.frombuffer(bytearray(b), dtype=torch.uint8).to(dev)
+                 for b in (sparse, dense, mixed, sparse[:5000])]
+        want = [parse_buffer(b, "f64") for b in (sparse, dense, mixed, sparse[:5000])]
+        vals = [torch.empty(len(w[0]) + 1, dtype=torch.float64, device=dev) for w in want]
+        sts = [torch.empty(len(w[0]) + 1, dtype=torch.uint8, device=dev) for w in want]
+        table = ffpmod.JobTable(texts, vals, sts, dev)
+        c.parse_batch(table.dev, table.n, sum(t.numel() for t in texts))
+        res = table.download()
+        for i, (wb, ws) in enumerate(want):
+            assert res[i] == (len(wb), 0), (i, res[i])
+            got = vals[i].view(torch.int64).cpu().numpy().view(np.uint64)[:len(wb)]
+            assert np.array_equal(got, np.array(wb, dtype=np.uint64)), i
+            assert np.array_equal(sts[i].cpu().numpy()[:len(wb)], np.array(ws, dtype=np.uint8)), i
+    finally:
+        c.close()
+
+
 def test_long_tokens(ctx):
     rng = np.random.default_rng(12)
     long_digits = "".join(map(str, rng.integers(0, 10, 100_000).tolist()))
