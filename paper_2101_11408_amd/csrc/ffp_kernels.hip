@@ -232,18 +232,28 @@ __device__ __forceinline__ uint32_t nondelim_word_few(uint32_t x, const DelimSet
 
 // Non-delimiter bits of 16 bytes: a lone delimiter below 0x80 by the
 // three-operation byte test, sets of 2 to 4 such bytes by one comparison per
-// member, larger sets from the LDS table.
-template <bool kSingle>
+// member (kFew), larger sets from the LDS table.  Loops over many chunks
+// take the kFew decision outside the loop (one branch per loop, not per
+// chunk, keeps the registers of the unrolled loop down).
+template <bool kSingle, bool kFew = false>
 __device__ __forceinline__ uint32_t nondelim_mask16(uint4 v, uint32_t drep, const uint8_t* lut,
                                                     const DelimSet& d) {
   if (kSingle)
     return pack_high_bits(nondelim_word(v.x, drep), nondelim_word(v.y, drep),
                           nondelim_word(v.z, drep), nondelim_word(v.w, drep));
-  if (d.nfew)
+  if (kFew)
     return pack_high_bits(nondelim_word_few(v.x, d), nondelim_word_few(v.y, d),
                           nondelim_word_few(v.z, d), nondelim_word_few(v.w, d));
   return pack_high_bits(nondelim_word_lut(v.x, lut), nondelim_word_lut(v.y, lut),
                         nondelim_word_lut(v.z, lut), nondelim_word_lut(v.w, lut));
+}
+
+// The same with the kFew decision taken at run time (single chunks).
+template <bool kSingle>
+__device__ __forceinline__ uint32_t nondelim_mask16_any(uint4 v, uint32_t drep, const uint8_t* lut,
+                                                        const DelimSet& d) {
+  return !kSingle && d.nfew ? nondelim_mask16<kSingle, true>(v, drep, lut, d)
+                            : nondelim_mask16<kSingle, false>(v, drep, lut, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,7 +570,7 @@ __device__ void count_csv(const CountParams& P, const uint8_t* lut, uint32_t* s_
       const int chunk = r * kThreads + tid;
       const uint64_t off = bstart + (uint64_t)chunk * kChunk;
       const uint4 v = load_chunk(vbase, off, align, vend, P.delim.byte);
-      const uint32_t m = off < vend ? nondelim_mask16<false>(v, 0u, lut, P.delim) : 0u;
+      const uint32_t m = off < vend ? nondelim_mask16_any<false>(v, 0u, lut, P.delim) : 0u;
       const CsvBits cb = csv_chunk(v, text_bits(off, align, vend));
       s_nd[chunk] = (uint16_t)m;
       uint32_t row;
@@ -618,14 +628,26 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
     const uint64_t bstart = (b - job.block_begin) << kShift;
     __syncthreads();  // s_nd / s_prev of the previous block are consumed
     uint32_t m[kCountRows];
+    if (!kSingle && P.delim.nfew) {
 #pragma unroll
-    for (int r = 0; r < kCountRows; ++r) {
-      const uint64_t off = bstart + (uint64_t)(r * kThreads + tid) * kChunk;
-      m[r] = off < vend ? nondelim_mask16<kSingle>(
-                              load_chunk(vbase, off, align, vend, P.delim.byte), drep, s_lut,
-                              P.delim)
-                        : 0u;
-      s_nd[r * kThreads + tid] = (uint16_t)m[r];
+      for (int r = 0; r < kCountRows; ++r) {
+        const uint64_t off = bstart + (uint64_t)(r * kThreads + tid) * kChunk;
+        m[r] = off < vend ? nondelim_mask16<kSingle, true>(
+                                load_chunk(vbase, off, align, vend, P.delim.byte), drep, s_lut,
+                                P.delim)
+                          : 0u;
+        s_nd[r * kThreads + tid] = (uint16_t)m[r];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < kCountRows; ++r) {
+        const uint64_t off = bstart + (uint64_t)(r * kThreads + tid) * kChunk;
+        m[r] = off < vend ? nondelim_mask16<kSingle, false>(
+                                load_chunk(vbase, off, align, vend, P.delim.byte), drep, s_lut,
+                                P.delim)
+                          : 0u;
+        s_nd[r * kThreads + tid] = (uint16_t)m[r];
+      }
     }
     if (tid == 0) s_prev = prev_nondelim(vbase, bstart, align, P.delim);
     __syncthreads();
@@ -822,7 +844,7 @@ __device__ uint64_t count_starts_before(const uint8_t* vbase, uint64_t align, ui
     // the byte before the chunk: past the text's first byte for c > 0
     // (off - 1 >= 15 >= align) and before vbytes <= vend
     const uint32_t prev = c ? (lut[gload(vbase + off - 1)] ? 0u : 1u) : 0u;
-    const uint32_t m = nondelim_mask16<kSingle>(v, drep, lut, delim);
+    const uint32_t m = nondelim_mask16_any<kSingle>(v, drep, lut, delim);
     n += __popc(m & ~((m << 1) | prev) & 0xFFFFu);
   }
   return n;
@@ -1020,12 +1042,15 @@ k_parse(ParseParams P) {
       // -- store the tile to LDS and classify bytes ---------------------
       uint32_t ndm[K], dgm[K];
       CsvBits cb[csv ? K : 1];
+      // (JSON documents: ten delimiters, always the table)
+      const bool few = !kSingle && !doc && P.delim.nfew != 0;
 #pragma unroll
       for (int c = 0; c < K; ++c) {
         const int chunk = c * kThreads + tid;
         const uint4 v = pre[c];
         *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + chunk * kChunk]) = v;
-        ndm[c] = nondelim_mask16<kSingle>(v, drep, sm.delim_lut, P.delim);
+        ndm[c] = few ? nondelim_mask16<kSingle, true>(v, drep, sm.delim_lut, P.delim)
+                     : nondelim_mask16<kSingle, false>(v, drep, sm.delim_lut, P.delim);
         sm.nd[chunk] = (uint16_t)ndm[c];
         dgm[c] = pack_high_bits(digit_word(v.x), digit_word(v.y), digit_word(v.z), digit_word(v.w));
         sm.dg[chunk] = (uint16_t)dgm[c];
@@ -1146,7 +1171,7 @@ k_parse(ParseParams P) {
         if (tid < S::kExtChunks) {  // wave 0: chunk tid of the next tile
           const uint4 v = ext_v;
           *reinterpret_cast<uint4*>(&sm.text[S::kPadFront + S::kBytes + tid * kChunk]) = v;
-          const uint32_t m = nondelim_mask16<kSingle>(v, drep, sm.delim_lut, P.delim);
+          const uint32_t m = nondelim_mask16_any<kSingle>(v, drep, sm.delim_lut, P.delim);
           sm.nd[S::kChunks + tid] = (uint16_t)m;
           sm.dg[S::kChunks + tid] = (uint16_t)pack_high_bits(digit_word(v.x), digit_word(v.y),
                                                              digit_word(v.z), digit_word(v.w));
