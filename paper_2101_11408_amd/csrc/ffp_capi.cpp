@@ -171,9 +171,18 @@ constexpr uint64_t kSumInParseMaxBlocks = 1024;
 // counting costs more than the launch (26.5 against 24.9 us at 64 KiB).
 constexpr uint64_t kSelfCountMaxBlocks = 8;
 
+// Plain calls of at most this many 4 KiB blocks (128 KiB) run without the
+// fallback kernel: each parse workgroup decides the queued tokens of its own
+// block after parsing it (ParseParams::fb_local), one wave per token.  The
+// fallback kernel's launch and its dependency on the parse kernel are most
+// of its cost on such a call; a block that queues many tokens keeps four
+// waves on them instead of the fallback kernel's wider grid.
+constexpr uint64_t kLocalFbMaxBlocks = 32;
+
 // count -> scan -> parse -> fallback for a job set whose block count is
 // `nblocks` (plain calls) or on the device (batched calls: nblocks is then
-// the scratch's bound and max_blocks the call's); small calls skip the scan.
+// the scratch's bound and max_blocks the call's); small calls skip the scan,
+// the smallest the count kernel, small plain calls the fallback kernel.
 int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const CallShape& shape,
                 uint64_t nblocks, uint64_t max_blocks, hipStream_t s) {
   // (the parse kernel's 4 KiB-tile instances carry the summation)
@@ -190,6 +199,10 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
                           !reduce_out && !sum_out && !count_paths;
   const bool sum_in_parse = !self_count && nblocks > 0 && max_blocks <= kSumInParseMaxBlocks &&
                             shape.tile_k == 1 && !json_doc;
+  const bool fb_local = !js.jobs && nblocks > 0 && nblocks <= kLocalFbMaxBlocks &&
+                        shape.tile_k == 1 && js.block_shift == ffp::kMinBlockShift && !json_doc &&
+                        !csv && !reduce_out && !sum_out &&
+                        nblocks * ffp::kLocalQueueSeg <= sc.queue_cap;
   // A call without the count kernel runs on the spare state the previous
   // call left clean and cleans the other one; every other call cleans its
   // own state and both spares.
@@ -249,6 +262,7 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
   P.self_count = self_count ? 1u : 0u;
   P.other_st = other;
   P.csv_columns = ctx->csv_columns;
+  P.fb_local = fb_local ? 1u : 0u;
   P.reduce_out = reduce_out;
   P.sum_out = sum_out;
   uint64_t grid = (uint64_t)shape.grid;
@@ -276,6 +290,7 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
     if (hipEventRecord(ev.second, s) != hipSuccess) return FFP_E_HIP;
     ctx->ev_used.push_back(ev);
   }
+  if (fb_local) return FFP_SUCCESS;  // the parse kernel decided the queued tokens
 
   ffp::FallbackParams F{};
   F.js = js;

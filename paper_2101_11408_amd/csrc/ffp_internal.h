@@ -211,7 +211,17 @@ struct ParseParams {
   uint32_t self_count;
   DeviceState* other_st;
   uint64_t csv_columns;  // FFP_CSV: bit c selects column c (c < 64)
+  // Small calls (4 KiB blocks, no reduction) decide their queued tokens in
+  // the parse kernel: block b queues into entries [b * kLocalQueueSeg,
+  // (b + 1) * kLocalQueueSeg) of the queue, and the workgroup that parsed
+  // the block runs the exact fallback on them (no fallback kernel).
+  uint32_t fb_local;
 };
+
+// Queue entries per 4 KiB block when a block's workgroup decides its own
+// queued tokens: a token starts at a byte whose predecessor is a delimiter,
+// so a block holds at most half its bytes in token starts.
+constexpr uint64_t kLocalQueueSeg = (1u << kMinBlockShift) / 2;
 
 struct FallbackParams {
   JobSet js;

@@ -851,24 +851,90 @@ __device__ uint64_t count_starts_before(const uint8_t* vbase, uint64_t align, ui
 }
 
 // ---------------------------------------------------------------------------
+// The exact fallback on one queued token (fb_decide), by one wavefront: the
+// fallback kernel's work, and that of the parse workgroups of small calls.
+// ---------------------------------------------------------------------------
+constexpr int kFbThreads = 256;
+constexpr int kFbWaves = kFbThreads / kWave;
+
+template <class F>
+__device__ __forceinline__ void fallback_token(const JobDesc& job, uint64_t pos, uint64_t idx,
+                                               FbLds* lds, const FallbackParams& P) {
+  typename F::bits_t bits;
+  uint32_t status;
+  fb_decide<F>(job.text, job.nbytes, pos, g_table, g_pow5, lds, P.flags, bits, status);
+  if (fb_lane() == 0) {
+    gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, bits);
+    gstore(job.status + idx, (uint8_t)status);
+    uint64_t key;
+    const bool in = (P.reduce_out || P.sum_out) && order_key(bits, status, job.dtype, key);
+    if (in && P.reduce_out) {
+      atomicMin(&P.st->red_min, (unsigned long long)key);
+      atomicMax(&P.st->red_max, (unsigned long long)key);
+      atomicAdd(&P.st->red_count, 1ull);
+    }
+    if (in && P.sum_out) {
+      const SumTerm x = sum_term(bits, job.dtype);
+      if (!x.inf && x.m) sum_add(&P.st->sum_acc[x.neg ? 1 : 0][0], x);
+      atomicOr(&P.st->sum_flags, sum_flag_bits(x));
+    }
+  }
+}
+
+// The nq queued tokens of one block of a plain call without a reduction,
+// decided by the waves of the calling workgroup in turn (lds: one FbLds per
+// wave).  Not inlined: the parse kernel calls it once per block at most, and
+// as a call its registers do not add to those of the token loop.
+__device__ __noinline__ void decide_queue_segment(const QueueEntry* seg, uint32_t nq,
+                                                  const uint8_t* text, uint64_t nbytes,
+                                                  void* values, uint8_t* status, uint32_t dtype,
+                                                  uint32_t flags, FbLds* lds) {
+  JobDesc job{};
+  job.text = text;
+  job.nbytes = nbytes;
+  job.values = values;
+  job.status = status;
+  job.dtype = dtype;
+  FallbackParams F{};
+  F.flags = flags;
+  const uint32_t wid = threadIdx.x / kWave;
+  for (uint32_t i = wid; i < nq; i += kThreads / kWave) {
+    const QueueEntry e = seg[i];
+    const uint64_t idx = e.index_job & ((1ull << 48) - 1);
+    fb_wave_sync();  // the previous token's LDS reads are done
+    switch (dtype) {
+      case kF64: fallback_token<F64>(job, e.offset, idx, lds + wid, F); break;
+      case kF32: fallback_token<F32>(job, e.offset, idx, lds + wid, F); break;
+      case kF16: fallback_token<F16>(job, e.offset, idx, lds + wid, F); break;
+      default: fallback_token<BF16>(job, e.offset, idx, lds + wid, F); break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_parse (the tile layout and the lexers are in ffp_lexer.h)
 // ---------------------------------------------------------------------------
 
 // Algorithm 1 (and w+1 for long significands) on a lexed token, the queue
 // append for undecided tokens, and the stores.  Returns the path counter.
-template <class F, bool kExt>
+// kLocalFb (with ParseParams::fb_local set): the token goes to the block's
+// own queue segment, at seg_base plus the workgroup's LDS counter *local_n.
+template <class F, bool kExt, bool kLocalFb>
 __device__ __forceinline__ int finish_token(const Lexed& L, uint64_t text_pos, const JobDesc& job,
                                             uint64_t first_idx, uint32_t j,
                                             const unsigned long long* table,
                                             const TableEntry* ent,
-                                            const ParseParams& P, uint64_t& bits_out,
+                                            const ParseParams& P, uint32_t* local_n,
+                                            uint64_t seg_base, uint64_t& bits_out,
                                             uint32_t& status_out) {
   Decision<F> d = decide_lexed<F, kExt>(L, table, P.flags, ent);
   bits_out = d.bits;
   status_out = d.fallback ? kPending : d.status;
   uint8_t st = (uint8_t)d.status;
   if (d.fallback) {
-    const unsigned long long slot = atomicAdd(&P.st->queue_tail, 1ull);
+    const unsigned long long slot = kLocalFb && P.fb_local
+                                        ? seg_base + atomicAdd(local_n, 1u)
+                                        : atomicAdd(&P.st->queue_tail, 1ull);
     if (slot < P.queue_cap) {
       QueueEntry e;
       e.offset = text_pos;
@@ -924,6 +990,14 @@ k_parse(ParseParams P) {
   if (kShortStarts && P.st->dense) return;
   if (kMode == kModePlainDense && !P.st->dense) return;
   __shared__ uint32_t s_sum_flags;
+  // Small calls: the block's queued tokens, decided by this workgroup after
+  // the block's tile (ParseParams::fb_local).  The fallback's per-wave LDS
+  // then lives in the tile's text array, unused until the next tile.
+  constexpr bool kLocalFb = K == 1 && !kReduce &&
+                            (kMode == kModePlain || kMode == kModeGrammar || kMode == kModeExt);
+  __shared__ uint32_t s_fb_n;
+  static_assert(!kLocalFb || sizeof(FbLds) * (kThreads / kWave) <= sizeof(sm.text),
+                "the fallback's LDS fits the tile text");
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
 
@@ -948,6 +1022,7 @@ k_parse(ParseParams P) {
     sm.red_max = kNoMax;
     sm.red_count = 0;
     s_sum_flags = 0;
+    s_fb_n = 0;
   }
   if (kReduce)
     for (int i = tid; i < 2 * kSumLimbs; i += kThreads) s_sum[i] = 0;
@@ -1219,10 +1294,10 @@ k_parse(ParseParams P) {
           }
           int path;
           switch (job.dtype) {
-            case kF64: path = finish_token<F64, kExt>(L, pos, job, next_idx, j, table, &ent, P, vbits, vstatus); break;
-            case kF32: path = finish_token<F32, kExt>(L, pos, job, next_idx, j, table, &ent, P, vbits, vstatus); break;
-            case kF16: path = finish_token<F16, kExt>(L, pos, job, next_idx, j, table, &ent, P, vbits, vstatus); break;
-            default: path = finish_token<BF16, kExt>(L, pos, job, next_idx, j, table, &ent, P, vbits, vstatus); break;
+            case kF64: path = finish_token<F64, kExt, kLocalFb>(L, pos, job, next_idx, j, table, &ent, P, &s_fb_n, blk * kLocalQueueSeg, vbits, vstatus); break;
+            case kF32: path = finish_token<F32, kExt, kLocalFb>(L, pos, job, next_idx, j, table, &ent, P, &s_fb_n, blk * kLocalQueueSeg, vbits, vstatus); break;
+            case kF16: path = finish_token<F16, kExt, kLocalFb>(L, pos, job, next_idx, j, table, &ent, P, &s_fb_n, blk * kLocalQueueSeg, vbits, vstatus); break;
+            default: path = finish_token<BF16, kExt, kLocalFb>(L, pos, job, next_idx, j, table, &ent, P, &s_fb_n, blk * kLocalQueueSeg, vbits, vstatus); break;
           }
           if (P.count_paths) {
             c_tok += 1;
@@ -1264,6 +1339,17 @@ k_parse(ParseParams P) {
         }
       } else if (tid == 0) {
         sm.prev_nd = (sm.nd[S::kChunks - 1] >> 15) & 1u;
+      }
+    }
+    if (kLocalFb && P.fb_local) {
+      // the block's queued tokens, one wave each (as in k_fallback)
+      __syncthreads();  // the block's queue entries and s_fb_n are written
+      const uint32_t nq = s_fb_n;
+      if (nq) {
+        decide_queue_segment(P.queue + blk * kLocalQueueSeg, nq, job.text, job.nbytes, job.values, job.status,
+                             job.dtype, P.flags, reinterpret_cast<FbLds*>(sm.text));
+        __syncthreads();  // s_fb_n is read and the tile's LDS is free again
+        if (tid == 0) s_fb_n = 0;
       }
     }
     if (kReduce && P.sum_out) {
@@ -1308,33 +1394,6 @@ k_parse(ParseParams P) {
 // k_fallback: one wavefront per queued token (fb_decide), wavefronts striding
 // over the queue.
 // ---------------------------------------------------------------------------
-constexpr int kFbThreads = 256;
-constexpr int kFbWaves = kFbThreads / kWave;
-
-template <class F>
-__device__ __forceinline__ void fallback_token(const JobDesc& job, uint64_t pos, uint64_t idx,
-                                               FbLds* lds, const FallbackParams& P) {
-  typename F::bits_t bits;
-  uint32_t status;
-  fb_decide<F>(job.text, job.nbytes, pos, g_table, g_pow5, lds, P.flags, bits, status);
-  if (fb_lane() == 0) {
-    gstore(reinterpret_cast<typename F::bits_t*>(job.values) + idx, bits);
-    gstore(job.status + idx, (uint8_t)status);
-    uint64_t key;
-    const bool in = (P.reduce_out || P.sum_out) && order_key(bits, status, job.dtype, key);
-    if (in && P.reduce_out) {
-      atomicMin(&P.st->red_min, (unsigned long long)key);
-      atomicMax(&P.st->red_max, (unsigned long long)key);
-      atomicAdd(&P.st->red_count, 1ull);
-    }
-    if (in && P.sum_out) {
-      const SumTerm x = sum_term(bits, job.dtype);
-      if (!x.inf && x.m) sum_add(&P.st->sum_acc[x.neg ? 1 : 0][0], x);
-      atomicOr(&P.st->sum_flags, sum_flag_bits(x));
-    }
-  }
-}
-
 // Compiled for six waves per SIMD (80 registers): a token's decision is a
 // chain of dependent cross-lane steps and memory reads, so more resident
 // wavefronts beat fewer, wider ones (config 3: 4.88 ms per call at four

@@ -1024,3 +1024,44 @@ def test_small_calls_alternate_device_states(ffpmod):
                 assert c.last_device_error() == 0, label
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("flags", [0, 0x06, 0x30 | 0x08])
+def test_small_calls_decide_queued_tokens_in_parse(ffpmod, flags):
+    """Plain calls of at most 32 blocks of 4 KiB decide their queued tokens in
+    the parse kernel (each workgroup those of its own block, from the block's
+    queue segment); larger calls keep the fallback kernel.  Texts of nothing
+    but queued tokens (every block's segment busy), of mixed tokens, and of
+    sizes around the 128 KiB limit, in every output type, with the plain,
+    the JSON / inf-nan and the directed-rounding lexers."""
+    rng = np.random.default_rng(310)
+    hard = W.join_tokens(W.hard_tokens(rng, 3000))
+    mixed = W.join_tokens(W.mixed_tokens(rng, 4000) + W.hard_tokens(rng, 300))
+    # the first 20 digits of binary64 midpoints (2w + 1) 2^(e-1): their
+    # truncations to 19 digits fall on either side of the midpoint, so every
+    # token is queued (about 178 in each 4 KiB block)
+    mids = []
+    for _ in range(7000):
+        w = int(rng.integers(2 ** 52, 2 ** 53))
+        x = str((2 * w + 1) << int(rng.integers(20, 70)))
+        mids.append("%se%d" % (x[:20], len(x) - 20))
+    dense = W.join_tokens(mids)
+    cases = []
+    for name, pool in (("hard", hard), ("mixed", mixed), ("dense", dense)):
+        for kib in (4, 60, 128, 132):
+            buf = pool[: kib * 1024 - 37]
+            cases.append((name, kib, buf[: buf.rfind(b"\n") + 1]))
+    c = ffpmod.Context(0, flags=flags)
+    try:
+        for name, kib, buf in cases:
+            for fmt in ("f64", "f32", "f16", "bf16"):
+                _log("case local fallback", hex(flags), name, kib, "KiB", fmt)
+                rc, n, bits, status = run_gpu(c, buf, fmt, offset=kib % 7)
+                wb, ws = parse_buffer(buf, fmt, flags=flags)
+                assert rc == len(wb) and n == len(wb), (name, kib, fmt, rc, len(wb))
+                bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
+                                     (status[:n] != np.array(ws, dtype=np.uint8)))
+                assert bad.size == 0, (name, kib, fmt, bad[:5])
+                assert c.last_device_error() == 0
+    finally:
+        c.close()
