@@ -225,11 +225,10 @@ struct FbDigits {
   bool sticky = false;
 };
 
+// pre: the digits of dm in lanes below this one (fb_excl_scan of the
+// per-lane counts), total: those of the whole window.
 __device__ __forceinline__ void fb_feed(FbDigits& s, uint32_t dm, const uint32_t (&wd)[4],
-                                        uint8_t* out, int limit) {
-  const uint32_t cnt = __popc(dm);
-  const uint32_t pre = fb_excl_scan(cnt);
-  const uint32_t total = fb_read32(pre + cnt, kWave - 1);
+                                        uint8_t* out, int limit, uint32_t pre, uint32_t total) {
   if (s.z < 0) {
     constexpr uint32_t kZero = '0' * 0x01010101u;
     const uint32_t zm = pack_high_bits(byte_eq_word(wd[0], kZero), byte_eq_word(wd[1], kZero),
@@ -243,19 +242,34 @@ __device__ __forceinline__ void fb_feed(FbDigits& s, uint32_t dm, const uint32_t
     }
   }
   if (s.z >= 0) {
-    int64_t g = s.n + pre;
-    bool stick = false;
+    // index of the lane's first digit among the significant digits, in 32
+    // bits: at least -kFbWindow (the leading zeros of this window), and
+    // clamped at `limit` above (which keeps every such digit out of range)
+    const int64_t g64 = s.n + (int64_t)pre - s.z;
+    const int32_t g0 = g64 > limit ? limit : (int32_t)g64;
+    uint32_t r = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       if ((dm >> k) & 1u) {
-        const int64_t si = g - s.z;
-        const uint32_t d = fb_byte(wd, k) - '0';
-        if (si >= 0 && si < limit) out[si] = (uint8_t)d;
-        stick |= si >= limit && d != 0;
-        ++g;
+        const uint32_t si = (uint32_t)(g0 + (int32_t)r);
+        if (si < (uint32_t)limit) out[si] = (uint8_t)(fb_byte(wd, k) - '0');
+        ++r;
       }
     }
-    s.sticky |= fb_ballot(stick) != 0;
+    // a nonzero digit past the kept ones (tokens of more than `limit`
+    // significant digits only)
+    if (fb_ballot(g0 + (int32_t)__popc(dm) > limit) != 0) {
+      bool stick = false;
+      uint32_t r2 = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if ((dm >> k) & 1u) {
+          stick |= g0 + (int32_t)r2 >= limit && fb_byte(wd, k) != '0';
+          ++r2;
+        }
+      }
+      s.sticky |= fb_ballot(stick) != 0;
+    }
   }
   s.n += total;
 }
@@ -335,13 +349,15 @@ __device__ FbToken fb_lex(const uint8_t* text, uint64_t nbytes, uint64_t pos, Fb
       const int ep = fb_first(em & fb_mask_lt(endp));
       const int mend = ep < endp ? ep : endp;
       const uint32_t mdm = dm & fb_mask_lt(mend);
+      const uint32_t cnt = __popc(mdm);
+      const uint32_t pre = fb_excl_scan(cnt);
       const int dp = fb_first(dot & fb_mask_lt(mend));
-      if (dp < kFbWindow) {
-        const uint32_t before = __popc(mdm & fb_mask_lt(dp));
-        const uint32_t pre = fb_excl_scan(before);
-        nint = mant.n + (int64_t)fb_read32(pre + before, kWave - 1);
-      }
-      fb_feed(mant, mdm, wd, lds->digits, kFallbackDigits);
+      // digits before the point: those of the lanes below its lane, and its
+      // lane's own below it
+      if (dp < kFbWindow)
+        nint = mant.n + (int64_t)fb_read32(pre + __popc(mdm & fb_mask_lt(dp)), dp >> 4);
+      fb_feed(mant, mdm, wd, lds->digits, kFallbackDigits, pre,
+              fb_read32(pre + cnt, kWave - 1));
       if (ep < endp) {
         state = 1;
         es = ep + 1;
@@ -357,7 +373,9 @@ __device__ FbToken fb_lex(const uint8_t* text, uint64_t nbytes, uint64_t pos, Fb
     }
     if (state == 2) {
       const uint32_t edm = dm & fb_mask_lt(endp) & ~fb_mask_lt(es);
-      fb_feed(expo, edm, wd, lds->edigits, kExpKeep);
+      const uint32_t cnt = __popc(edm);
+      const uint32_t pre = fb_excl_scan(cnt);
+      fb_feed(expo, edm, wd, lds->edigits, kExpKeep, pre, fb_read32(pre + cnt, kWave - 1));
     }
     if (endp < kFbWindow) break;
   }
