@@ -831,28 +831,36 @@ def run_copycal(args):
 
 
 def _counter_rows(csv_path, counter, match):
+    """Counter values of the matching kernels' dispatches, by kernel name."""
     import csv
-    vals = []
+    vals = {}
     with open(csv_path) as f:
         for row in csv.DictReader(f):
             if row["Counter_Name"] == counter and match(row["Kernel_Name"]):
-                vals.append(float(row["Counter_Value"]))
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
     if not vals:
         raise SystemExit("no %s rows for the kernel in %s" % (counter, csv_path))
     return vals
 
 
+def _per_launch(vals):
+    """Mean per dispatch of each kernel, summed over the kernels: a parse
+    launch of 16 KiB tiles dispatches two instances (the one not needed for
+    the call returns at once), and both count towards the launch."""
+    return sum(sum(v) / len(v) for v in vals.values())
+
+
 def reduce_traffic(workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, command):
     """profiles/traffic.json[workload] = HBM bytes per parse-kernel launch:
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over dispatches),
-    each scaled by bytes / counter of the calibration kernel."""
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over dispatches,
+    summed over the instances a launch dispatches), each scaled by bytes /
+    counter of the calibration kernel."""
     is_parse = lambda n: "k_parse" in n
     is_cal = lambda n: "bitwise_not" in n or "BitwiseNot" in n
-    mean = lambda v: sum(v) / len(v)
-    f_k = mean(_counter_rows(fetch_csv, "FETCH_SIZE", is_parse))
-    w_k = mean(_counter_rows(write_csv, "WRITE_SIZE", is_parse))
-    f_c = mean(_counter_rows(cal_fetch_csv, "FETCH_SIZE", is_cal))
-    w_c = mean(_counter_rows(cal_write_csv, "WRITE_SIZE", is_cal))
+    f_k = _per_launch(_counter_rows(fetch_csv, "FETCH_SIZE", is_parse))
+    w_k = _per_launch(_counter_rows(write_csv, "WRITE_SIZE", is_parse))
+    f_c = _per_launch(_counter_rows(cal_fetch_csv, "FETCH_SIZE", is_cal))
+    w_c = _per_launch(_counter_rows(cal_write_csv, "WRITE_SIZE", is_cal))
     ff = CAL_BYTES / (f_c * 1024.0)
     fw = CAL_BYTES / (w_c * 1024.0)
     ent = {
