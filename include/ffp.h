@@ -332,11 +332,10 @@ void ffp_batch_graph_destroy(ffp_graph* g);
  * every parse workgroup two blocks, so that small inputs spread over many
  * workgroups).  A call never uses tiles larger than its blocks.  Until a
  * schedule is set (ffp_set_tuning, ffp_autotune_batch or the FFP_TILE_K
- * environment variable) the tile is chosen per call: 8 KiB for contexts
- * without grammar or rounding flags and calls without a reduction, 16 KiB
- * otherwise, and 16 KiB for a plain call whose capacity allows at most one
- * token per 64 bytes of text (long tokens); ffp_get_tuning then reports
- * the first choice.  The schedule never changes results. */
+ * environment variable) the tile is chosen per call: 16 KiB, 8 KiB for
+ * FFP_JSON_DOCUMENT and FFP_CSV contexts (within the block size above);
+ * ffp_get_tuning then reports that choice.  The schedule never changes
+ * results. */
 typedef struct ffp_tuning {
     int32_t tile_k;
     int32_t blocks_per_cu;

@@ -1625,9 +1625,12 @@ static void launch_parse_mode(const ParseParams& P, int grid, hipStream_t s) {
   else {
     hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModePlain>), dim3(grid), dim3(kThreads), 0, s,
                        P);
-    if constexpr (K == 4 && !kReduce)  // the full-list twin for dense calls
-      hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModePlainDense>), dim3(grid),
-                         dim3(kThreads), 0, s, P);
+    // the full-list twin for dense calls: its LDS admits four workgroups
+    // per CU where the plain instance has five, so it gets four fifths of
+    // the grid (one dispatch wave; its block loop strides by the grid)
+    if constexpr (K == 4 && !kReduce)
+      hipLaunchKernelGGL((k_parse<K, kSingle, kReduce, kModePlainDense>),
+                         dim3(grid > 4 ? grid - grid / 5 : grid), dim3(kThreads), 0, s, P);
   }
 }
 
