@@ -501,9 +501,48 @@ def run_plain(args, buf, ntok, workload, desc, out_dtype="f64", cpu=True, delims
         rec["parity"] = {"vs": "oracle", "tokens_checked": int(len(wb)),
                          "tokens": ntok, "full": True,
                          "mismatches": count_mismatches(got_bits, got_st, wb, ws)}
+        if red is not None:  # the minimum, maximum and count of the oracle's values
+            want = expected_minmax(wb, ws, out_dtype)
+            rec["reduce"]["oracle"] = {"min_bits": hex(want[0]), "max_bits": hex(want[1]),
+                                       "count": want[2]}
+            rec["parity"]["reduce_matches"] = want == (mn, mx, cnt)
         rec["context"] = {"glibc_strtod": strtod_context(buf)} if out_dtype == "f64" and \
             delims == b"\n" and flags == 0 else {}
     return rec
+
+
+def expected_minmax(bits, status, out_dtype):
+    """(minimum bits, maximum bits, count) of the values with status OK, NaN
+    left out, -0 ordered before +0; the format's quiet NaN twice and 0 for
+    an empty set (the reduction's contract)."""
+    import numpy as np
+    qnan = {"f64": 0x7FF8000000000000, "f32": 0x7FC00000, "f16": 0x7E00, "bf16": 0x7FC0}
+    width = VALUE_BYTES[out_dtype] * 8
+    b = np.asarray(bits, dtype=np.uint64)[np.asarray(status, dtype=np.uint8) == 0]
+    if out_dtype == "f64":
+        v = b.view(np.float64)
+    elif out_dtype == "f32":
+        v = b.astype(np.uint32).view(np.float32).astype(np.float64)
+    elif out_dtype == "f16":
+        v = b.astype(np.uint16).view(np.float16).astype(np.float64)
+    else:
+        v = (b.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+    keep = ~np.isnan(v)
+    b, v = b[keep], v[keep]
+    if b.size == 0:
+        return qnan[out_dtype], qnan[out_dtype], 0
+    sign = np.uint64(1 << (width - 1))
+    neg_zero = (v == 0) & ((b & sign) != 0)
+    lo, hi = v.min(), v.max()
+    if lo == 0:
+        mn = int(sign) if neg_zero.any() else 0
+    else:
+        mn = int(b[np.argmin(v)])
+    if hi == 0:
+        mx = 0 if (~neg_zero & (v == 0)).any() else int(sign)
+    else:
+        mx = int(b[np.argmax(v)])
+    return mn, mx, int(b.size)
 
 
 # ---------------------------------------------------------------------------
