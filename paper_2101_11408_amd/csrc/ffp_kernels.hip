@@ -1033,6 +1033,11 @@ k_parse(ParseParams P) {
   // path counters, kept in scalars (a runtime-indexed array would live in
   // scratch memory)
   uint32_t c_tok = 0, c_inv = 0, c_early = 0, c_one = 0, c_two = 0, c_fb = 0;
+  // reduction instances: this lane's minimum and maximum order keys and
+  // count of the values it decided (wave reductions once, at the end, instead
+  // of three per round)
+  uint64_t r_min = kNoMin, r_max = kNoMax;
+  uint32_t r_cnt = 0;
 
   for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const JobDesc job = job_of_block(P.js, blk);
@@ -1311,13 +1316,10 @@ k_parse(ParseParams P) {
         if (kReduce) {
           uint64_t key = 0;
           const bool in = has_token && order_key(vbits, vstatus, job.dtype, key);
-          const uint64_t kmin = wave_min_u64(in ? key : kNoMin);
-          const uint64_t kmax = wave_max_u64(in ? key : kNoMax);
-          const uint64_t cnt = wave_sum_u64(in ? 1u : 0u);
-          if (lane == 0 && cnt) {
-            atomicMin(&sm.red_min, (unsigned long long)kmin);
-            atomicMax(&sm.red_max, (unsigned long long)kmax);
-            atomicAdd(&sm.red_count, (unsigned long long)cnt);
+          if (in) {  // this lane's running minimum, maximum and count
+            r_min = key < r_min ? key : r_min;
+            r_max = key > r_max ? key : r_max;
+            ++r_cnt;
           }
           if (P.sum_out) {  // the same values, into the exact sum
             const SumTerm x = sum_term(vbits, job.dtype);
@@ -1373,6 +1375,15 @@ k_parse(ParseParams P) {
   }
 
   if (kReduce) {
+    // the lanes' running values, reduced once per workgroup
+    const uint64_t kmin = wave_min_u64(r_min);
+    const uint64_t kmax = wave_max_u64(r_max);
+    const uint64_t cnt = wave_sum_u64(r_cnt);
+    if (lane == 0 && cnt) {
+      atomicMin(&sm.red_min, (unsigned long long)kmin);
+      atomicMax(&sm.red_max, (unsigned long long)kmax);
+      atomicAdd(&sm.red_count, (unsigned long long)cnt);
+    }
     __syncthreads();
     if (tid == 0 && sm.red_count) {
       atomicMin(&P.st->red_min, sm.red_min);
