@@ -220,9 +220,11 @@ int launch_jobs(ffp_ctx* ctx, const Scratch& sc, const ffp::JobSet& js, const Ca
   sp.st = st;
   sp.spare = spare;
   sp.json_doc = json_doc ? 1u : 0u;
-  // the 16 KiB plain parse keeps at most 4096 starts per tile; a block with
-  // no more than that cannot have a tile with more
-  sp.dense_limit = json_doc ? 0u : 4096u;
+  // the 16 KiB plain parse keeps at most kShortTileStarts starts per tile:
+  // 16 KiB blocks are tiles, so their counts decide; 64 KiB blocks carry a
+  // flag for a dense tile from the count kernel (4 KiB blocks never run
+  // 16 KiB tiles)
+  sp.dense_limit = json_doc || js.block_shift == ffp::kMaxBlockShift ? 0u : ffp::kShortTileStarts;
   if (nblocks > 0 && !self_count) {
     ffp::CountParams cp{};
     cp.js = js;

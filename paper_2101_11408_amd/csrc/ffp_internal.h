@@ -179,13 +179,21 @@ struct CountParams {
 // (bits 0-62) and whether the block begins inside a string (bit 63).
 constexpr uint64_t kPrefixMask = ~0ull >> 1;
 
+// The plain 16 KiB-tile parse keeps at most this many token starts per tile.
+// Other calls with 64 KiB blocks: the count word of a block carries
+// kDenseTileBit when one of its four 16 KiB tiles holds more (the scan
+// kernel then sets DeviceState::dense and masks the bit off).
+constexpr uint32_t kShortTileStarts = 4096;
+constexpr uint64_t kDenseTileBit = 1ull << 62;
+
 struct ScanParams {
   JobSet js;
   uint64_t* block_sum;  // in: counts; out: exclusive prefix over all blocks
   DeviceState* st;
   DeviceState* spare;   // the context's two spare states, reset here (or null)
   uint32_t json_doc;    // count words of JSON documents (see kPrefixMask)
-  uint32_t dense_limit; // DeviceState::dense: block counts above this (0: never)
+  uint32_t dense_limit; // DeviceState::dense: block counts above this (0: never),
+                        // or a count word with kDenseTileBit
 };
 
 struct ParseParams {

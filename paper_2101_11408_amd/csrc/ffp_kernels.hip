@@ -596,6 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
   __shared__ uint8_t s_lut[256];
   __shared__ uint32_t s_scan[kThreads / kWave];
   __shared__ uint32_t s_prev;
+  __shared__ uint64_t s_tiles[kThreads / kWave];  // 64 KiB blocks: per-wave tile starts
   const int tid = threadIdx.x;
   if (!kSingle)
     for (int i = tid; i < 256; i += kThreads) s_lut[i] = is_delim(P.delim, (uint32_t)i);
@@ -652,15 +653,34 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
     if (tid == 0) s_prev = prev_nondelim(vbase, bstart, align, P.delim);
     __syncthreads();
     uint32_t n = 0;
+    // 64 KiB blocks: the starts of each 16 KiB tile (rows 4t .. 4t+3), one
+    // 16-bit field per tile (at most 8192 starts each)
+    uint64_t tiles = 0;
 #pragma unroll
     for (int r = 0; r < kCountRows; ++r) {
       const int chunk = r * kThreads + tid;
       const uint32_t pb = chunk == 0 ? s_prev : ((uint32_t)s_nd[chunk - 1] >> 15);
-      n += __popc(m[r] & ~((m[r] << 1) | pb) & 0xFFFFu);
+      const uint32_t c = __popc(m[r] & ~((m[r] << 1) | pb) & 0xFFFFu);
+      n += c;
+      if (kCountRows == 16) tiles += (uint64_t)c << (16 * (r / 4));
     }
     uint32_t total;
     (void)block_excl_scan<kThreads>(n, total, s_scan);
-    if (tid == 0) P.block_sum[b] = total;
+    uint64_t word = total;
+    if (kCountRows == 16) {
+      tiles = wave_sum_u64(tiles);
+      if ((tid & (kWave - 1)) == 0) s_tiles[tid / kWave] = tiles;
+      __syncthreads();
+      if (tid == 0) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / kWave; ++w) t += s_tiles[w];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+          if (((t >> (16 * f)) & 0xFFFFu) > kShortTileStarts) word |= kDenseTileBit;
+      }
+    }
+    if (tid == 0) P.block_sum[b] = word;
   }
 }
 
@@ -688,7 +708,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
     }
   }
   reset_sum_state(P.st, tid, kScanThreads);
-  bool dense = false;  // a block above P.dense_limit starts (plain counts only)
+  // a block above P.dense_limit starts, or one with a dense 16 KiB tile
+  // (plain counts only)
+  bool dense = false;
   for (uint64_t base = 0; base < n; base += (uint64_t)kScanThreads * kScanPer) {
     uint64_t v[kScanPer];
     uint64_t sum = 0;
@@ -721,8 +743,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanParams P) {
       for (int i = 0; i < kScanPer; ++i) {
         const uint64_t k = base + (uint64_t)tid * kScanPer + i;
         v[i] = k < n ? P.block_sum[k] : 0;
+        dense = dense || (v[i] & kDenseTileBit) ||
+                (P.dense_limit && (v[i] & ~kDenseTileBit) > P.dense_limit);
+        v[i] &= ~kDenseTileBit;
         sum += v[i];
-        dense = dense || (P.dense_limit && v[i] > P.dense_limit);
       }
     }
     __syncthreads();  // s_carry of the previous round is final
@@ -986,6 +1010,7 @@ k_parse(ParseParams P) {
   // token bitmaps here until the starts are written.
   constexpr bool kShortStarts = K == 4 && kMode == kModePlain && !kReduce;
   constexpr int kStartsCap = kShortStarts ? S::kBytes / 4 : S::kBytes / 2;
+  static_assert(!kShortStarts || kStartsCap == (int)kShortTileStarts, "short start list");
   __shared__ uint16_t s_starts[kStartsCap];
   if (kShortStarts && P.st->dense) return;
   if (kMode == kModePlainDense && !P.st->dense) return;

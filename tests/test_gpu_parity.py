@@ -251,10 +251,13 @@ def test_many_tiny_tokens(ctx):
 @pytest.mark.parametrize("block_kib", [16, 64])
 def test_dense_tiles_at_16k(ffpmod, block_kib):
     """16 KiB tiles: the plain instance keeps at most 4096 starts per tile and
-    runs when no block of the call has more; otherwise its full-list twin
-    runs.  Dense text (one-digit tokens: 8192 per tile), sparse text, and a
-    text dense in one block only, in plain calls and in one batched call
-    mixing them; every output against the oracle."""
+    runs when no tile of the call has more (16 KiB blocks: their counts; 64
+    KiB blocks: a per-tile flag of the count kernel); otherwise its
+    full-list twin runs.  Dense text (one-digit tokens: 8192 per tile),
+    sparse text, a text dense in one block only, tiles with exactly 4097 and
+    4096 starts at each tile position of a block, short tokens (dense per
+    block, not per tile), in plain calls and in one batched call mixing
+    them; every output against the oracle."""
     rng = np.random.default_rng(170 + block_kib)
     dense = b"7\n" * 150_000 + b"8"
     sparse = W.join_tokens(W.mixed_tokens(rng, 20_000))
@@ -271,6 +274,36 @@ def test_dense_tiles_at_16k(ffpmod, block_kib):
                 bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT[fmt])) |
                                      (status[:n] != np.array(ws, dtype=np.uint8)))
                 assert bad.size == 0, (label, fmt, bad[:5])
+        # tiles at the limit: a text placed 9 bytes past a 16-byte boundary
+        # has its 16 KiB tiles at text offsets 16384 t - 9; one tile with
+        # exactly 4097 (dense) or 4096 (not) starts at each of a 64 KiB
+        # block's four tile positions, the rest sparse
+        filler = W.join_tokens(W.mixed_tokens(rng, 8000))
+        for t in (1, 2, 3, 4):
+            at = 16384 * t - 9
+            head = filler[:at]
+            head = head[: head.rfind(b"\n") + 1]
+            head += b"\n" * (at - len(head))
+            for k, rest in ((4097, b""), (4096, b"\n" * (16384 - 8192))):
+                buf = head + b"1\n" * k + rest + filler[at:at + 40000]
+                buf = buf[: buf.rfind(b"\n") + 1]
+                _log("case dense tile limit", block_kib, t, k)
+                rc, n, bits, status = run_gpu(c, buf, "f64", offset=9)
+                wb, ws = parse_buffer(buf, "f64")
+                assert rc == n == len(wb), (t, k, rc, n, len(wb))
+                bad = np.flatnonzero((bits[:n] != np.array(wb, dtype=NP_DT["f64"])) |
+                                     (status[:n] != np.array(ws, dtype=np.uint8)))
+                assert bad.size == 0, (t, k, bad[:5])
+        # short tokens: more than 4096 starts per 64 KiB block, at most 4096
+        # per 16 KiB tile (the per-tile flag keeps the short start list)
+        short = W.join_tokens(["%d.%d" % (int(a), int(b)) for a, b in
+                               zip(rng.integers(0, 10, 60000), rng.integers(0, 100, 60000))])
+        _log("case dense tiles short tokens", block_kib)
+        rc, n, bits, status = run_gpu(c, short, "f64", offset=9)
+        wb, ws = parse_buffer(short, "f64")
+        assert rc == n == len(wb)
+        assert np.array_equal(bits[:n], np.array(wb, dtype=NP_DT["f64"]))
+        assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8))
         # one batched call: the flag covers the whole call
         dev = torch.device("cuda", 0)
         texts = [torch.frombuffer(bytearray(b), dtype=torch.uint8).to(dev)
