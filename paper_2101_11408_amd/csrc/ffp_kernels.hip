@@ -664,10 +664,8 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
       n += c;
       if (kCountRows == 16) tiles += (uint64_t)c << (16 * (r / 4));
     }
-    uint32_t total;
-    (void)block_excl_scan<kThreads>(n, total, s_scan);
-    uint64_t word = total;
     if (kCountRows == 16) {
+      // the block's total is the sum of its tiles' fields
       tiles = wave_sum_u64(tiles);
       if ((tid & (kWave - 1)) == 0) s_tiles[tid / kWave] = tiles;
       __syncthreads();
@@ -675,12 +673,20 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
         uint64_t t = 0;
 #pragma unroll
         for (int w = 0; w < kThreads / kWave; ++w) t += s_tiles[w];
+        uint64_t word = 0;
 #pragma unroll
-        for (int f = 0; f < 4; ++f)
-          if (((t >> (16 * f)) & 0xFFFFu) > kShortTileStarts) word |= kDenseTileBit;
+        for (int f = 0; f < 4; ++f) {
+          const uint64_t c = (t >> (16 * f)) & 0xFFFFu;
+          word += c;
+          if (c > kShortTileStarts) word |= kDenseTileBit;
+        }
+        P.block_sum[b] = word;
       }
+    } else {
+      uint32_t total;
+      (void)block_excl_scan<kThreads>(n, total, s_scan);
+      if (tid == 0) P.block_sum[b] = total;
     }
-    if (tid == 0) P.block_sum[b] = word;
   }
 }
 
