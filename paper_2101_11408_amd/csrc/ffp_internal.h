@@ -180,9 +180,9 @@ struct CountParams {
 constexpr uint64_t kPrefixMask = ~0ull >> 1;
 
 // The plain 16 KiB-tile parse keeps at most this many token starts per tile.
-// Other calls with 64 KiB blocks: the count word of a block carries
-// kDenseTileBit when one of its four 16 KiB tiles holds more (the scan
-// kernel then sets DeviceState::dense and masks the bit off).
+// Calls with 64 KiB blocks that run the scan kernel: the count word of a
+// block carries kDenseTileBit when one of its four 16 KiB tiles holds more
+// (the scan kernel then sets DeviceState::dense and masks the bit off).
 constexpr uint32_t kShortTileStarts = 4096;
 constexpr uint64_t kDenseTileBit = 1ull << 62;
 

@@ -674,12 +674,16 @@ __global__ __launch_bounds__(kThreads) void k_count(CountParams P) {
 #pragma unroll
         for (int w = 0; w < kThreads / kWave; ++w) t += s_tiles[w];
         uint64_t word = 0;
+        bool dense = false;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const uint64_t c = (t >> (16 * f)) & 0xFFFFu;
           word += c;
-          if (c > kShortTileStarts) word |= kDenseTileBit;
+          dense = dense || c > kShortTileStarts;
         }
+        // the flag only where the scan kernel runs and masks it off (calls
+        // without it, P.reset_state, read these counts as they are)
+        if (dense && !P.reset_state) word |= kDenseTileBit;
         P.block_sum[b] = word;
       }
     } else {

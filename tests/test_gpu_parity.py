@@ -248,6 +248,44 @@ def test_many_tiny_tokens(ctx):
     compare_full(ctx, buf, "f64", "dense")
 
 
+@pytest.mark.parametrize("tile_k,block_kib", [(1, 64), (2, 64), (1, 16), (2, 16)])
+def test_dense_blocks_with_small_tiles(ffpmod, tile_k, block_kib):
+    """Dense text (one-digit tokens, 8192 starts per 16 KiB) with a fixed
+    schedule of 4 or 8 KiB tiles in 16 and 64 KiB blocks: calls of at most
+    1024 blocks run without the scan kernel and read the count kernel's
+    block counts as they are (no dense-tile flag in them), larger ones
+    through the scan; plain and batched calls against the oracle."""
+    rng = np.random.default_rng(180 + tile_k + block_kib)
+    dense = b"7\n" * 150_000 + b"8"
+    sparse = W.join_tokens(W.mixed_tokens(rng, 20_000))
+    mixed = sparse[:300_000] + b"\n" + b"1\n" * 40_000 + sparse[300_000:]
+    c = ffpmod.Context(0)
+    try:
+        c.set_tuning(tile_k, 0, block_kib)
+        for label, buf in (("dense", dense), ("mixed", mixed)):
+            _log("case dense blocks small tiles", tile_k, block_kib, label)
+            rc, n, bits, status = run_gpu(c, buf, "f64", offset=5)
+            wb, ws = parse_buffer(buf, "f64")
+            assert rc == n == len(wb), (label, rc, n, len(wb))
+            assert np.array_equal(bits[:n], np.array(wb, dtype=NP_DT["f64"])), label
+            assert np.array_equal(status[:n], np.array(ws, dtype=np.uint8)), label
+        dev = torch.device("cuda", 0)
+        texts = [torch.frombuffer(bytearray(b), dtype=torch.uint8).to(dev)
+                 for b in (dense, mixed, sparse[:5000])]
+        want = [parse_buffer(b, "f64") for b in (dense, mixed, sparse[:5000])]
+        vals = [torch.empty(len(w[0]) + 1, dtype=torch.float64, device=dev) for w in want]
+        sts = [torch.empty(len(w[0]) + 1, dtype=torch.uint8, device=dev) for w in want]
+        table = ffpmod.JobTable(texts, vals, sts, dev)
+        c.parse_batch(table.dev, table.n, sum(t.numel() for t in texts))
+        res = table.download()
+        for i, (wb, ws) in enumerate(want):
+            assert res[i] == (len(wb), 0), (i, res[i])
+            got = vals[i].view(torch.int64).cpu().numpy().view(np.uint64)[:len(wb)]
+            assert np.array_equal(got, np.array(wb, dtype=np.uint64)), i
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("block_kib", [16, 64])
 def test_dense_tiles_at_16k(ffpmod, block_kib):
     """16 KiB tiles: the plain instance keeps at most 4096 starts per tile and
